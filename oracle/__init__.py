@@ -1,0 +1,208 @@
+"""FP64 CPU oracle for early-abandoning pruned DTW -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline leg
+may import this package.  The product path (``paper_2010_05371_amd``) never
+does, and shares no code with it.
+
+Thin ctypes wrapper over ``oracle.c`` (plain C, built with gcc).  Every
+function is the plain definition from the paper (Herrmann & Webb, arXiv
+2010.05371):
+
+* ``dtw``         -- Section 2, Eq. 1-5 with the Sakoe-Chiba window of
+  Section 2.1, full (lS+1)x(lT+1) matrix in double precision;
+* ``eap``         -- Section 2.2's threshold contract: DTW if <= ub else +inf;
+* ``znorm``       -- z-normalisation (population sigma), the UCR-Suite step the
+  paper's search inherits (Section 5);
+* ``nn_search``   -- brute-force nearest neighbour over every offset,
+  lexicographic minimum of (distance, offset);
+* ``dtw_grad``    -- optimal warping path (Section 2) and the gradient of the
+  path cost with respect to both series;
+* ``eap_model``   -- a model of Algorithm 3 (Section 4), kept only to check the
+  threshold contract and the worked example (never a reference value).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int64_p = ctypes.POINTER(ctypes.c_int64)
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain C, -O2, pthreads)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-pthread",
+             "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    i64, dp, ip = ctypes.c_int64, _c_double_p, _c_int64_p
+    lib.oracle_znorm.argtypes = [dp, i64, dp]
+    lib.oracle_znorm.restype = None
+    lib.oracle_window_stats.argtypes = [dp, i64, i64, dp, dp]
+    lib.oracle_window_stats.restype = None
+    lib.oracle_dtw.argtypes = [dp, i64, dp, i64, i64]
+    lib.oracle_dtw.restype = ctypes.c_double
+    lib.oracle_dtw_matrix.argtypes = [dp, i64, dp, i64, i64, dp]
+    lib.oracle_dtw_matrix.restype = ctypes.c_int
+    lib.oracle_eap.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double]
+    lib.oracle_eap.restype = ctypes.c_double
+    lib.oracle_dtw_grad.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double, dp, dp, ip, ip, dp, dp]
+    lib.oracle_dtw_grad.restype = i64
+    lib.oracle_nn_dists.argtypes = [dp, i64, dp, i64, i64, ip, i64, ctypes.c_int, dp]
+    lib.oracle_nn_dists.restype = ctypes.c_int
+    lib.oracle_nn_search.argtypes = [dp, i64, dp, i64, i64, i64, i64, ctypes.c_int, ip, dp]
+    lib.oracle_nn_search.restype = ctypes.c_int
+    lib.oracle_dtw_pairs.argtypes = [dp, dp, i64, i64, ip, ip, i64, ctypes.c_int, dp]
+    lib.oracle_dtw_pairs.restype = ctypes.c_int
+    lib.oracle_eap_model.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double, ip, ip, ip, ip]
+    lib.oracle_eap_model.restype = ctypes.c_double
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    if a.dtype == np.float64:
+        return a.ctypes.data_as(_c_double_p)
+    return a.ctypes.data_as(_c_int64_p)
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def znorm(x) -> np.ndarray:
+    x = _f64(x)
+    z = np.empty_like(x)
+    _load().oracle_znorm(_ptr(x), x.size, _ptr(z))
+    return z
+
+
+def window_stats(x, m: int):
+    x = _f64(x)
+    k = x.size - m + 1
+    mu = np.empty(max(k, 0))
+    sd = np.empty(max(k, 0))
+    if k > 0:
+        _load().oracle_window_stats(_ptr(x), x.size, m, _ptr(mu), _ptr(sd))
+    return mu, sd
+
+
+def dtw(S, T, window: int | None = None) -> float:
+    S, T = _f64(S), _f64(T)
+    r = max(S.size, T.size) if window is None else int(window)
+    return float(_load().oracle_dtw(_ptr(S), S.size, _ptr(T), T.size, r))
+
+
+def dtw_matrix(S, T, window: int | None = None) -> np.ndarray:
+    S, T = _f64(S), _f64(T)
+    r = max(S.size, T.size) if window is None else int(window)
+    out = np.empty((S.size + 1, T.size + 1))
+    rc = _load().oracle_dtw_matrix(_ptr(S), S.size, _ptr(T), T.size, r, _ptr(out))
+    if rc != 0:
+        raise MemoryError("oracle_dtw_matrix")
+    return out
+
+
+def eap(S, T, window: int | None, ub: float) -> float:
+    S, T = _f64(S), _f64(T)
+    r = max(S.size, T.size) if window is None else int(window)
+    return float(_load().oracle_eap(_ptr(S), S.size, _ptr(T), T.size, r, float(ub)))
+
+
+def dtw_grad(S, T, window: int | None, gout: float = 1.0):
+    """Returns (dist, dS, dT, path[(i,j) 1-based, from (lS,lT) back to (1,1)], min_gap)."""
+    S, T = _f64(S), _f64(T)
+    r = max(S.size, T.size) if window is None else int(window)
+    dS = np.empty(S.size)
+    dT = np.empty(T.size)
+    pi = np.empty(S.size + T.size, dtype=np.int64)
+    pj = np.empty(S.size + T.size, dtype=np.int64)
+    dist = np.empty(1)
+    gap = np.empty(1)
+    n = _load().oracle_dtw_grad(_ptr(S), S.size, _ptr(T), T.size, r, float(gout), _ptr(dS),
+                                _ptr(dT), _ptr(pi), _ptr(pj), _ptr(dist), _ptr(gap))
+    if n < 0:
+        raise MemoryError("oracle_dtw_grad")
+    path = list(zip(pi[:n].tolist(), pj[:n].tolist()))
+    return float(dist[0]), dS, dT, path, float(gap[0])
+
+
+def nn_dists(query, series, window: int, offsets, nthreads: int | None = None) -> np.ndarray:
+    q, x = _f64(query), _f64(series)
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    out = np.empty(offs.size)
+    rc = _load().oracle_nn_dists(_ptr(q), q.size, _ptr(x), x.size, int(window), _ptr(offs),
+                                 offs.size, nthreads or default_threads(), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_nn_dists failed ({rc})")
+    return out
+
+
+def nn_search(query, series, window: int, k_begin: int = 0, k_end: int | None = None,
+              nthreads: int | None = None):
+    """(best offset, best distance) over offsets [k_begin, k_end)."""
+    q, x = _f64(query), _f64(series)
+    if k_end is None:
+        k_end = x.size - q.size + 1
+    bk = np.empty(1, dtype=np.int64)
+    bd = np.empty(1)
+    rc = _load().oracle_nn_search(_ptr(q), q.size, _ptr(x), x.size, int(window), int(k_begin),
+                                  int(k_end), nthreads or default_threads(), _ptr(bk), _ptr(bd))
+    if rc != 0:
+        raise ValueError(f"oracle_nn_search failed ({rc})")
+    return int(bk[0]), float(bd[0])
+
+
+def dtw_pairs(X, Y, window: int, ia, ib, nthreads: int | None = None) -> np.ndarray:
+    X, Y = _f64(X), _f64(Y)
+    L = X.shape[1]
+    ia = np.ascontiguousarray(np.asarray(ia, dtype=np.int64))
+    ib = np.ascontiguousarray(np.asarray(ib, dtype=np.int64))
+    out = np.empty(ia.size)
+    rc = _load().oracle_dtw_pairs(_ptr(X), _ptr(Y), L, int(window), _ptr(ia), _ptr(ib), ia.size,
+                                  nthreads or default_threads(), _ptr(out))
+    if rc != 0:
+        raise MemoryError("oracle_dtw_pairs")
+    return out
+
+
+def eap_model(S, T, window: int | None, ub: float):
+    """Model of Algorithm 3: (value, evaluated cells, per-line pruning point, abandon cell)."""
+    S, T = _f64(S), _f64(T)
+    r = max(S.size, T.size) if window is None else int(window)
+    cells = np.zeros(1, dtype=np.int64)
+    nl = max(S.size, T.size)
+    trace = np.zeros(max(nl, 1), dtype=np.int64)
+    ai = np.zeros(1, dtype=np.int64)
+    aj = np.zeros(1, dtype=np.int64)
+    v = _load().oracle_eap_model(_ptr(S), S.size, _ptr(T), T.size, r, float(ub), _ptr(cells),
+                                 _ptr(trace), _ptr(ai), _ptr(aj))
+    return float(v), int(cells[0]), trace[:nl].tolist(), (int(ai[0]), int(aj[0]))

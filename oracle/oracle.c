@@ -1,0 +1,459 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for early-abandoning pruned DTW.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path (the HIP library and
+ * its Python binding) may include, link or call this file.  Only the test
+ * suite, the smoke check and the benchmark's cpu_baseline leg use it.
+ *
+ * Every function here is the plain definition written out, in double
+ * precision, with no blocking, no fusion and no pruning, except
+ * oracle_eap_model(), which is a model of the paper's EAPrunedDTW line sweep
+ * (Section 4, Algorithm 3) kept only to check the threshold contract and the
+ * worked example's printed pruning facts; it is never used as a reference
+ * value for the GPU.
+ *
+ * Paper: Herrmann & Webb, "Early Abandoning PrunedDTW and its application to
+ * similarity search" (arXiv 2010.05371).
+ *
+ * Conventions (readings of the paper):
+ *  - rows i = 1..lS index S, columns j = 1..lT index T (1-based, as in Eq. 1-5);
+ *  - cost(a, b) = (a - b)^2 (Section 2, "usually the squared Euclidean distance");
+ *  - Sakoe-Chiba window r: a cell is admissible iff |i - j| <= r (Section 2.1);
+ *  - z-normalisation uses the population standard deviation; a window whose
+ *    standard deviation is zero normalises to all zeros.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_INF (INFINITY)
+
+/* ------------------------------------------------------------------------- */
+/* z-normalisation (two-pass, population sigma).                             */
+/* The paper inherits this step from the UCR Suite it embeds its DTW in      */
+/* (Section 5, experimental setup); it is not spelled out there.             */
+/* ------------------------------------------------------------------------- */
+void oracle_znorm(const double *x, int64_t m, double *z) {
+  double mean = 0.0;
+  for (int64_t t = 0; t < m; ++t) mean += x[t];
+  mean /= (double)m;
+  double var = 0.0;
+  for (int64_t t = 0; t < m; ++t) {
+    double dv = x[t] - mean;
+    var += dv * dv;
+  }
+  var /= (double)m;
+  double sd = sqrt(var);
+  for (int64_t t = 0; t < m; ++t) z[t] = (sd > 0.0) ? (x[t] - mean) / sd : 0.0;
+}
+
+/* mean and population sigma of one window (two-pass), for the stats tests. */
+void oracle_window_stats(const double *x, int64_t n, int64_t m, double *mu, double *sigma) {
+  for (int64_t k = 0; k + m <= n; ++k) {
+    double mean = 0.0;
+    for (int64_t t = 0; t < m; ++t) mean += x[k + t];
+    mean /= (double)m;
+    double var = 0.0;
+    for (int64_t t = 0; t < m; ++t) {
+      double dv = x[k + t] - mean;
+      var += dv * dv;
+    }
+    mu[k] = mean;
+    sigma[k] = sqrt(var / (double)m);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Full-matrix banded DTW (Section 2, Eq. 1-5, window of Section 2.1).       */
+/* M has (lS+1) x (lT+1) cells; M(0,0)=0, M(i,0)=M(0,j)=+inf, cells outside   */
+/* the window are +inf and never computed.                                    */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double *M;       /* (lS+1)*(lT+1) */
+  int64_t cap;     /* cells allocated */
+} dtw_ws;
+
+static int ws_reserve(dtw_ws *w, int64_t cells) {
+  if (w->cap >= cells) return 0;
+  free(w->M);
+  w->M = (double *)malloc((size_t)cells * sizeof(double));
+  w->cap = w->M ? cells : 0;
+  return w->M ? 0 : -1;
+}
+
+static inline double min3d(double a, double b, double c) {
+  double m = a < b ? a : b;
+  return m < c ? m : c;
+}
+
+/* Fills the whole matrix; returns M(lS, lT). */
+static double dtw_matrix(dtw_ws *w, const double *S, int64_t lS, const double *T, int64_t lT,
+                         int64_t r) {
+  const int64_t W = lT + 1;
+  if (ws_reserve(w, (lS + 1) * W) != 0) return NAN;
+  double *M = w->M;
+  for (int64_t c = 0; c < (lS + 1) * W; ++c) M[c] = ORACLE_INF;
+  M[0] = 0.0;
+  for (int64_t i = 1; i <= lS; ++i) {
+    int64_t jlo = i - r, jhi = i + r;
+    if (jlo < 1) jlo = 1;
+    if (jhi > lT) jhi = lT;
+    for (int64_t j = jlo; j <= jhi; ++j) {
+      double d = S[i - 1] - T[j - 1];
+      double cost = d * d;
+      M[i * W + j] = cost + min3d(M[(i - 1) * W + j], M[i * W + j - 1], M[(i - 1) * W + j - 1]);
+    }
+  }
+  return M[lS * W + lT];
+}
+
+double oracle_dtw(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r) {
+  if (lS == 0 && lT == 0) return 0.0;          /* Eq. 2 */
+  if (lS == 0 || lT == 0) return ORACLE_INF;   /* Eq. 3-4 */
+  dtw_ws w = {0, 0};
+  double v = dtw_matrix(&w, S, lS, T, lT, r);
+  free(w.M);
+  return v;
+}
+
+/* Writes the whole (lS+1)x(lT+1) DTW matrix (for tests of single cells). */
+int oracle_dtw_matrix(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r,
+                      double *out) {
+  dtw_ws w = {0, 0};
+  double v = dtw_matrix(&w, S, lS, T, lT, r);
+  if (isnan(v) && !w.M) return -1;
+  memcpy(out, w.M, (size_t)((lS + 1) * (lT + 1)) * sizeof(double));
+  free(w.M);
+  return 0;
+}
+
+/* Threshold contract (Section 2.2): the early-abandoned value is the DTW when
+ * it does not exceed ub and +inf when it strictly exceeds it.  Ties are kept. */
+double oracle_eap(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r, double ub) {
+  double v = oracle_dtw(S, lS, T, lT, r);
+  return (v <= ub) ? v : ORACLE_INF;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Optimal warping path and its gradient (Section 2: warping path, several   */
+/* optimal paths possible).  Backtrack from (lS,lT) to (1,1); among the       */
+/* admissible predecessors take the smallest value, ties broken               */
+/* diagonal > top (i-1,j) > left (i,j-1).                                    */
+/* d DTW / d S(i) = sum over path cells (i,j) of 2(S(i)-T(j)) * gout,         */
+/* d DTW / d T(j) = -sum over path cells (i,j) of 2(S(i)-T(j)) * gout.        */
+/* min_gap receives the smallest relative gap between the chosen predecessor  */
+/* and the best other finite predecessor along the path (a tie detector).     */
+/* Returns the path length (number of cells) or -1; +inf distance => zero     */
+/* gradients and length 0.                                                    */
+/* ------------------------------------------------------------------------- */
+int64_t oracle_dtw_grad(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r,
+                        double gout, double *dS, double *dT, int64_t *path_i, int64_t *path_j,
+                        double *dist, double *min_gap) {
+  for (int64_t i = 0; i < lS; ++i) dS[i] = 0.0;
+  for (int64_t j = 0; j < lT; ++j) dT[j] = 0.0;
+  if (min_gap) *min_gap = ORACLE_INF;
+  if (lS == 0 || lT == 0) {
+    if (dist) *dist = (lS == 0 && lT == 0) ? 0.0 : ORACLE_INF;
+    return 0;
+  }
+  dtw_ws w = {0, 0};
+  double v = dtw_matrix(&w, S, lS, T, lT, r);
+  if (!w.M) return -1;
+  if (dist) *dist = v;
+  if (!(v < ORACLE_INF)) {
+    free(w.M);
+    return 0;
+  }
+  const int64_t W = lT + 1;
+  const double *M = w.M;
+  int64_t i = lS, j = lT, len = 0;
+  for (;;) {
+    double d = S[i - 1] - T[j - 1];
+    double g = 2.0 * d * gout;
+    dS[i - 1] += g;
+    dT[j - 1] -= g;
+    if (path_i) path_i[len] = i;
+    if (path_j) path_j[len] = j;
+    ++len;
+    if (i == 1 && j == 1) break;
+    double vd = M[(i - 1) * W + (j - 1)];
+    double vt = M[(i - 1) * W + j];
+    double vl = M[i * W + (j - 1)];
+    double best = min3d(vd, vt, vl);
+    int step; /* 0 diag, 1 top, 2 left */
+    if (vd == best) step = 0;
+    else if (vt == best) step = 1;
+    else step = 2;
+    if (min_gap) {
+      double other = ORACLE_INF;
+      if (step != 0 && vd < other) other = vd;
+      if (step != 1 && vt < other) other = vt;
+      if (step != 2 && vl < other) other = vl;
+      if (other < ORACLE_INF) {
+        double scale = fabs(best) > 1e-300 ? fabs(best) : 1.0;
+        double gap = (other - best) / scale;
+        if (gap < *min_gap) *min_gap = gap;
+      }
+    }
+    if (step == 0) { --i; --j; }
+    else if (step == 1) { --i; }
+    else { --j; }
+  }
+  free(w.M);
+  return len;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Multi-threaded drivers.  Threads get contiguous static slices; each slice */
+/* is reduced in order, then slices are reduced in order, so the result does  */
+/* not depend on the thread count.                                            */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const double *q;
+  int64_t m;
+  const double *x;
+  int64_t r;
+  const int64_t *offsets; /* candidate offsets to evaluate */
+  int64_t lo, hi;         /* slice [lo,hi) of offsets[] */
+  double *out;            /* per-offset distances (indexed like offsets[]) */
+  int err;
+} nn_job;
+
+static void *nn_worker(void *arg) {
+  nn_job *jb = (nn_job *)arg;
+  double *zq = (double *)malloc((size_t)jb->m * sizeof(double));
+  double *zc = (double *)malloc((size_t)jb->m * sizeof(double));
+  dtw_ws w = {0, 0};
+  if (!zq || !zc) { jb->err = -1; goto done; }
+  oracle_znorm(jb->q, jb->m, zq);
+  for (int64_t t = jb->lo; t < jb->hi; ++t) {
+    int64_t k = jb->offsets[t];
+    oracle_znorm(jb->x + k, jb->m, zc);
+    double v = dtw_matrix(&w, zq, jb->m, zc, jb->m, jb->r);
+    if (!w.M) { jb->err = -1; goto done; }
+    jb->out[t] = v;
+  }
+done:
+  free(zq);
+  free(zc);
+  free(w.M);
+  return NULL;
+}
+
+/* Distances d_k = DTW(z(query), z(x[k..k+m)), window r) for the listed
+ * offsets (Section 2.2's candidates T_1..T_m, Section 5's subsequence search).
+ * Returns 0 on success. */
+int oracle_nn_dists(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                    const int64_t *offsets, int64_t noff, int nthreads, double *out) {
+  for (int64_t t = 0; t < noff; ++t)
+    if (offsets[t] < 0 || offsets[t] + m > n) return -2;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  pthread_t th[256];
+  int live[256];
+  nn_job jobs[256];
+  int64_t per = (noff + nthreads - 1) / nthreads;
+  for (int t = 0; t < nthreads; ++t) {
+    int64_t lo = (int64_t)t * per, hi = lo + per;
+    if (lo > noff) lo = noff;
+    if (hi > noff) hi = noff;
+    jobs[t] = (nn_job){q, m, x, r, offsets, lo, hi, out, 0};
+    live[t] = pthread_create(&th[t], NULL, nn_worker, &jobs[t]) == 0;
+    if (!live[t]) nn_worker(&jobs[t]);
+  }
+  int err = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    if (live[t]) pthread_join(th[t], NULL);
+    if (jobs[t].err) err = jobs[t].err;
+  }
+  return err;
+}
+
+/* Brute-force nearest neighbour over every offset k in [k_begin, k_end):
+ * the lexicographic minimum of (d_k, k), i.e. the smallest offset among equal
+ * minimal distances (a sequential scan that only replaces its best on a
+ * strictly better candidate, Section 2.2). */
+int oracle_nn_search(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                     int64_t k_begin, int64_t k_end, int nthreads, int64_t *best_k,
+                     double *best_d) {
+  if (m <= 0 || n < m || k_begin < 0 || k_end > n - m + 1 || k_begin >= k_end) return -2;
+  int64_t noff = k_end - k_begin;
+  int64_t *offs = (int64_t *)malloc((size_t)noff * sizeof(int64_t));
+  double *d = (double *)malloc((size_t)noff * sizeof(double));
+  if (!offs || !d) { free(offs); free(d); return -1; }
+  for (int64_t t = 0; t < noff; ++t) offs[t] = k_begin + t;
+  int rc = oracle_nn_dists(q, m, x, n, r, offs, noff, nthreads, d);
+  if (rc == 0) {
+    int64_t bk = -1;
+    double bd = ORACLE_INF;
+    for (int64_t t = 0; t < noff; ++t) {
+      if (bk < 0 || d[t] < bd) { bd = d[t]; bk = offs[t]; }
+    }
+    *best_k = bk;
+    *best_d = bd;
+  }
+  free(offs);
+  free(d);
+  return rc;
+}
+
+typedef struct {
+  const double *X, *Y;   /* rows of length L */
+  int64_t L, r;
+  const int64_t *ia, *ib; /* pair p = (X[ia[p]], Y[ib[p]]) */
+  int64_t lo, hi;
+  double *out;
+  int err;
+} pair_job;
+
+static void *pair_worker(void *arg) {
+  pair_job *jb = (pair_job *)arg;
+  dtw_ws w = {0, 0};
+  for (int64_t p = jb->lo; p < jb->hi; ++p) {
+    const double *a = jb->X + jb->ia[p] * jb->L;
+    const double *b = jb->Y + jb->ib[p] * jb->L;
+    double v = dtw_matrix(&w, a, jb->L, b, jb->L, jb->r);
+    if (!w.M) { jb->err = -1; break; }
+    jb->out[p] = v;
+  }
+  free(w.M);
+  return NULL;
+}
+
+/* DTW of listed pairs (X[ia[p]], Y[ib[p]]), all of length L, window r. */
+int oracle_dtw_pairs(const double *X, const double *Y, int64_t L, int64_t r, const int64_t *ia,
+                     const int64_t *ib, int64_t npairs, int nthreads, double *out) {
+  if (L <= 0) {
+    for (int64_t p = 0; p < npairs; ++p) out[p] = 0.0;
+    return 0;
+  }
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  pthread_t th[256];
+  int live[256];
+  pair_job jobs[256];
+  int64_t per = (npairs + nthreads - 1) / nthreads;
+  for (int t = 0; t < nthreads; ++t) {
+    int64_t lo = (int64_t)t * per, hi = lo + per;
+    if (lo > npairs) lo = npairs;
+    if (hi > npairs) hi = npairs;
+    jobs[t] = (pair_job){X, Y, L, r, ia, ib, lo, hi, out, 0};
+    live[t] = pthread_create(&th[t], NULL, pair_worker, &jobs[t]) == 0;
+    if (!live[t]) pair_worker(&jobs[t]);
+  }
+  int err = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    if (live[t]) pthread_join(th[t], NULL);
+    if (jobs[t].err) err = jobs[t].err;
+  }
+  return err;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Model of the paper's EAPrunedDTW line sweep (Section 4, Algorithm 3),      */
+/* with a Sakoe-Chiba window (the paper states its algorithms without one,   */
+/* Section 2.1; the windowed reading is documented in the design doc) and with the */
+/* cost recomputed for every column of the last stage.  Kept only to check   */
+/* the threshold contract and the worked example; never a reference value.   */
+/*                                                                           */
+/* Lines run over `li` and columns over `co`; co is the shorter series and,  */
+/* at equal lengths, lines run over S.  Outputs: the value (or +inf), the    */
+/* number of evaluated cells, and, if trace is non-NULL, per line the value  */
+/* of the pruning point at the end of the line (trace[i-1]), 0 if the line    */
+/* was not completed.  abandon_i / abandon_j receive the cell at which the     */
+/* sweep gave up (0,0 if it did not).                                         */
+/* ------------------------------------------------------------------------- */
+double oracle_eap_model(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r,
+                        double ub, int64_t *cells, int64_t *trace, int64_t *abandon_i,
+                        int64_t *abandon_j) {
+  const double *li = S, *co = T;
+  int64_t nli = lS, nco = lT;
+  if (lT > lS) { li = T; co = S; nli = lT; nco = lS; }
+  if (cells) *cells = 0;
+  if (abandon_i) *abandon_i = 0;
+  if (abandon_j) *abandon_j = 0;
+  if (nli == 0 && nco == 0) return 0.0;
+  if (nco == 0) return ORACLE_INF;
+  if (nli - nco > r) return ORACLE_INF; /* no admissible path */
+  if (trace) for (int64_t i = 0; i < nli; ++i) trace[i] = 0;
+
+  double *a = (double *)malloc((size_t)(nco + 1) * sizeof(double));
+  double *b = (double *)malloc((size_t)(nco + 1) * sizeof(double));
+  if (!a || !b) { free(a); free(b); return NAN; }
+  for (int64_t j = 0; j <= nco; ++j) a[j] = b[j] = ORACLE_INF;
+  double *above = a, *line = b;
+  above[0] = 0.0;              /* the origin cell (0,0) sits in the row above line 1 */
+  int64_t left_edge = 1;       /* first column not known to be > ub (grows only) */
+  int64_t tail_above = 1;      /* first column of the > ub tail of the line above */
+  int64_t ncells = 0;
+  double result = ORACLE_INF;
+  int done = 0;
+
+  for (int64_t i = 1; i <= nli && !done; ++i) {
+    int64_t wlo = i - r < 1 ? 1 : i - r;
+    int64_t whi = i + r > nco ? nco : i + r;
+    if (left_edge < wlo) left_edge = wlo;
+    int64_t tail = 0;          /* column after the last cell <= ub seen on this line */
+    int64_t j = left_edge;
+    line[j - 1] = ORACLE_INF;  /* the column left of the border is beyond ub */
+    const double li_i = li[i - 1];
+#define COST(jj) ((li_i - co[(jj) - 1]) * (li_i - co[(jj) - 1]))
+    /* 1) cells left of the border's continuation: left neighbour is > ub */
+    while (j == left_edge && j < tail_above) {
+      line[j] = COST(j) + (above[j] < above[j - 1] ? above[j] : above[j - 1]);
+      ++ncells;
+      if (line[j] <= ub) tail = j + 1;
+      else ++left_edge;
+      ++j;
+    }
+    /* 2) ordinary cells with all three dependencies */
+    while (j < tail_above) {
+      line[j] = COST(j) + min3d(line[j - 1], above[j], above[j - 1]);
+      ++ncells;
+      if (line[j] <= ub) tail = j + 1;
+      ++j;
+    }
+    /* 3) the column of the previous line's pruning point: no top dependency */
+    if (j <= whi) {
+      if (j == left_edge) {
+        line[j] = COST(j) + above[j - 1];
+        ++ncells;
+        if (line[j] <= ub) tail = j + 1;
+        else { /* the two borders collide: nothing on this line is <= ub */
+          if (abandon_i) *abandon_i = (li == S) ? i : j;
+          if (abandon_j) *abandon_j = (li == S) ? j : i;
+          done = 1;
+          break;
+        }
+      } else {
+        line[j] = COST(j) + (line[j - 1] < above[j - 1] ? line[j - 1] : above[j - 1]);
+        ++ncells;
+        if (line[j] <= ub) tail = j + 1;
+      }
+      ++j;
+    } else if (j == left_edge) { /* the left border ran through the whole line */
+      if (abandon_i) *abandon_i = (li == S) ? i : j - 1;
+      if (abandon_j) *abandon_j = (li == S) ? j - 1 : i;
+      done = 1;
+      break;
+    }
+    /* 4) beyond the previous pruning point: only the left dependency */
+    while (j == tail && j <= whi) {
+      line[j] = COST(j) + line[j - 1];
+      ++ncells;
+      if (line[j] <= ub) tail = j + 1;
+      ++j;
+    }
+#undef COST
+    tail_above = tail;
+    if (trace) trace[i - 1] = tail;
+    double *t = above; above = line; line = t;
+  }
+  if (!done && tail_above > nco) result = above[nco];
+  if (cells) *cells = ncells;
+  free(a);
+  free(b);
+  return result;
+}
