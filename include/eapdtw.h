@@ -1,0 +1,223 @@
+/*
+ * eapdtw.h -- C ABI of the MI355X (gfx950) early-abandoning pruned DTW library.
+ *
+ * Method: Herrmann & Webb, "Early Abandoning PrunedDTW and its application to
+ * similarity search", arXiv 2010.05371.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - DTW is the recurrence of Section 2 (Eq. 1-5): rows i index the first
+ *    series S, columns j index the second series T, cost(a,b) = (a-b)^2 in
+ *    float32, M(0,0)=0, M(i,0)=M(0,j)=+inf.
+ *  - window r is the Sakoe-Chiba window of Section 2.1: a cell is admissible
+ *    iff |i-j| <= r.  r >= max(lS,lT)-1 is unconstrained DTW.  |lS-lT| > r has
+ *    no admissible path and yields +inf.  r < 0 is EINVAL.
+ *  - ub is the early-abandoning bound of Section 2.2: a result <= ub is the
+ *    exact DTW value (bit-identical to the unpruned float32 computation); a
+ *    result that would strictly exceed ub is returned as +inf (ties are kept).
+ *    ub = +inf computes plain DTW.  ub < 0 returns +inf.  NaN ub is EINVAL.
+ *  - Pointers documented as DEVICE point to memory on the context's device
+ *    (e.g. torch tensors on ROCm); they are owned by the caller and must stay
+ *    valid until the stream reaches the call's end.  HOST pointers are owned by
+ *    the caller.  Series are contiguous float32.
+ *  - Every call is ordered on the context's stream.  Calls that return values
+ *    through HOST pointers synchronise that stream before returning; calls
+ *    whose outputs are DEVICE buffers are asynchronous.
+ *  - No exception or abort crosses the ABI: every failure is a negative status
+ *    code and eapdtw_last_error() describes it.  Argument errors are detected on
+ *    the host before any device work is queued.  After a device fault the
+ *    context is poisoned and every later call returns EAPDTW_EPOISONED.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef EAPDTW_H
+#define EAPDTW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EAPDTW_OK 0
+#define EAPDTW_EINVAL (-1)     /* invalid argument (checked before any device work) */
+#define EAPDTW_ENOMEM (-2)     /* device scratch allocation failed */
+#define EAPDTW_EDEVICE (-3)    /* HIP runtime error */
+#define EAPDTW_ENODEV (-4)     /* no usable gfx950 device */
+#define EAPDTW_ENONFINITE (-5) /* NaN or infinity in the input series */
+#define EAPDTW_EPOISONED (-6)  /* an earlier device fault poisoned the context */
+
+typedef struct eapdtw_ctx eapdtw_ctx;
+
+/* Work counters of one call (all optional: pass NULL to skip them).
+ *  cells_nominal   : admissible (in-window) cells of every problem
+ *  cells_evaluated : cells computed for problems that were still alive
+ *  cells_computed  : every cell a SIMD lane computed (>= evaluated)
+ *  problems        : candidates (search) or pairs
+ *  abandoned       : problems that ended as +inf (strictly above the bound)
+ *  kernel_ms       : device time of the call between two stream events       */
+typedef struct {
+  uint64_t cells_nominal;
+  uint64_t cells_evaluated;
+  uint64_t cells_computed;
+  uint64_t problems;
+  uint64_t abandoned;
+  float kernel_ms;
+} eapdtw_stats;
+
+/* One query of a batched search: HOST struct, `query` is a DEVICE pointer. */
+typedef struct {
+  const float *query;
+  int64_t m;
+  int64_t window;
+} eapdtw_query;
+
+/* One result of a batched search (HOST). */
+typedef struct {
+  int64_t offset;
+  double dist;
+} eapdtw_result;
+
+/* Version string of the library. */
+const char *eapdtw_version(void);
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * order work on (NULL: the device's null stream).  *out receives the context.
+ * Returns ENODEV if the device does not exist or is not gfx950. */
+int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out);
+
+/* Releases the context and its device scratch.  NULL is ignored. */
+void eapdtw_destroy(eapdtw_ctx *ctx);
+
+/* Re-targets the context's stream (hipStream_t, NULL = null stream). */
+int eapdtw_set_stream(eapdtw_ctx *ctx, void *hip_stream);
+
+/* Text of the context's last failure ("" if none).  With ctx == NULL: the
+ * calling thread's last eapdtw_create() failure. */
+const char *eapdtw_last_error(const eapdtw_ctx *ctx);
+
+/* Tuning knobs (for tests and the autotuner).  Keys:
+ *   "check_interval" : row groups between reloads of the shared best-so-far (>=1)
+ *   "seed"           : 1 = seed the best-so-far from a window-0 pass and one
+ *                      workgroup of candidates around its best offset (default),
+ *                      0 = start the search from +inf
+ *   "rows_per_group" : rows handled per group by the band kernels (1,2,4,8; 0=auto)
+ *   "wide_rows"      : rows per tile of the wide-window kernel (8,16,32; 0=auto)
+ *   "lanes_per_problem": reserved (1)
+ *   "graph"          : 1 = replay batched searches from a captured hipGraph
+ *   "force_wide"     : 1 = use the wide-window kernel even for narrow windows
+ * Returns EINVAL for an unknown key or value. */
+int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
+int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);
+
+/* ---------------------------------------------------------------------------
+ * Single pair: DTW(S, T) under window r and early-abandoning bound ub
+ * (Section 2 Eq. 1-5; Section 2.1 window; Section 2.2 bound).
+ *   S [lS], T [lT] : DEVICE float32, not normalised by the call.
+ *   window         : r >= 0.
+ *   ub             : bound (+INFINITY = plain DTW); compared in float32,
+ *                    rounded down so that a float32 result <= ub is kept.
+ *   out_dist       : HOST, the distance or +INFINITY.
+ * lS == lT == 0 gives 0; exactly one empty series gives +inf (Eq. 2-4).
+ * Synchronous. */
+int eapdtw_dtw(eapdtw_ctx *ctx, const float *S, int64_t lS, const float *T, int64_t lT,
+               int64_t window, double ub, double *out_dist, eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Batch of independent pairs of equal length `len` (Section 2 Eq. 1-5).
+ *   X, Y [npairs][len] : DEVICE float32 row-major; pair p = (X[p], Y[p]).
+ *   ub_mode 0          : no bound (plain DTW), `ub` ignored.
+ *   ub_mode 1          : ub [npairs] DEVICE float32, one bound per pair.
+ *   ub_mode 2          : the PrunedDTW setting of Section 2.3 -- the bound of
+ *                        each pair is its squared Euclidean distance (the
+ *                        diagonal path), computed with the same float32
+ *                        operations as the diagonal cells, so it never binds.
+ *   out [npairs]       : DEVICE float32 distances (+inf when abandoned).
+ * Asynchronous on the context's stream. */
+int eapdtw_dtw_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs, int64_t len,
+                     int64_t window, int ub_mode, const float *ub, float *out, eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * All pairwise distances of N series (Section 2.3: pruning with the squared
+ * Euclidean distance as the only bound, e.g. for 1-NN classification).
+ *   X [N][len] : DEVICE float32 row-major.
+ *   out_D      : DEVICE float32 [N*(N-1)/2], the strict upper triangle in
+ *                row-major order: pair (i,j), i<j, at
+ *                i*N - i*(i+1)/2 + (j-i-1); the pair's rows are X[i], columns X[j].
+ * Asynchronous. */
+int eapdtw_pairwise(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t window,
+                    float *out_D, eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Nearest-neighbour subsequence search (Section 2.2 early abandoning against
+ * the best-so-far; Section 5, the "no lower bound" configuration: every
+ * candidate is evaluated with the pruned, early-abandoned DTW).
+ *   query [m]   : DEVICE float32; z-normalised by the call (population sigma).
+ *   series [n]  : DEVICE float32; every offset k in [0, n-m] is a candidate
+ *                 z-normalised on the fly; a window with zero deviation
+ *                 normalises to all zeros.
+ *   window      : r >= 0.
+ *   out_offset  : HOST, the smallest offset among the minimal distances.
+ *   out_dist    : HOST, that distance (float32 value widened).
+ * m == 0, n < m: EINVAL.  Non-finite values in query or series: ENONFINITE.
+ * Synchronous. */
+int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                     int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
+                     eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Many queries of uneven length and window against one series, in one
+ * persistent launch (each query: the search of eapdtw_nn_search).
+ *   qs [nq] : HOST array of queries (query pointers are DEVICE).
+ *   out [nq]: HOST results.
+ * Synchronous. */
+int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
+                           const float *series, int64_t n, eapdtw_result *out,
+                           eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Forward of the differentiable batch (Section 2: DTW value; the gradient
+ * follows the optimal warping path).  Plain DTW (no bound) of pairs
+ * (S[p], T[p]) of equal length, storing the band state every few rows into
+ * `ckpt` so that the backward can recompute the matrix tile by tile.
+ *   S, T [npairs][len]: DEVICE float32.   out_dist [npairs]: DEVICE float32.
+ *   ckpt : DEVICE scratch of eapdtw_dtw_ckpt_bytes(npairs, len, window) bytes,
+ *          owned by the caller, consumed by eapdtw_dtw_bwd.
+ * Asynchronous. */
+int64_t eapdtw_dtw_ckpt_bytes(int64_t npairs, int64_t len, int64_t window);
+int eapdtw_dtw_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
+                   int64_t window, float *out_dist, void *ckpt);
+
+/* Backward: recomputes the forward from `ckpt` in tiles, backtracks the
+ * optimal path (ties: diagonal, then (i-1,j), then (i,j-1)) and scatters
+ * dD/dS(i) = sum_j 2(S(i)-T(j)) g and dD/dT(j) = -sum_i 2(S(i)-T(j)) g over the
+ * path cells, g = grad_out[p].  A pair with infinite distance gets zero
+ * gradients.
+ *   grad_out [npairs], grad_S, grad_T [npairs][len]: DEVICE float32
+ *   (grad_S/grad_T are overwritten).
+ * Asynchronous. */
+int eapdtw_dtw_bwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
+                   int64_t window, const void *ckpt, const float *grad_out, float *grad_S,
+                   float *grad_T);
+
+/* ---------------------------------------------------------------------------
+ * Exposed steps of the search, for tests.
+ * Window statistics of every offset k in [0, n-m]: mean and population
+ * standard deviation of series[k..k+m), as the search computes them.
+ *   mean, sigma [n-m+1] : DEVICE float64.  Asynchronous. */
+int eapdtw_window_stats(eapdtw_ctx *ctx, const float *series, int64_t n, int64_t m, double *mean,
+                        double *sigma);
+
+/* z-normalised copy of x [m] (population sigma, zero deviation -> zeros).
+ *   x, out [m] : DEVICE float32.  Asynchronous. */
+int eapdtw_znorm(eapdtw_ctx *ctx, const float *x, int64_t m, float *out);
+
+/* Per-candidate early-abandoned distances of a search against a fixed bound:
+ *   out[k] = EAP(z(query), z(series[k..k+m)), window, ub) for k in [0, n-m].
+ *   out [n-m+1] : DEVICE float32.  Asynchronous. */
+int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                    int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EAPDTW_H */

@@ -1,0 +1,249 @@
+"""Early-abandoning pruned DTW (Herrmann & Webb, arXiv 2010.05371) on MI355X.
+
+Thin Python binding over the C ABI of ``libeapdtw.so`` (include/eapdtw.h):
+argument marshalling only -- every step of the method runs in the gfx950 HIP
+kernels.  PyTorch provides device memory and the current stream.  There is no
+CPU fallback: without the built library or a gfx950 device every call raises.
+
+Functions (names follow the C ABI):
+
+* ``dtw(S, T, window, ub=inf)``            -- one pair (Section 2, Eq. 1-5;
+  Section 2.1 window; Section 2.2 bound) -> float
+* ``dtw_pairs(X, Y, window, ub=None|tensor|'ed')`` -- batch of pairs -> tensor
+* ``pairwise(X, window)``                  -- all i<j distances (ub = squared ED)
+* ``nn_search(query, series, window)``     -- best (offset, distance)
+* ``nn_search_batch([(query, window), ...], series)``
+* ``nn_dists(query, series, window, ub)``  -- per-candidate bounded distances
+* ``window_stats(series, m)``, ``znorm(x)`` -- exposed steps of the search
+* ``DTWFunction.apply(S, T, window)``      -- differentiable batch (autograd)
+* ``window_from_ratio(ratio, m)``          -- integer window, rounded up
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import threading
+
+import torch
+
+from . import _lib
+from ._lib import EapdtwError, Query, Result, Stats
+
+__all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_dists",
+           "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
+           "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index"]
+
+
+def window_from_ratio(ratio: float, m: int) -> int:
+    """Integer Sakoe-Chiba window for a ratio of the series length, rounded up."""
+    if ratio < 0:
+        raise ValueError("ratio must be >= 0")
+    return int(math.ceil(ratio * m - 1e-9))
+
+
+class Context:
+    """One library context (device, stream, scratch)."""
+
+    def __init__(self, device: int | None = None):
+        lib = _lib.load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self._lib = lib
+        h = ctypes.c_void_p()
+        rc = lib.eapdtw_create(self.device, None, ctypes.byref(h))
+        if rc != 0:
+            raise EapdtwError(rc, lib.eapdtw_last_error(None).decode())
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                self._lib.eapdtw_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, rc: int):
+        if rc != 0:
+            raise EapdtwError(rc, self._lib.eapdtw_last_error(self._h).decode())
+
+    def bind_stream(self):
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        self.check(self._lib.eapdtw_set_stream(self._h, ctypes.c_void_p(st)))
+
+    def set_option(self, key: str, value: int):
+        self.check(self._lib.eapdtw_set_option(self._h, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = ctypes.c_int64()
+        self.check(self._lib.eapdtw_get_option(self._h, key.encode(), ctypes.byref(v)))
+        return v.value
+
+
+_ctx_lock = threading.Lock()
+_ctxs: dict = {}
+
+
+def context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    key = (threading.get_ident(), int(device))
+    with _ctx_lock:
+        c = _ctxs.get(key)
+        if c is None:
+            c = Context(device)
+            _ctxs[key] = c
+    return c
+
+
+def set_option(key: str, value: int, device: int | None = None):
+    context(device).set_option(key, value)
+
+
+def get_option(key: str, device: int | None = None) -> int:
+    return context(device).get_option(key)
+
+
+def _dev(x, device=None) -> torch.Tensor:
+    """float32 contiguous tensor on the GPU (host data is copied)."""
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(x)
+    if device is None:
+        device = torch.cuda.current_device() if not x.is_cuda else x.device.index
+    x = x.to(device=f"cuda:{device}", dtype=torch.float32)
+    return x.contiguous()
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def dtw(S, T, window: int, ub: float = math.inf, stats: bool = False):
+    S, T = _dev(S), _dev(T)
+    ctx = context(S.device.index)
+    ctx.bind_stream()
+    out = ctypes.c_double()
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_dtw(ctx.handle, _ptr(S), S.numel(), _ptr(T), T.numel(), int(window),
+                                  float(ub), ctypes.byref(out), ctypes.byref(st)))
+    return (out.value, st.as_dict()) if stats else out.value
+
+
+def dtw_pairs(X, Y, window: int, ub=None, stats: bool = False):
+    """DTW of pairs (X[p], Y[p]).  ub: None (plain DTW), a per-pair tensor, or
+    'ed' for the squared Euclidean distance of each pair (Section 2.3)."""
+    X, Y = _dev(X), _dev(Y)
+    if X.shape != Y.shape or X.dim() != 2:
+        raise ValueError("X and Y must both be [npairs, len]")
+    ctx = context(X.device.index)
+    ctx.bind_stream()
+    out = torch.empty(X.shape[0], device=X.device, dtype=torch.float32)
+    if ub is None:
+        mode, ubt = 0, None
+    elif isinstance(ub, str):
+        if ub != "ed":
+            raise ValueError("ub must be None, 'ed' or a tensor")
+        mode, ubt = 2, None
+    else:
+        mode, ubt = 1, _dev(ub, X.device.index)
+        if ubt.numel() != X.shape[0]:
+            raise ValueError("ub must have one entry per pair")
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_dtw_pairs(ctx.handle, _ptr(X), _ptr(Y), X.shape[0], X.shape[1],
+                                        int(window), mode, _ptr(ubt) if ubt is not None else None,
+                                        _ptr(out), ctypes.byref(st) if stats else None))
+    return (out, st.as_dict()) if stats else out
+
+
+def pairwise_index(N: int, i: int, j: int) -> int:
+    """Position of pair (i, j), i < j, in the upper-triangle output of pairwise()."""
+    return i * N - i * (i + 1) // 2 + (j - i - 1)
+
+
+def pairwise(X, window: int, stats: bool = False):
+    X = _dev(X)
+    if X.dim() != 2:
+        raise ValueError("X must be [N, len]")
+    N = X.shape[0]
+    ctx = context(X.device.index)
+    ctx.bind_stream()
+    out = torch.empty(N * (N - 1) // 2, device=X.device, dtype=torch.float32)
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_pairwise(ctx.handle, _ptr(X), N, X.shape[1], int(window), _ptr(out),
+                                       ctypes.byref(st) if stats else None))
+    return (out, st.as_dict()) if stats else out
+
+
+def nn_search(query, series, window: int, stats: bool = False):
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    off = ctypes.c_int64()
+    dist = ctypes.c_double()
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn_search(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                        int(window), ctypes.byref(off), ctypes.byref(dist),
+                                        ctypes.byref(st) if stats else None))
+    res = (off.value, dist.value)
+    return (res, st.as_dict()) if stats else res
+
+
+def nn_search_batch(queries, series, stats: bool = False):
+    """queries: list of (query, window).  Returns a list of (offset, distance)."""
+    x = _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    qs = [(_dev(q, x.device.index), int(w)) for q, w in queries]
+    arr = (Query * len(qs))()
+    for i, (q, w) in enumerate(qs):
+        arr[i].query = q.data_ptr()
+        arr[i].m = q.numel()
+        arr[i].window = w
+    res = (Result * len(qs))()
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn_search_batch(ctx.handle, arr, len(qs), _ptr(x), x.numel(), res,
+                                              ctypes.byref(st) if stats else None))
+    out = [(r.offset, r.dist) for r in res]
+    return (out, st.as_dict()) if stats else out
+
+
+def nn_dists(query, series, window: int, ub: float = math.inf, stats: bool = False):
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    out = torch.empty(x.numel() - q.numel() + 1, device=x.device, dtype=torch.float32)
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn_dists(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                       int(window), float(ub), _ptr(out),
+                                       ctypes.byref(st) if stats else None))
+    return (out, st.as_dict()) if stats else out
+
+
+def window_stats(series, m: int):
+    x = _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    K = x.numel() - m + 1
+    mean = torch.empty(max(K, 0), device=x.device, dtype=torch.float64)
+    sd = torch.empty(max(K, 0), device=x.device, dtype=torch.float64)
+    ctx.check(ctx._lib.eapdtw_window_stats(ctx.handle, _ptr(x), x.numel(), int(m), _ptr(mean),
+                                           _ptr(sd)))
+    return mean, sd
+
+
+def znorm(x):
+    x = _dev(x)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    out = torch.empty_like(x)
+    ctx.check(ctx._lib.eapdtw_znorm(ctx.handle, _ptr(x), x.numel(), _ptr(out)))
+    return out
+
+
+from .autograd import DTWFunction  # noqa: E402

@@ -1,0 +1,161 @@
+// aux.hip -- small kernels around the DTW sweeps: query normalisation, input
+// checks, transposition into the coalesced pair layout, counters.
+#include "band.h"
+#include "dispatch.h"
+
+namespace eapdtw {
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ bool not_finite(float v) { return !(fabsf(v) <= 3.402823466e38f); }
+
+// Block-wide float64 sum (256 threads).
+__device__ double block_sum_f64(double v, double *sh) {
+  v = wave_sum_f64(v);
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += sh[i];
+  return t;
+}
+
+// z-normalisation of one short series by one workgroup (two passes in
+// float64, population sigma; zero sigma normalises to zeros).  Writes
+// out[pad + j] for j < m and +inf into the `pad` entries on each side when
+// pad > 0.  Counts non-finite inputs.
+__global__ void znorm_kernel(const float *__restrict__ q, int m, float *__restrict__ out, int pad,
+                             unsigned long long *counters) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  int bad = 0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const float v = q[j];
+    bad += not_finite(v);
+    s += (double)v;
+  }
+  const double mean = block_sum_f64(s, sh) / (double)m;
+  double ss = 0.0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const double dv = (double)q[j] - mean;
+    ss += dv * dv;
+  }
+  const double var = block_sum_f64(ss, sh) / (double)m;
+  const double sd = sqrt(var);
+  for (int j = threadIdx.x; j < m; j += blockDim.x)
+    out[pad + j] = sd > 0.0 ? (float)(((double)q[j] - mean) / sd) : 0.0f;
+  for (int j = threadIdx.x; j < pad; j += blockDim.x) {
+    out[j] = kInf;
+    out[pad + m + j] = kInf;
+  }
+  if (counters && bad) atomicAdd(&counters[kCntNonFinite], (unsigned long long)bad);
+}
+
+hipError_t launch_query_prep(const float *q, int m, float *qpad, unsigned long long *counters,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(znorm_kernel, dim3(1), dim3(256), 0, st, q, m, qpad, kColPad, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_znorm(const float *x, int m, float *out, hipStream_t st) {
+  hipLaunchKernelGGL(znorm_kernel, dim3(1), dim3(256), 0, st, x, m, out, 0,
+                     (unsigned long long *)nullptr);
+  return hipGetLastError();
+}
+
+__global__ void check_finite_kernel(const float *__restrict__ x, int64_t n,
+                                    unsigned long long *counters) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad += not_finite(x[i]);
+  if (bad) atomicAdd(&counters[kCntNonFinite], (unsigned long long)bad);
+}
+
+__global__ void fill_f32_kernel(float *p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float *x, int64_t n, unsigned long long *counters,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, n,
+                     counters);
+  return hipGetLastError();
+}
+
+// src [npairs][len] row-major  ->  dst [(len + 2 pad)][ld], element t of pair p
+// at dst[(t + pad) * ld + p]; padding rows and the columns p >= npairs hold
+// padval.  32x32 tiles through LDS keep both sides coalesced.
+__global__ void transpose_pad_kernel(const float *__restrict__ src, int64_t npairs, int len,
+                                     int64_t ld, int pad, float padval, float *__restrict__ dst) {
+  __shared__ float tile[32][33];
+  const int64_t p0 = (int64_t)blockIdx.x * 32;
+  const int64_t t0 = (int64_t)blockIdx.y * 32 - pad;  // padded row index start (in t units)
+  const int tx = threadIdx.x, ty = threadIdx.y;       // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t p = p0 + r, t = t0 + tx;
+    float v = padval;
+    if (p < npairs && t >= 0 && t < len) v = src[p * len + t];
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  const int64_t rows = (int64_t)len + 2 * pad;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t trow = t0 + r + pad, p = p0 + tx;
+    if (trow >= 0 && trow < rows && p < ld) dst[trow * ld + p] = tile[tx][r];
+  }
+}
+
+hipError_t launch_transpose_pad(const float *src, int64_t npairs, int len, int64_t ld, int pad,
+                                float padval, float *dst, hipStream_t st) {
+  const int64_t rows = (int64_t)len + 2 * pad;
+  dim3 grid((unsigned)((ld + 31) / 32), (unsigned)((rows + 31) / 32));
+  hipLaunchKernelGGL(transpose_pad_kernel, grid, dim3(32, 8), 0, st, src, npairs, len, ld, pad,
+                     padval, dst);
+  return hipGetLastError();
+}
+
+// Window statistics exactly as the search kernels compute them (one wave per
+// 64 consecutive offsets).
+__global__ __launch_bounds__(64) void window_stats_kernel(const float *__restrict__ x, int64_t n,
+                                                          int m, double *mean, double *sd) {
+  const int64_t K = n - m + 1;
+  const int64_t kb = (int64_t)blockIdx.x * kWave;
+  const int lane = threadIdx.x;
+  double mu, s;
+  wave_window_stats(x, n, m, kb, lane, mu, s);
+  if (kb + lane < K) {
+    mean[kb + lane] = mu;
+    sd[kb + lane] = s;
+  }
+}
+
+hipError_t launch_window_stats(const float *x, int64_t n, int m, double *mean, double *sd,
+                               hipStream_t st) {
+  const int64_t K = n - m + 1;
+  hipLaunchKernelGGL(window_stats_kernel, dim3((unsigned)((K + 63) / 64)), dim3(64), 0, st, x, n,
+                     m, mean, sd);
+  return hipGetLastError();
+}
+
+}  // namespace eapdtw

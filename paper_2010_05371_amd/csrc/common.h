@@ -1,0 +1,81 @@
+// common.h -- shared device/host definitions of the gfx950 EAPrunedDTW kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eapdtw {
+
+constexpr float kInf = __builtin_huge_valf();
+constexpr int kWave = 64;
+
+// Largest window handled by the band-in-registers kernels; wider windows go to
+// the tiled wide-window kernel.
+constexpr int kBandRMax = 64;
+// Padding (in elements) on each side of a padded column series: out-of-matrix
+// columns hold +inf so that their cells evaluate to +inf.  Twice the largest
+// band window, because a row-longer-than-column pair reaches 2r past the end.
+constexpr int kColPad = 2 * kBandRMax + 16;
+
+// Counter slots written by the kernels (device u64 array).
+enum Counter : int {
+  kCntEvaluated = 0,  // cells computed for problems still alive
+  kCntComputed = 1,   // all lane-cells computed
+  kCntAbandoned = 2,  // problems finished as +inf
+  kCntNonFinite = 3,  // non-finite input values seen
+  kCntSlots = 8
+};
+
+// The shared best-so-far of a search packs (distance, offset) into one u64 so
+// that a single 64-bit atomic min keeps the lexicographic minimum: distances
+// are non-negative float32, whose bit patterns order like unsigned integers.
+__host__ __device__ inline unsigned long long pack_best(float d, uint32_t k) {
+  return ((unsigned long long)__builtin_bit_cast(uint32_t, d) << 32) | k;
+}
+__host__ __device__ inline float best_dist(unsigned long long b) {
+  return __builtin_bit_cast(float, (uint32_t)(b >> 32));
+}
+__host__ __device__ inline uint32_t best_offset(unsigned long long b) { return (uint32_t)b; }
+
+// Arguments of the subsequence-search band kernel.
+struct NNArgs {
+  const float *x;                    // series [n]
+  int64_t n;
+  int m;                             // query length
+  const float *qpad;                 // z(query) with kColPad +inf on each side
+  unsigned long long *bsf;           // shared best-so-far (packed)
+  int64_t k_begin, k_end;            // candidate offsets [k_begin, k_end)
+  const unsigned long long *center;  // optional: restrict to 64 offsets around center's offset
+  const unsigned long long *bsf_init;// optional: seed bsf (distance part) from this word first
+  float fixed_ub;                    // per-candidate-distance mode: fixed bound
+  float *dists;                      // per-candidate-distance mode: out[k - k_begin]
+  unsigned long long *counters;      // kCntSlots (nullable)
+  int check_interval;                // row groups between best-so-far reloads
+};
+
+// Arguments of the pair band kernel.  Row and column series are stored
+// transposed (element t of pair p at [t * ld + p]) so that a wave's loads are
+// coalesced; the column series is padded with kColPad +inf rows on each side.
+struct PairArgs {
+  const float *rowsT;     // [lrow][ld]
+  const float *colsT;     // [lcol + 2*kColPad][ld]
+  int64_t ld;
+  int64_t npairs;
+  int lrow, lcol;
+  int ub_mode;            // 0 none, 1 per-pair array, 2 squared Euclidean distance
+  const float *ub;        // [npairs] when ub_mode == 1
+  float ub_scalar;        // bound for every pair when ub_mode == 3
+  float *out;             // [npairs]
+  float *ckpt;            // optional checkpoints: [nck][2R+1][ld]
+  int ckpt_every;         // rows between checkpoints (multiple of the row group)
+  unsigned long long *counters;
+};
+
+// Number of admissible in-matrix cells of row i (0-based) of an lrow x lcol
+// matrix under window r.
+__host__ __device__ inline int row_cells(int i, int lcol, int r) {
+  int lo = i - r < 0 ? 0 : i - r;
+  int hi = i + r > lcol - 1 ? lcol - 1 : i + r;
+  return hi >= lo ? hi - lo + 1 : 0;
+}
+
+}  // namespace eapdtw

@@ -1,0 +1,29 @@
+// dispatch.h -- host-side entry points of the device kernels.
+#pragma once
+#include "common.h"
+
+namespace eapdtw {
+
+typedef hipError_t (*NNLaunchFn)(const NNArgs &, int64_t nblocks, int rows_per_group, bool dists,
+                                 hipStream_t);
+typedef hipError_t (*PairLaunchFn)(const PairArgs &, int64_t nblocks, int rows_per_group,
+                                   hipStream_t);
+
+// Band-in-registers kernels for windows 0..kBandRMax (nullptr otherwise).
+NNLaunchFn nn_band_launcher(int r);
+PairLaunchFn pair_band_launcher(int r);
+
+// Auxiliary kernels (aux.hip).
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
+hipError_t launch_query_prep(const float *q, int m, float *qpad, unsigned long long *counters,
+                             hipStream_t st);
+hipError_t launch_check_finite(const float *x, int64_t n, unsigned long long *counters,
+                               hipStream_t st);
+hipError_t launch_transpose_pad(const float *src, int64_t npairs, int len, int64_t ld,
+                                int pad, float padval, float *dst, hipStream_t st);
+hipError_t launch_window_stats(const float *x, int64_t n, int m, double *mean, double *sd,
+                               hipStream_t st);
+hipError_t launch_znorm(const float *x, int m, float *out, hipStream_t st);
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
+
+}  // namespace eapdtw

@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports every symbol include/eapdtw.h declares;
+host-side behaviour that needs no GPU (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2010_05371_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eapdtw.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eapdtw_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("eapdtw_dtw", "eapdtw_nn_search", "eapdtw_nn_search_batch", "eapdtw_dtw_pairs",
+                 "eapdtw_pairwise", "eapdtw_dtw_fwd", "eapdtw_dtw_bwd", "eapdtw_create",
+                 "eapdtw_destroy", "eapdtw_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and they are real exported C symbols
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    for n in declared_functions():
+        assert ctypes.cast(getattr(raw, n), ctypes.c_void_p).value
+
+
+def test_version():
+    assert b"gfx950" in _lib.load().eapdtw_version()
+
+
+def test_null_context_is_einval():
+    lib = _lib.load()
+    out = ctypes.c_double()
+    assert lib.eapdtw_dtw(None, None, 0, None, 0, 0, 0.0, ctypes.byref(out), None) == _lib.EAPDTW_EINVAL
+    assert lib.eapdtw_set_option(None, b"seed", 1) == _lib.EAPDTW_EINVAL
+    assert lib.eapdtw_nn_search(None, None, 1, None, 1, 0, None, None, None) == _lib.EAPDTW_EINVAL
+
+
+def test_create_rejects_null_out():
+    lib = _lib.load()
+    assert lib.eapdtw_create(0, None, None) == _lib.EAPDTW_EINVAL
+    assert lib.eapdtw_last_error(None)
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be visible: ENODEV is only checked without one")
+def test_create_without_device_is_enodev():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    rc = lib.eapdtw_create(0, None, ctypes.byref(h))
+    assert rc == _lib.EAPDTW_ENODEV
+    assert not h.value
+    assert lib.eapdtw_last_error(None)
+
+
+def test_ckpt_bytes_is_host_arithmetic():
+    lib = _lib.load()
+    assert lib.eapdtw_dtw_ckpt_bytes(-1, 10, 2) < 0
