@@ -1,0 +1,183 @@
+"""Benchmark of the early-abandoning pruned DTW hot path on one MI355X.
+
+One step = the nearest-neighbour subsequence search of the noisy
+multi-sinusoid workload (2,000,000-point series, query of length 256 cut from
+an independent realisation plus N(0, 0.1) noise) at every window of the
+workload, r in {0, 13, 26, 52} (0, 5, 10, 20 % of 256): z-normalised window
+statistics, pruned and early-abandoned DTW of every candidate, shared
+best-so-far.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line (rank 0): candidates/s over the step, effective and
+nominal cells/s, pruned fraction, the VALU roofline of the dominant kernel
+(5 float32 operations per evaluated cell against the 157.3 TFLOP/s vector
+peak) and the FP64 CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NN-search candidates/s + effective DTW GCUPS (1 MI355X); fwd+bwd pairs/s"
+PEAK_FP32_VALU = 157.3e12        # FLOP/s, MI355X vector FP32 (packed FMA)
+OPS_PER_CELL = 5                 # sub, mul, add, two 2-input mins
+M = 256
+N_SERIES = 2_000_000
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("band.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_2010_05371_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(p) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("kernels", {}).get(kernel)
+
+
+def cpu_baseline(q32, x32, windows, budget_s: float):
+    """The FP64 oracle (brute force, every window) on a bounded sample of offsets."""
+    import numpy as np
+
+    import gen
+    import oracle
+    q, x = gen.as_oracle(q32), gen.as_oracle(x32)
+    threads = oracle.default_threads()
+    # calibrate on a small sample, then size the sample to the budget
+    probe = 64 * threads
+    t0 = time.perf_counter()
+    for w in windows:
+        oracle.nn_dists(q, x, w, np.arange(probe), nthreads=threads)
+    dt = time.perf_counter() - t0
+    n = int(max(probe, min(x.size - q.size + 1, probe * budget_s / max(dt, 1e-6))))
+    offs = np.linspace(0, x.size - q.size, n).astype(np.int64)
+    t0 = time.perf_counter()
+    for w in windows:
+        oracle.nn_dists(q, x, w, offs, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * len(windows) / dt, "unit": "candidates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} evenly spaced offsets of the 2,000,000-point series, each at windows "
+                      f"{list(windows)}, brute-force FP64 full-matrix DTW with two-pass "
+                      f"z-normalisation ({dt:.1f} s on {threads} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of CPU oracle work for cpu_baseline (0 = skip)")
+    ap.add_argument("--n", type=int, default=N_SERIES)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2010_05371_amd as eap
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    q32, x32, windows = gen.c2(n=args.n, m=M)
+    q = torch.from_numpy(q32).to(dev)
+    x = torch.from_numpy(x32).to(dev)
+    K = x32.size - q32.size + 1
+
+    def step(record):
+        for w in windows:
+            (k, d), st = eap.nn_search(q, x, w, stats=True)
+            if record is not None:
+                record.setdefault(w, []).append((k, d, st))
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    rec = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    cand_per_step = K * len(windows)
+
+    per_window = {}
+    tot_eval = tot_nom = 0
+    dom = None
+    for w in windows:
+        rs = rec[w]
+        st = rs[-1][2]
+        main_ms = float(np.mean([r[2]["main_kernel_ms"] for r in rs]))
+        call_ms = float(np.mean([r[2]["kernel_ms"] for r in rs]))
+        ev, nom, comp = st["cells_evaluated"], st["cells_nominal"], st["cells_computed"]
+        tot_eval += ev
+        tot_nom += nom
+        per_window[str(w)] = {
+            "offset": rs[-1][0], "dist": rs[-1][1], "call_ms": round(call_ms, 4),
+            "main_kernel_ms": round(main_ms, 4), "candidates_per_s": K / (call_ms / 1e3),
+            "cells_nominal": nom, "cells_evaluated": ev, "cells_computed": comp,
+            "pruned_fraction": 1.0 - ev / nom, "abandoned": st["abandoned"],
+            "effective_gcups_kernel": ev / (main_ms / 1e3) / 1e9,
+        }
+        if dom is None or main_ms > per_window[str(dom)]["main_kernel_ms"]:
+            dom = w
+    dw = per_window[str(dom)]
+    achieved = OPS_PER_CELL * dw["cells_evaluated"] / (dw["main_kernel_ms"] / 1e3)
+    kname = f"nn_band_kernel<{dom}, 4, false>"
+    traffic = load_traffic(kname)
+    line = {
+        "metric": METRIC,
+        "value": cand_per_step / (ms_per_step / 1e3),
+        "unit": "candidates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "nn_search noisy multi-sinusoid n=2,000,000 m=256 windows {0,13,26,52}",
+                   "n": int(x32.size), "m": M, "windows": list(windows),
+                   "candidates_per_window": K},
+        "effective_gcups": tot_eval / (ms_per_step / 1e3) / 1e9,
+        "nominal_gcups": tot_nom / (ms_per_step / 1e3) / 1e9,
+        "pruned_fraction": 1.0 - tot_eval / tot_nom,
+        "per_window": per_window,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU, "traffic": traffic,
+                     "ops_per_cell": OPS_PER_CELL,
+                     "cells_per_launch": dw["cells_evaluated"],
+                     "launch_ms": dw["main_kernel_ms"]},
+    }
+    if args.cpu_budget > 0:
+        line["cpu_baseline"] = cpu_baseline(q32, x32, windows, args.cpu_budget)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,9 @@ typedef struct eapdtw_ctx eapdtw_ctx;
  *  cells_computed  : every cell a SIMD lane computed (>= evaluated)
  *  problems        : candidates (search) or pairs
  *  abandoned       : problems that ended as +inf (strictly above the bound)
- *  kernel_ms       : device time of the call between two stream events       */
+ *  kernel_ms       : device time of the whole call between two stream events
+ *  main_kernel_ms  : device time of the call's dominant DP kernel alone
+ *                    (stream events around that launch)                      */
 typedef struct {
   uint64_t cells_nominal;
   uint64_t cells_evaluated;
@@ -62,6 +64,7 @@ typedef struct {
   uint64_t problems;
   uint64_t abandoned;
   float kernel_ms;
+  float main_kernel_ms;
 } eapdtw_stats;
 
 /* One query of a batched search: HOST struct, `query` is a DEVICE pointer. */

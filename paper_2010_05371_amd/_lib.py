@@ -24,7 +24,8 @@ ERROR_NAMES = {
 class Stats(ctypes.Structure):
     _fields_ = [("cells_nominal", ctypes.c_uint64), ("cells_evaluated", ctypes.c_uint64),
                 ("cells_computed", ctypes.c_uint64), ("problems", ctypes.c_uint64),
-                ("abandoned", ctypes.c_uint64), ("kernel_ms", ctypes.c_float)]
+                ("abandoned", ctypes.c_uint64), ("kernel_ms", ctypes.c_float),
+                ("main_kernel_ms", ctypes.c_float)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -11,6 +11,7 @@
 
 #include "../../include/eapdtw.h"
 #include "dispatch.h"
+#include "wide.h"
 
 using namespace eapdtw;
 
@@ -23,7 +24,7 @@ struct eapdtw_ctx {
   size_t scratch_cap = 0;
   char *pinned = nullptr;
   size_t pinned_cap = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
   // options
   int64_t check_interval = 1;
   int64_t seed = 1;
@@ -32,6 +33,8 @@ struct eapdtw_ctx {
   int64_t lanes_per_problem = 1;
   int64_t graph = 1;
   int64_t force_wide = 0;
+  int64_t seed_stride = 4;
+  int64_t seed_window = 8;
 };
 
 static thread_local std::string g_create_error;
@@ -129,6 +132,13 @@ int64_t band_cells_total(int64_t lrow, int64_t lcol, int64_t r) {
   return c;
 }
 
+// Persistent single-wave workgroups of the wide kernels: enough to fill the
+// chip, each with its own boundary row in the scratch.
+int64_t wide_grid(int64_t ntasks) {
+  const int64_t cap = 4096;
+  return ntasks < cap ? ntasks : cap;
+}
+
 int pick_rows(const eapdtw_ctx *ctx, int r) {
   if (ctx->rows_per_group) return (int)ctx->rows_per_group;
   return r == 0 ? 8 : 4;
@@ -144,15 +154,33 @@ int readback(eapdtw_ctx *ctx, size_t off, size_t nbytes) {
   return EAPDTW_OK;
 }
 
+// sum of one counter over its stripes
+uint64_t counter_sum(const unsigned long long *cnt, int slot) {
+  uint64_t t = 0;
+  for (int s = 0; s < kCntStripes; ++s) t += cnt[s * kCntStride + slot];
+  return t;
+}
+
 void fill_stats(eapdtw_stats *st, const unsigned long long *cnt, uint64_t nominal,
-                uint64_t problems, float ms) {
+                uint64_t problems, float ms, float main_ms = -1.f) {
   if (!st) return;
   st->cells_nominal = nominal;
-  st->cells_evaluated = cnt[kCntEvaluated];
-  st->cells_computed = cnt[kCntComputed];
+  st->cells_evaluated = counter_sum(cnt, kCntEvaluated);
+  st->cells_computed = counter_sum(cnt, kCntComputed);
   st->problems = problems;
-  st->abandoned = cnt[kCntAbandoned];
+  st->abandoned = counter_sum(cnt, kCntAbandoned);
   st->kernel_ms = ms;
+  st->main_kernel_ms = main_ms < 0.f ? ms : main_ms;
+}
+
+// elapsed time between two recorded events (0 when unavailable)
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    ms = 0.f;
+  }
+  return ms;
 }
 
 }  // namespace
@@ -194,7 +222,8 @@ int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out) {
   eapdtw_ctx *c = new eapdtw_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess) {
     g_create_error = "hipEventCreate failed";
     delete c;
     return EAPDTW_EDEVICE;
@@ -211,6 +240,8 @@ void eapdtw_destroy(eapdtw_ctx *ctx) {
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+  if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
   delete ctx;
 }
 
@@ -237,6 +268,8 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "lanes_per_problem")) return &ctx->lanes_per_problem;
   if (!strcmp(key, "graph")) return &ctx->graph;
   if (!strcmp(key, "force_wide")) return &ctx->force_wide;
+  if (!strcmp(key, "seed_stride")) return &ctx->seed_stride;
+  if (!strcmp(key, "seed_window")) return &ctx->seed_window;
   return nullptr;
 }
 
@@ -250,6 +283,8 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 8 || value == 16 || value == 32;
   else if (!strcmp(key, "lanes_per_problem")) ok = value == 1;
+  else if (!strcmp(key, "seed_stride")) ok = value >= 1 && value <= 1024;
+  else if (!strcmp(key, "seed_window")) ok = value >= 0 && value <= kBandRMax;
   if (!ok) return fail(ctx, EAPDTW_EINVAL, std::string("bad value for option ") + key);
   *slot = value;
   return EAPDTW_OK;
@@ -260,6 +295,88 @@ int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value) {
   int64_t *slot = option_slot(const_cast<eapdtw_ctx *>(ctx), key);
   if (!slot) return EAPDTW_EINVAL;
   *value = *slot;
+  return EAPDTW_OK;
+}
+
+// --------------------------------------------------------------------------- pair engine
+
+// Every call's scratch starts with the striped counters.
+constexpr size_t kCntBytes = sizeof(unsigned long long) * kCntWords;
+
+static bool use_band(const eapdtw_ctx *ctx, int64_t r) { return r <= kBandRMax && !ctx->force_wide; }
+
+// DTW of pairs (rows X[p] of length lrow, columns Y[p] of length lcol), window
+// r (already clipped to max(lrow,lcol)-1), bound per ub_mode.  Queues all
+// device work on the context stream; with `stats` it also waits and fills them.
+static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs,
+                        int64_t lrow, int64_t lcol, int64_t r, int ub_mode, const float *ub,
+                        float ub_scalar, float *out, float *ckpt, int ckpt_every,
+                        eapdtw_stats *stats) {
+  hipStream_t st = ctx->stream;
+  const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
+  const bool band = use_band(ctx, r);
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_rows = pl.add(sizeof(float) * lrow * ld);
+  const size_t o_cols = pl.add(sizeof(float) * (lcol + (band ? 2 * kColPad : 0)) * ld);
+  const int64_t ntasks = ld / kWave;
+  const int64_t grid = wide_grid(ntasks);
+  const size_t o_bnd = band ? 0 : pl.add(sizeof(float) * grid * (lcol + 1) * kWave);
+  int rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
+  HIPCHK(launch_transpose_pad(X, npairs, (int)lrow, ld, 0, 0.0f, at<float>(ctx, o_rows), st));
+  HIPCHK(launch_transpose_pad(Y, npairs, (int)lcol, ld, band ? kColPad : 0, INFINITY,
+                              at<float>(ctx, o_cols), st));
+  if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
+  if (band) {
+    PairArgs a{};
+    a.rowsT = at<float>(ctx, o_rows);
+    a.colsT = at<float>(ctx, o_cols);
+    a.ld = ld;
+    a.npairs = npairs;
+    a.lrow = (int)lrow;
+    a.lcol = (int)lcol;
+    a.ub_mode = ub_mode;
+    a.ub = ub;
+    a.ub_scalar = ub_scalar;
+    a.out = out;
+    a.ckpt = ckpt;
+    a.ckpt_every = ckpt_every;
+    a.counters = cnt;
+    HIPCHK(pair_band_launcher((int)r)(a, ntasks, pick_rows(ctx, (int)r), st));
+  } else {
+    if (ckpt) return fail(ctx, EAPDTW_EINVAL, "checkpoints need a window of at most 64");
+    WideArgs w{};
+    w.lrow = (int)lrow;
+    w.lcol = (int)lcol;
+    w.r = (int)r;
+    w.RT = at<float>(ctx, o_rows);
+    w.XT = at<float>(ctx, o_cols);
+    w.N = npairs;
+    w.ld = ld;
+    w.ub_mode = ub_mode;
+    w.ub = ub;
+    w.ub_scalar = ub_scalar;
+    w.out = out;
+    w.ntasks = ntasks;
+    w.bnd = at<float>(ctx, o_bnd);
+    w.bnd_stride = (lcol + 1) * kWave;
+    w.counters = cnt;
+    w.check_interval = 1;
+    HIPCHK(launch_wide(kWidePairs, 0, w, (int)grid, st));
+  }
+  if (stats) {
+    HIPCHK(hipEventRecord(ctx->ev3, st));
+    HIPCHK(hipEventRecord(ctx->ev1, st));
+    rc = readback(ctx, o_cnt, kCntBytes);
+    if (rc) return rc;
+    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned),
+               (uint64_t)(band_cells_total(lrow, lcol, r) * npairs), (uint64_t)npairs,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+  }
   return EAPDTW_OK;
 }
 
@@ -286,46 +403,23 @@ int eapdtw_dtw(eapdtw_ctx *ctx, const float *S, int64_t lS, const float *T, int6
   }
   const int64_t lmax = lS > lT ? lS : lT;
   const int64_t r = window < lmax - 1 ? window : lmax - 1;
-  PairLaunchFn fn = pair_band_launcher((int)r);
-  if (!fn) return fail(ctx, EAPDTW_EINVAL, "window wider than the band kernels (wide-window path not built yet)");
-  const int64_t ld = kWave;
+  HIPCHK(hipSetDevice(ctx->device));
+  // the single result is written into a scratch word placed after the engine's buffers
   Plan pl;
-  size_t o_rows = pl.add(sizeof(float) * lS * ld);
-  size_t o_cols = pl.add(sizeof(float) * (lT + 2 * kColPad) * ld);
-  size_t o_out = pl.add(sizeof(float) * ld);
-  size_t o_cnt = pl.add(sizeof(unsigned long long) * kCntSlots);
+  pl.add(kCntBytes);
+  const int64_t ld = kWave;
+  pl.add(sizeof(float) * lS * ld);
+  pl.add(sizeof(float) * (lT + 2 * kColPad) * ld);
+  if (!use_band(ctx, r)) pl.add(sizeof(float) * 1 * (lT + 1) * kWave);
+  const size_t o_out = pl.add(sizeof(float));
   int rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
-  HIPCHK(hipSetDevice(ctx->device));
-  hipStream_t st = ctx->stream;
-  HIPCHK(hipEventRecord(ctx->ev0, st));
-  HIPCHK(launch_fill_u64(at<unsigned long long>(ctx, o_cnt), 0ull, kCntSlots, st));
-  HIPCHK(launch_transpose_pad(S, 1, (int)lS, ld, 0, 0.0f, at<float>(ctx, o_rows), st));
-  HIPCHK(launch_transpose_pad(T, 1, (int)lT, ld, kColPad, INFINITY, at<float>(ctx, o_cols), st));
-  PairArgs a{};
-  a.rowsT = at<float>(ctx, o_rows);
-  a.colsT = at<float>(ctx, o_cols);
-  a.ld = ld;
-  a.npairs = 1;
-  a.lrow = (int)lS;
-  a.lcol = (int)lT;
-  a.ub_mode = 3;
-  a.ub_scalar = bound_down(ub);
-  a.out = at<float>(ctx, o_out);
-  a.counters = at<unsigned long long>(ctx, o_cnt);
-  HIPCHK(fn(a, 1, pick_rows(ctx, (int)r), st));
-  HIPCHK(hipEventRecord(ctx->ev1, st));
-  // out (one float) and the counters are read back together
-  rc = readback(ctx, o_out, (o_cnt - o_out) + sizeof(unsigned long long) * kCntSlots);
+  rc = pairs_engine(ctx, S, T, 1, lS, lT, r, 3, nullptr, bound_down(ub), at<float>(ctx, o_out),
+                    nullptr, 0, stats);
   if (rc) return rc;
-  const float d = *reinterpret_cast<float *>(ctx->pinned);
-  *out_dist = (double)d;
-  if (stats) {
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned + (o_cnt - o_out)),
-               (uint64_t)band_cells_total(lS, lT, r), 1, ms);
-  }
+  rc = readback(ctx, o_out, sizeof(float));
+  if (rc) return rc;
+  *out_dist = (double)*reinterpret_cast<float *>(ctx->pinned);
   return EAPDTW_OK;
 }
 
@@ -343,49 +437,13 @@ static int pairs_common(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
   if (stats) std::memset(stats, 0, sizeof *stats);
   if (npairs == 0) return EAPDTW_OK;
   HIPCHK(hipSetDevice(ctx->device));
-  hipStream_t st = ctx->stream;
   if (len == 0) {
-    HIPCHK(launch_fill_f32(out, 0.0f, npairs, st));
+    HIPCHK(launch_fill_f32(out, 0.0f, npairs, ctx->stream));
     return EAPDTW_OK;
   }
   const int64_t r = window < len - 1 ? window : len - 1;
-  PairLaunchFn fn = pair_band_launcher((int)r);
-  if (!fn) return fail(ctx, EAPDTW_EINVAL, "window wider than the band kernels (wide-window path not built yet)");
-  const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
-  Plan pl;
-  size_t o_rows = pl.add(sizeof(float) * len * ld);
-  size_t o_cols = pl.add(sizeof(float) * (len + 2 * kColPad) * ld);
-  size_t o_cnt = pl.add(sizeof(unsigned long long) * kCntSlots);
-  int rc = ensure_scratch(ctx, pl.off);
-  if (rc) return rc;
-  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
-  HIPCHK(launch_fill_u64(at<unsigned long long>(ctx, o_cnt), 0ull, kCntSlots, st));
-  HIPCHK(launch_transpose_pad(X, npairs, (int)len, ld, 0, 0.0f, at<float>(ctx, o_rows), st));
-  HIPCHK(launch_transpose_pad(Y, npairs, (int)len, ld, kColPad, INFINITY, at<float>(ctx, o_cols), st));
-  PairArgs a{};
-  a.rowsT = at<float>(ctx, o_rows);
-  a.colsT = at<float>(ctx, o_cols);
-  a.ld = ld;
-  a.npairs = npairs;
-  a.lrow = (int)len;
-  a.lcol = (int)len;
-  a.ub_mode = ub_mode;
-  a.ub = ub;
-  a.out = out;
-  a.ckpt = ckpt;
-  a.ckpt_every = ckpt_every;
-  a.counters = at<unsigned long long>(ctx, o_cnt);
-  HIPCHK(fn(a, ld / kWave, pick_rows(ctx, (int)r), st));
-  if (stats) {
-    HIPCHK(hipEventRecord(ctx->ev1, st));
-    rc = readback(ctx, o_cnt, sizeof(unsigned long long) * kCntSlots);
-    if (rc) return rc;
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned),
-               (uint64_t)(band_cells_total(len, len, r) * npairs), (uint64_t)npairs, ms);
-  }
-  return EAPDTW_OK;
+  return pairs_engine(ctx, X, Y, npairs, len, len, r, ub_mode, ub, 0.0f, out, ckpt, ckpt_every,
+                      stats);
 }
 
 int eapdtw_dtw_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs, int64_t len,
@@ -397,15 +455,65 @@ int eapdtw_dtw_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t np
 int eapdtw_pairwise(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t window,
                     float *out_D, eapdtw_stats *stats) {
   CHECK_CTX();
-  (void)X; (void)N; (void)len; (void)window; (void)out_D; (void)stats;
-  return fail(ctx, EAPDTW_EINVAL, "pairwise: not built yet");
+  if (N < 0 || len < 0) return fail(ctx, EAPDTW_EINVAL, "negative size");
+  if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
+  if (N > 1 && (!X || !out_D)) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
+  if (len > INT_MAX / 2 || N > (int64_t)1 << 31) return fail(ctx, EAPDTW_EINVAL, "too large");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (N < 2) return EAPDTW_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int64_t npairs = N * (N - 1) / 2;
+  if (len == 0) {
+    HIPCHK(launch_fill_f32(out_D, 0.0f, npairs, st));
+    return EAPDTW_OK;
+  }
+  const int64_t r = window < len - 1 ? window : len - 1;
+  const int64_t ldN = (N + kWave - 1) / kWave * kWave;
+  const int64_t nblk_j = ldN / kWave;
+  const int64_t ntasks = N * nblk_j;
+  const int64_t grid = wide_grid(ntasks);
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_xt = pl.add(sizeof(float) * len * ldN);
+  const size_t o_bnd = pl.add(sizeof(float) * grid * (len + 1) * kWave);
+  int rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
+  HIPCHK(launch_transpose_pad(X, N, (int)len, ldN, 0, 0.0f, at<float>(ctx, o_xt), st));
+  WideArgs w{};
+  w.lrow = (int)len;
+  w.lcol = (int)len;
+  w.r = (int)r;
+  w.X = X;
+  w.XT = at<float>(ctx, o_xt);
+  w.N = N;
+  w.ld = ldN;
+  w.nblk_j = nblk_j;
+  w.ub_mode = 2;
+  w.out = out_D;
+  w.ntasks = ntasks;
+  w.bnd = at<float>(ctx, o_bnd);
+  w.bnd_stride = (len + 1) * kWave;
+  w.counters = cnt;
+  w.check_interval = 1;
+  if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
+  HIPCHK(launch_wide(kWidePairwise, 0, w, (int)grid, st));
+  if (stats) {
+    HIPCHK(hipEventRecord(ctx->ev3, st));
+    HIPCHK(hipEventRecord(ctx->ev1, st));
+    rc = readback(ctx, o_cnt, kCntBytes);
+    if (rc) return rc;
+    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned),
+               (uint64_t)(band_cells_total(len, len, r) * npairs), (uint64_t)npairs,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+  }
+  return EAPDTW_OK;
 }
 
 // --------------------------------------------------------------------------- search
-
-struct SearchBufs {
-  size_t o_q, o_bsf, o_cnt, o_dists;
-};
 
 static int search_validate(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                            int64_t n, int64_t window) {
@@ -418,6 +526,82 @@ static int search_validate(eapdtw_ctx *ctx, const float *query, int64_t m, const
   return EAPDTW_OK;
 }
 
+// Queues the search of one query: query normalisation into qpad, bound
+// seeding, and the DP pass over offsets [0, n-m].  dists != nullptr selects the
+// per-candidate mode against fixed_ub (no best-so-far).  bsf points at two
+// words (search, seeding pass); cnt at cleared counters.
+static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                        int64_t n, int64_t r, float *qpad, unsigned long long *bsf,
+                        unsigned long long *cnt, float *dists, float fixed_ub, float *bnd,
+                        int64_t bnd_waves, bool time_main) {
+  hipStream_t st = ctx->stream;
+  const int64_t K = n - m + 1;
+  const int64_t nblk = (K + kWave - 1) / kWave;
+  HIPCHK(launch_query_prep(query, (int)m, qpad, cnt, st));
+  if (!dists) HIPCHK(launch_check_finite(series, n, cnt, st));
+  NNArgs a{};
+  a.x = series;
+  a.n = n;
+  a.m = (int)m;
+  a.qpad = qpad;
+  a.k_begin = 0;
+  a.k_end = K;
+  a.check_interval = (int)ctx->check_interval;
+  a.block_stride = 1;
+  if (!dists && ctx->seed && r > 0) {
+    // Bound seeding.  A candidate's DTW under a narrower window is never below
+    // its DTW under the search window (fewer admissible paths), so
+    //  1. the window-0 (squared Euclidean) pass over every seed_stride-th
+    //     block of candidates yields a valid distance bound and an offset;
+    //  2. one workgroup of candidates around that offset, under window
+    //     min(r, seed_window), tightens it.
+    // Both record distance-only bounds; the search itself then finds the
+    // exact minimum and its offset (the true minimum is never abandoned).
+    const int64_t sstr = ctx->seed_stride;
+    NNArgs e = a;
+    e.bsf = bsf + 1;
+    e.block_stride = (int)sstr;
+    HIPCHK(nn_band_launcher(0)(e, (nblk + sstr - 1) / sstr, 8, false, st));
+    const int64_t rs = r < ctx->seed_window ? r : ctx->seed_window;
+    NNArgs s = a;
+    s.bsf = bsf;
+    s.center = bsf + 1;
+    s.bsf_init = bsf + 1;
+    s.bound_only = 1;
+    HIPCHK(nn_band_launcher((int)rs)(s, 1, pick_rows(ctx, (int)rs), false, st));
+  }
+  if (time_main) HIPCHK(hipEventRecord(ctx->ev2, st));
+  if (use_band(ctx, r)) {
+    a.bsf = bsf;
+    a.counters = cnt;
+    a.fixed_ub = fixed_ub;
+    a.dists = dists;
+    HIPCHK(nn_band_launcher((int)r)(a, nblk, dists ? 4 : pick_rows(ctx, (int)r), dists != nullptr, st));
+  } else {
+    WideArgs w{};
+    w.lrow = (int)m;
+    w.lcol = (int)m;
+    w.r = (int)r;
+    w.x = series;
+    w.n = n;
+    w.qpad = qpad;
+    w.bsf = bsf;
+    w.k_begin = 0;
+    w.k_end = K;
+    w.fixed_ub = fixed_ub;
+    w.dists = dists;
+    w.dists_mode = dists != nullptr;
+    w.ntasks = nblk;
+    w.bnd = bnd;
+    w.bnd_stride = (m + 1) * kWave;
+    w.counters = cnt;
+    w.check_interval = (int)ctx->check_interval;
+    HIPCHK(launch_wide(kWideSearch, 0, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
+  }
+  if (time_main) HIPCHK(hipEventRecord(ctx->ev3, st));
+  return EAPDTW_OK;
+}
+
 int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                      int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
                      eapdtw_stats *stats) {
@@ -427,14 +611,13 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
   if (rc) return rc;
   if (stats) std::memset(stats, 0, sizeof *stats);
   const int64_t r = window < m - 1 ? window : m - 1;
-  NNLaunchFn fn = nn_band_launcher((int)r);
-  if (!fn) return fail(ctx, EAPDTW_EINVAL, "window wider than the band kernels (wide-window path not built yet)");
-  NNLaunchFn fn0 = nn_band_launcher(0);
   const int64_t K = n - m + 1;
+  const int64_t grid = use_band(ctx, r) ? 0 : wide_grid((K + kWave - 1) / kWave);
   Plan pl;
-  size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);  // [0] search, [1] window-0 pass
-  size_t o_cnt = pl.add(sizeof(unsigned long long) * kCntSlots);
-  size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);  // [0] search, [1] seeding pass
+  const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
@@ -442,50 +625,23 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
   unsigned long long *bsf = at<unsigned long long>(ctx, o_bsf);
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
   if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
   HIPCHK(launch_fill_u64(bsf, pack_best(INFINITY, 0xffffffffu), 2, st));
-  HIPCHK(launch_fill_u64(cnt, 0ull, kCntSlots, st));
-  HIPCHK(launch_query_prep(query, (int)m, at<float>(ctx, o_q), cnt, st));
-  HIPCHK(launch_check_finite(series, n, cnt, st));
-  NNArgs a{};
-  a.x = series;
-  a.n = n;
-  a.m = (int)m;
-  a.qpad = at<float>(ctx, o_q);
-  a.k_begin = 0;
-  a.k_end = K;
-  a.check_interval = (int)ctx->check_interval;
-  const int64_t nblk = (K + kWave - 1) / kWave;
-  if (ctx->seed && r > 0) {
-    // bound seeding: the window-0 distance (squared Euclidean) of any
-    // candidate bounds its DTW, so the best window-0 candidate gives a valid
-    // starting bound; one workgroup of candidates around it tightens it.
-    NNArgs e = a;
-    e.bsf = bsf + 1;
-    e.counters = nullptr;
-    HIPCHK(fn0(e, nblk, 8, false, st));
-    NNArgs s = a;
-    s.bsf = bsf;
-    s.center = bsf + 1;
-    s.bsf_init = bsf + 1;
-    s.counters = nullptr;
-    HIPCHK(fn(s, 1, pick_rows(ctx, (int)r), false, st));
-  }
-  a.bsf = bsf;
-  a.counters = cnt;
-  HIPCHK(fn(a, nblk, pick_rows(ctx, (int)r), false, st));
-  if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
-  rc = readback(ctx, o_bsf, (o_cnt - o_bsf) + sizeof(unsigned long long) * kCntSlots);
+  rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr);
   if (rc) return rc;
-  const unsigned long long best = *reinterpret_cast<unsigned long long *>(ctx->pinned);
-  const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned + (o_cnt - o_bsf));
-  if (hc[kCntNonFinite]) return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
+  if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
+  // counters and the two best-so-far words are contiguous
+  rc = readback(ctx, o_cnt, o_bsf + 2 * sizeof(unsigned long long) - o_cnt);
+  if (rc) return rc;
+  const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned);
+  const unsigned long long best = *reinterpret_cast<unsigned long long *>(ctx->pinned + (o_bsf - o_cnt));
+  if (counter_sum(hc, kCntNonFinite)) return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
   *out_offset = best_offset(best) == 0xffffffffu ? -1 : (int64_t)best_offset(best);
   *out_dist = (double)best_dist(best);
-  if (stats) {
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K, ms);
-  }
+  if (stats)
+    fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
   return EAPDTW_OK;
 }
 
@@ -498,40 +654,31 @@ int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
   if (rc) return rc;
   if (stats) std::memset(stats, 0, sizeof *stats);
   const int64_t r = window < m - 1 ? window : m - 1;
-  NNLaunchFn fn = nn_band_launcher((int)r);
-  if (!fn) return fail(ctx, EAPDTW_EINVAL, "window wider than the band kernels (wide-window path not built yet)");
   const int64_t K = n - m + 1;
+  const int64_t grid = use_band(ctx, r) ? 0 : wide_grid((K + kWave - 1) / kWave);
   Plan pl;
-  size_t o_cnt = pl.add(sizeof(unsigned long long) * kCntSlots);
-  size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
+  const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
   if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
-  HIPCHK(launch_fill_u64(cnt, 0ull, kCntSlots, st));
-  HIPCHK(launch_query_prep(query, (int)m, at<float>(ctx, o_q), cnt, st));
-  NNArgs a{};
-  a.x = series;
-  a.n = n;
-  a.m = (int)m;
-  a.qpad = at<float>(ctx, o_q);
-  a.k_begin = 0;
-  a.k_end = K;
-  a.fixed_ub = ub;
-  a.dists = out;
-  a.counters = cnt;
-  a.check_interval = 1;
-  HIPCHK(fn(a, (K + kWave - 1) / kWave, 4, true, st));
+  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
+  rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q),
+                    at<unsigned long long>(ctx, o_bsf), cnt, out, ub,
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr);
+  if (rc) return rc;
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev1, st));
-    rc = readback(ctx, o_cnt, sizeof(unsigned long long) * kCntSlots);
+    rc = readback(ctx, o_cnt, kCntBytes);
     if (rc) return rc;
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
     fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned),
-               (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K, ms);
+               (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
   }
   return EAPDTW_OK;
 }

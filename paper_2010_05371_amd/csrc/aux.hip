@@ -79,7 +79,7 @@ __global__ void check_finite_kernel(const float *__restrict__ x, int64_t n,
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     bad += not_finite(x[i]);
-  if (bad) atomicAdd(&counters[kCntNonFinite], (unsigned long long)bad);
+  if (bad) atomicAdd(&counter_stripe(counters, blockIdx.x)[kCntNonFinite], (unsigned long long)bad);
 }
 
 __global__ void fill_f32_kernel(float *p, float v, int64_t n) {

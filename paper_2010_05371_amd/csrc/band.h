@@ -219,7 +219,7 @@ __global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
     kbeg = lo;
     if (a.bsf_init && lane == 0) atomicMin(a.bsf, pack_best(best_dist(*a.bsf_init), 0xffffffffu));
   }
-  const int64_t kb = kbeg + (int64_t)blockIdx.x * kWave;
+  const int64_t kb = kbeg + (int64_t)blockIdx.x * kWave * (a.block_stride > 1 ? a.block_stride : 1);
   if (kb >= kend) return;
   const int64_t k = kb + lane;
   const bool active = k < kend;
@@ -285,14 +285,15 @@ __global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
   if (DISTS) {
     if (active) a.dists[k - a.k_begin] = keep ? d : kInf;
   } else if (keep) {
-    atomicMin(a.bsf, pack_best(d, (uint32_t)k));
+    atomicMin(a.bsf, pack_best(d, a.bound_only ? 0xffffffffu : (uint32_t)k));
   }
   if (a.counters) {
     const uint64_t aband = (uint64_t)__popcll(__ballot(active && !keep));
     if (lane == 0) {
-      atomicAdd(&a.counters[kCntEvaluated], (unsigned long long)evaluated);
-      atomicAdd(&a.counters[kCntComputed], (unsigned long long)computed);
-      atomicAdd(&a.counters[kCntAbandoned], (unsigned long long)aband);
+      unsigned long long *c = counter_stripe(a.counters, blockIdx.x);
+      atomicAdd(&c[kCntEvaluated], (unsigned long long)evaluated);
+      atomicAdd(&c[kCntComputed], (unsigned long long)computed);
+      atomicAdd(&c[kCntAbandoned], (unsigned long long)aband);
     }
   }
 }
@@ -389,9 +390,10 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
   if (a.counters) {
     const uint64_t aband = (uint64_t)__popcll(__ballot(active && !keep));
     if (lane == 0) {
-      atomicAdd(&a.counters[kCntEvaluated], (unsigned long long)evaluated);
-      atomicAdd(&a.counters[kCntComputed], (unsigned long long)computed);
-      atomicAdd(&a.counters[kCntAbandoned], (unsigned long long)aband);
+      unsigned long long *c = counter_stripe(a.counters, blockIdx.x);
+      atomicAdd(&c[kCntEvaluated], (unsigned long long)evaluated);
+      atomicAdd(&c[kCntComputed], (unsigned long long)computed);
+      atomicAdd(&c[kCntAbandoned], (unsigned long long)aband);
     }
   }
 }

@@ -15,8 +15,15 @@ constexpr int kBandRMax = 64;
 // columns hold +inf so that their cells evaluate to +inf.  Twice the largest
 // band window, because a row-longer-than-column pair reaches 2r past the end.
 constexpr int kColPad = 2 * kBandRMax + 16;
+// Tile heights of the wide-window kernels (banded / whole-matrix windows).
+constexpr int kWideBandRows = 16;
+constexpr int kWideFullRows = 64;
 
-// Counter slots written by the kernels (device u64 array).
+// Counter slots written by the kernels.  The device array holds kCntStripes
+// copies kCntStride words apart (one 128-byte line each); a workgroup adds
+// into stripe blockIdx % kCntStripes so that the end-of-wave atomics of tens
+// of thousands of workgroups do not serialise on one address.  The host sums
+// the stripes.
 enum Counter : int {
   kCntEvaluated = 0,  // cells computed for problems still alive
   kCntComputed = 1,   // all lane-cells computed
@@ -24,6 +31,13 @@ enum Counter : int {
   kCntNonFinite = 3,  // non-finite input values seen
   kCntSlots = 8
 };
+constexpr int kCntStripes = 64;
+constexpr int kCntStride = 16;
+constexpr int kCntWords = kCntStripes * kCntStride;
+
+__host__ __device__ inline unsigned long long *counter_stripe(unsigned long long *c, unsigned b) {
+  return c + (b % kCntStripes) * kCntStride;
+}
 
 // The shared best-so-far of a search packs (distance, offset) into one u64 so
 // that a single 64-bit atomic min keeps the lexicographic minimum: distances
@@ -48,8 +62,10 @@ struct NNArgs {
   const unsigned long long *bsf_init;// optional: seed bsf (distance part) from this word first
   float fixed_ub;                    // per-candidate-distance mode: fixed bound
   float *dists;                      // per-candidate-distance mode: out[k - k_begin]
-  unsigned long long *counters;      // kCntSlots (nullable)
+  unsigned long long *counters;      // kCntWords (nullable)
   int check_interval;                // row groups between best-so-far reloads
+  int block_stride;                  // workgroup b covers offsets from k_begin + 64 b stride
+  int bound_only;                    // record distance-only bounds (offset field all ones)
 };
 
 // Arguments of the pair band kernel.  Row and column series are stored

@@ -13,6 +13,12 @@ typedef hipError_t (*PairLaunchFn)(const PairArgs &, int64_t nblocks, int rows_p
 NNLaunchFn nn_band_launcher(int r);
 PairLaunchFn pair_band_launcher(int r);
 
+// Wide-window kernels (wide_inst.hip): kind is a WideKind, rows the tile height
+// (16, 32 or 64), grid the number of persistent single-wave workgroups.
+struct WideArgs;
+hipError_t launch_wide(int kind, int rows, const WideArgs &a, int grid, hipStream_t st);
+int wide_rows_for(int r, int lrow, int lcol);
+
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
 hipError_t launch_query_prep(const float *q, int m, float *qpad, unsigned long long *counters,

@@ -1,0 +1,371 @@
+// wide.h -- tiled DTW kernels for windows wider than the register band
+// (kBandRMax < r, including unconstrained DTW), gfx950.
+//
+// One SIMD lane owns one problem.  The matrix is cut into tiles of H rows;
+// a tile is swept column by column (column j holds cells (i0+h, j), h < H, in
+// H VGPRs), so every cell reads
+//   left (i, j-1)   -> the same register before the column update,
+//   top  (i-1, j)   -> the register of row h-1 just updated,
+//   diag (i-1, j-1) -> the register of row h-1 before the update,
+// and row 0 of a tile reads the last row of the tile above from a per-wave
+// boundary row kept in global memory ([column][lane], coalesced).
+// The Sakoe-Chiba band (Section 2.1) makes each tile a parallelogram: an
+// entering triangle of H columns where rows join the band one per column, a
+// middle stretch where all H rows are admissible and an exiting triangle where
+// rows leave it.  The triangles are unrolled statically so that out-of-band
+// cells are never computed and read as +inf.
+//
+// Pruning (Section 4 recast per tile and wave): the sweep of a tile starts at
+// the first column where the row above had a live cell (<= ub) in any lane --
+// columns to its left are dead in every later row (left border) -- and, past
+// the last column where the row above was live, stops after the first column
+// whose H cells are all dead in every lane (right border: from there on a
+// cell can only depend on its dead left neighbour).  A lane whose tile ended
+// without a live cell in its last row is dead; a wave whose lanes are all dead
+// stops (early abandoning, Section 2.2).
+#pragma once
+#include "band.h"
+
+namespace eapdtw {
+
+// Kinds of problem a wide wave can own.
+enum WideKind : int {
+  kWideSearch = 0,   // rows: z-normalised candidate (per lane); columns: query (uniform)
+  kWidePairwise = 1, // rows: X[i] (uniform); columns: X[j] (per lane), i < j
+  kWidePairs = 2,    // rows and columns per lane from transposed copies
+};
+
+struct WideArgs {
+  int lrow, lcol, r;
+  // search
+  const float *x;
+  int64_t n;
+  const float *qpad;                 // z(query), kColPad +inf on each side
+  unsigned long long *bsf;
+  int64_t k_begin, k_end;
+  float fixed_ub;                    // per-candidate-distance mode
+  float *dists;
+  int dists_mode;
+  int bound_only;
+  // pairwise / pairs
+  const float *X;                    // pairwise: rows X [N][len]
+  const float *XT;                   // pairwise: X transposed [len][ldN]; pairs: columns [lcol][ld]
+  const float *RT;                   // pairs: rows transposed [lrow][ld]
+  int64_t N, ld;
+  int64_t nblk_j;                    // pairwise: column blocks per row series
+  int ub_mode;                       // pairs: 0 none, 1 array, 2 ED; pairwise: ED
+  const float *ub;
+  float ub_scalar;
+  float *out;
+  // common
+  int64_t ntasks;
+  float *bnd;                        // boundary rows: [gridDim.x][lcol + 1][64]
+  int64_t bnd_stride;                // floats per wave
+  unsigned long long *counters;
+  int check_interval;
+};
+
+// Column value access per kind, for the lane's problem.
+struct WideProblem {
+  // rows
+  const float *xk;      // search: candidate start (per lane)
+  float mu_hi, mu_lo, inv;
+  const float *rowp;    // pairwise: row series (uniform); pairs: rows transposed + p
+  // columns
+  const float *colp;    // pairwise/pairs: column series transposed + lane offset
+  int64_t cstride;
+  float ub;
+  bool active;
+  float ed;
+};
+
+template <int KIND>
+__device__ __forceinline__ float wide_row_value(const WideArgs &a, const WideProblem &p, int i) {
+  if (i >= a.lrow) return kInf;  // rows past the end: every cell +inf
+  if (KIND == kWideSearch) return znorm_value(p.xk[i], p.mu_hi, p.mu_lo, p.inv);
+  if (KIND == kWidePairwise) return p.rowp[i];  // uniform address; kept in VGPRs
+  return p.rowp[(int64_t)i * a.ld];
+}
+
+template <int KIND>
+__device__ __forceinline__ float wide_col_value(const WideArgs &a, const WideProblem &p, int j) {
+  if (KIND == kWideSearch) return as_const(a.qpad + kColPad)[j];
+  return p.colp[(int64_t)j * p.cstride];
+}
+
+// Computes column j of the tile for rows [h_lo, h_hi] (static); rows above
+// h_lo read +inf as their top neighbour (out of band), rows below h_hi are not
+// computed and are forced to +inf when FORCE_BELOW.
+template <int H, int H_LO, int H_HI, bool FORCE_BELOW>
+__device__ __forceinline__ void wide_column(float (&col)[H], const float (&rv)[H], float cv,
+                                            float top0, float diag0) {
+  float up = (H_LO == 0) ? top0 : kInf;
+  float dg = (H_LO == 0) ? diag0 : col[H_LO > 0 ? H_LO - 1 : 0];
+  if (H_LO > 0) dg = col[H_LO - 1];
+#pragma unroll
+  for (int h = H_LO; h <= H_HI; ++h) {
+    const float left = col[h];
+    const float diff = cv - rv[h];
+    const float nv = __builtin_fmaf(diff, diff, fmin3(left, up, dg));
+    dg = left;
+    up = nv;
+    col[h] = nv;
+  }
+  if (FORCE_BELOW && H_HI + 1 < H) col[H_HI + 1 < H ? H_HI + 1 : 0] = kInf;
+}
+
+template <int H>
+__device__ __forceinline__ float col_min(const float (&col)[H]) {
+  float m = col[0];
+#pragma unroll
+  for (int h = 1; h < H; ++h) m = fminf(m, col[h]);
+  return m;
+}
+
+}  // namespace eapdtw
+
+namespace eapdtw {
+
+// Per-column bookkeeping state of one tile sweep.
+struct Sweep {
+  int j;              // next column
+  int jend;           // last column the tile may reach
+  int jmand;          // columns up to here may still be reached from the tile above
+  int first_live, last_live;
+  unsigned long long lane_live;
+  bool go;
+  float diag0;        // (i0-1, j-1)
+  int bv_lo, bv_hi;   // boundary columns valid from the tile above
+  int t;              // tile index
+  int64_t rows;       // admissible rows of the tile (<= H, last tile may be shorter)
+  uint64_t evaluated, computed;
+  unsigned long long alive_mask;
+};
+
+template <int H, int KIND, int H_LO, int H_HI>
+__device__ __forceinline__ void wide_step(const WideArgs &a, const WideProblem &p, float *Bw,
+                                          int lane, float (&col)[H], const float (&rv)[H],
+                                          Sweep &s, float ub, int tlast, int hans, float &ans) {
+  const int j = s.j;
+  const bool have_top = s.t > 0 && j >= s.bv_lo && j <= s.bv_hi;
+  const float top0 = have_top ? Bw[(int64_t)(j + 1) * kWave + lane] : kInf;
+  const float cv = wide_col_value<KIND>(a, p, j);
+  wide_column<H, H_LO, H_HI, false>(col, rv, cv, top0, s.diag0);
+  s.diag0 = top0;
+  Bw[(int64_t)(j + 1) * kWave + lane] = col[H - 1];
+  const bool lane_alive = (s.alive_mask >> lane) & 1ull;
+  const unsigned long long lm = __ballot(lane_alive && col[H - 1] <= ub);
+  if (lm) {
+    if (s.first_live > j) s.first_live = j;
+    s.last_live = j;
+    s.lane_live |= lm;
+  }
+  if (s.t == tlast && j == a.lcol - 1) {
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+      if (h == hans) ans = col[h];
+  }
+  // admissible cells of this column inside the matrix
+  int hl = H_LO, hh = H_HI;
+  if (hh > s.rows - 1) hh = (int)s.rows - 1;
+  const int nc = hh >= hl ? hh - hl + 1 : 0;
+  s.computed += (uint64_t)nc * kWave;
+  s.evaluated += (uint64_t)nc * (uint64_t)__popcll(s.alive_mask);
+  // right border: past the columns reachable from the tile above, stop after a
+  // column whose cells are all dead in every lane
+  if (j > s.jmand && ((j - s.jmand) & 3) == 0) {
+    if (!wave_any(lane_alive && col_min<H>(col) <= ub)) s.go = false;
+  }
+  s.j = j + 1;
+  if (s.j > s.jend) s.go = false;
+}
+
+// entering triangle: column c = j - (i0 - r) has rows 0..c admissible
+template <int H, int KIND, int C>
+struct EnterPhase {
+  __device__ __forceinline__ static void run(const WideArgs &a, const WideProblem &p, float *Bw,
+                                             int lane, float (&col)[H], const float (&rv)[H],
+                                             Sweep &s, float ub, int tlast, int hans, float &ans,
+                                             int jbase) {
+    if (s.go && s.j == jbase + C) wide_step<H, KIND, 0, C>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+    EnterPhase<H, KIND, C + 1>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, jbase);
+  }
+};
+template <int H, int KIND>
+struct EnterPhase<H, KIND, H - 1> {
+  __device__ __forceinline__ static void run(const WideArgs &, const WideProblem &, float *, int,
+                                             float (&)[H], const float (&)[H], Sweep &, float, int,
+                                             int, float &, int) {}
+};
+
+// exiting triangle: column c = j - (i0 + r + 1) has rows c+1..H-1 admissible
+template <int H, int KIND, int C>
+struct ExitPhase {
+  __device__ __forceinline__ static void run(const WideArgs &a, const WideProblem &p, float *Bw,
+                                             int lane, float (&col)[H], const float (&rv)[H],
+                                             Sweep &s, float ub, int tlast, int hans, float &ans,
+                                             int jbase) {
+    if (s.go && s.j == jbase + C) wide_step<H, KIND, C + 1, H - 1>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+    ExitPhase<H, KIND, C + 1>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, jbase);
+  }
+};
+template <int H, int KIND>
+struct ExitPhase<H, KIND, H - 1> {
+  __device__ __forceinline__ static void run(const WideArgs &, const WideProblem &, float *, int,
+                                             float (&)[H], const float (&)[H], Sweep &, float, int,
+                                             int, float &, int) {}
+};
+
+// One problem per lane: all tiles.  Returns the lane's result (+inf if the
+// distance exceeds the bound); accumulates the work counters.
+template <int H, int KIND, bool BANDED>
+__device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p, float *Bw, int lane,
+                                              uint64_t &evaluated, uint64_t &computed) {
+  const int r = a.r, lrow = a.lrow, lcol = a.lcol;
+  const int ntiles = (lrow + H - 1) / H;
+  const int tlast = ntiles - 1;
+  const int hans = (lrow - 1) - tlast * H;
+  float ub = p.ub;
+  bool alive = p.active && ub >= 0.0f;
+  bool stopped = !wave_any(alive);
+  int lo = 0, hi = -1;       // live columns of the row above the tile (border row: origin)
+  int bv_lo = 0, bv_hi = -1;
+  float ans = kInf;
+  int since = 0;
+  for (int t = 0; t < ntiles && !stopped; ++t) {
+    const int i0 = t * H;
+    float rv[H], col[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      rv[h] = wide_row_value<KIND>(a, p, i0 + h);
+      col[h] = kInf;
+    }
+    const int jb_lo = i0 - r > 0 ? i0 - r : 0;
+    const int jb_hi = i0 + H - 1 + r < lcol - 1 ? i0 + H - 1 + r : lcol - 1;
+    Sweep s;
+    s.j = jb_lo > lo ? jb_lo : lo;
+    s.jend = jb_hi;
+    s.jmand = hi + 1;
+    s.first_live = 0x7fffffff;
+    s.last_live = -1;
+    s.lane_live = 0ull;
+    s.go = s.j <= s.jend;
+    s.bv_lo = bv_lo;
+    s.bv_hi = bv_hi;
+    s.t = t;
+    s.rows = lrow - i0 < H ? lrow - i0 : H;
+    s.evaluated = 0;
+    s.computed = 0;
+    s.alive_mask = __ballot(alive);
+    if (t == 0) s.diag0 = (s.j == 0) ? 0.0f : kInf;
+    else s.diag0 = (s.j - 1 >= bv_lo && s.j - 1 <= bv_hi) ? Bw[(int64_t)s.j * kWave + lane] : kInf;
+    const int jstart = s.j;
+    // entering triangle [i0-r, i0-r+H-2], full columns up to i0+r, exiting triangle
+    if (BANDED) {
+      EnterPhase<H, KIND, 0>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 - r);
+      while (s.go && s.j <= i0 + r) wide_step<H, KIND, 0, H - 1>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+      ExitPhase<H, KIND, 0>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 + r + 1);
+    } else {
+      // the window covers the whole matrix: every column is a full column
+      while (s.go) wide_step<H, KIND, 0, H - 1>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+    }
+    evaluated += s.evaluated;
+    computed += s.computed;
+    bv_lo = jstart;
+    bv_hi = s.j - 1;
+    if (t == tlast) break;  // the answer cell was captured during the sweep
+    alive = alive && ((s.lane_live >> lane) & 1ull);
+    if (s.last_live < 0 || !wave_any(alive)) {
+      stopped = true;
+      break;
+    }
+    lo = s.first_live;
+    hi = s.last_live;
+    if (KIND == kWideSearch && !a.dists_mode && ++since >= a.check_interval) {
+      since = 0;
+      ub = fminf(ub, load_bsf_dist(a.bsf));
+    }
+  }
+  return (alive && !stopped && ans <= ub) ? ans : kInf;
+}
+
+template <int H, int KIND, bool BANDED>
+__global__ __launch_bounds__(64) void wide_kernel(WideArgs a) {
+  const int lane = threadIdx.x;
+  float *Bw = a.bnd + (int64_t)blockIdx.x * a.bnd_stride;
+  uint64_t evaluated = 0, computed = 0, abandoned = 0;
+  for (int64_t task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+    WideProblem p{};
+    if (KIND == kWideSearch) {
+      const int64_t kb = a.k_begin + task * kWave;
+      const int64_t k = kb + lane;
+      p.active = k < a.k_end;
+      const int64_t kc = p.active ? k : a.k_end - 1;
+      double mean, sd;
+      wave_window_stats(a.x, a.n, a.lrow, kb, lane, mean, sd);
+      znorm_params(mean, sd, p.mu_hi, p.mu_lo, p.inv);
+      p.xk = a.x + kc;
+      p.ub = a.dists_mode ? a.fixed_ub : load_bsf_dist(a.bsf);
+      const float d = wide_problem<H, KIND, BANDED>(a, p, Bw, lane, evaluated, computed);
+      const bool keep = p.active && d <= p.ub && d < kInf;
+      if (a.dists_mode) {
+        if (p.active) a.dists[k - a.k_begin] = d;
+      } else if (keep) {
+        atomicMin(a.bsf, pack_best(d, a.bound_only ? 0xffffffffu : (uint32_t)k));
+      }
+      abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
+    } else if (KIND == kWidePairwise) {
+      const int64_t i = task / a.nblk_j, jb = task % a.nblk_j;
+      if (jb * kWave + kWave - 1 <= i) continue;  // block entirely on or below the diagonal
+      const int64_t j = jb * kWave + lane;
+      p.active = j > i && j < a.N;
+      const int64_t jc = p.active ? j : a.N - 1;
+      p.rowp = a.X + i * a.lrow;
+      p.colp = a.XT + jc;
+      p.cstride = a.ld;
+      float acc = 0.0f;
+      for (int t = 0; t < a.lrow; ++t) {
+        const float diff = p.colp[(int64_t)t * p.cstride] - p.rowp[t];
+        acc = __builtin_fmaf(diff, diff, acc);
+      }
+      p.ed = acc;
+      p.ub = acc;
+      const float d = wide_problem<H, KIND, BANDED>(a, p, Bw, lane, evaluated, computed);
+      if (p.active) a.out[i * a.N - i * (i + 1) / 2 + (j - i - 1)] = d < kInf ? d : p.ed;
+      abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
+    } else {
+      const int64_t pp = task * kWave + lane;
+      p.active = pp < a.N;
+      const int64_t pc = p.active ? pp : a.N - 1;
+      p.rowp = a.RT + pc;
+      p.colp = a.XT + pc;
+      p.cstride = a.ld;
+      if (a.ub_mode == 1) {
+        p.ub = a.ub[pc];
+      } else if (a.ub_mode == 2) {
+        float acc = 0.0f;
+        for (int t = 0; t < a.lrow; ++t) {
+          const float diff = p.colp[(int64_t)t * p.cstride] - p.rowp[(int64_t)t * a.ld];
+          acc = __builtin_fmaf(diff, diff, acc);
+        }
+        p.ed = acc;
+        p.ub = acc;
+      } else if (a.ub_mode == 3) {
+        p.ub = a.ub_scalar;
+      } else {
+        p.ub = kInf;
+      }
+      const float d = wide_problem<H, KIND, BANDED>(a, p, Bw, lane, evaluated, computed);
+      if (p.active) a.out[pp] = (d < kInf || a.ub_mode != 2) ? d : p.ed;
+      abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
+    }
+  }
+  if (a.counters && lane == 0) {
+    unsigned long long *c = counter_stripe(a.counters, blockIdx.x);
+    atomicAdd(&c[kCntEvaluated], (unsigned long long)evaluated);
+    atomicAdd(&c[kCntComputed], (unsigned long long)computed);
+    atomicAdd(&c[kCntAbandoned], (unsigned long long)abandoned);
+  }
+}
+
+}  // namespace eapdtw
