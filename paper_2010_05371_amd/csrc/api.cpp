@@ -12,6 +12,7 @@
 #include "../../include/eapdtw.h"
 #include "dispatch.h"
 #include "wide.h"
+#include "bwd.h"
 
 using namespace eapdtw;
 
@@ -694,24 +695,70 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
 // --------------------------------------------------------------------------- differentiable batch
 
 int64_t eapdtw_dtw_ckpt_bytes(int64_t npairs, int64_t len, int64_t window) {
-  (void)npairs; (void)len; (void)window;
-  return -1;
+  if (npairs < 0 || len < 0 || window < 0 || len > INT_MAX / 2) return -1;
+  const int64_t r = len > 0 ? (window < len - 1 ? window : len - 1) : 0;
+  if (r > kBandRMax) return -1;
+  const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
+  const int64_t bytes = bwd_num_ckpt(len) * (2 * r + 1) * ld * (int64_t)sizeof(float);
+  return bytes > 4 ? bytes : 4;
+}
+
+static int diff_validate(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
+                         int64_t len, int64_t window, const void *ckpt) {
+  if (npairs < 0 || len < 0) return fail(ctx, EAPDTW_EINVAL, "negative size");
+  if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
+  if (npairs > 0 && len > 0 && (!S || !T || !ckpt)) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
+  if (eapdtw_dtw_ckpt_bytes(npairs, len, window) < 0)
+    return fail(ctx, EAPDTW_EINVAL, "the differentiable batch supports windows up to 64");
+  if (len > 65535) return fail(ctx, EAPDTW_EINVAL, "series longer than 65535");
+  return EAPDTW_OK;
 }
 
 int eapdtw_dtw_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
                    int64_t window, float *out_dist, void *ckpt) {
   CHECK_CTX();
-  (void)S; (void)T; (void)npairs; (void)len; (void)window; (void)out_dist; (void)ckpt;
-  return fail(ctx, EAPDTW_EINVAL, "forward: not built yet");
+  int rc = diff_validate(ctx, S, T, npairs, len, window, ckpt);
+  if (rc) return rc;
+  if (npairs > 0 && !out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL output");
+  return pairs_common(ctx, S, T, npairs, len, window, 0, nullptr, out_dist, nullptr,
+                      static_cast<float *>(ckpt), kBwdBlock);
 }
 
 int eapdtw_dtw_bwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
                    int64_t window, const void *ckpt, const float *grad_out, float *grad_S,
                    float *grad_T) {
   CHECK_CTX();
-  (void)S; (void)T; (void)npairs; (void)len; (void)window; (void)ckpt; (void)grad_out;
-  (void)grad_S; (void)grad_T;
-  return fail(ctx, EAPDTW_EINVAL, "backward: not built yet");
+  int rc = diff_validate(ctx, S, T, npairs, len, window, ckpt);
+  if (rc) return rc;
+  if (npairs == 0 || len == 0) return EAPDTW_OK;
+  if (!grad_out || !grad_S || !grad_T) return fail(ctx, EAPDTW_EINVAL, "NULL gradient buffer");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int64_t r = window < len - 1 ? window : len - 1;
+  const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
+  Plan pl;
+  const size_t o_rows = pl.add(sizeof(float) * len * ld);
+  const size_t o_cols = pl.add(sizeof(float) * (len + 2 * kColPad) * ld);
+  const size_t o_rr = pl.add(sizeof(unsigned) * len * ld);
+  const size_t o_cr = pl.add(sizeof(unsigned) * len * ld);
+  rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  HIPCHK(launch_transpose_pad(S, npairs, (int)len, ld, 0, 0.0f, at<float>(ctx, o_rows), st));
+  HIPCHK(launch_transpose_pad(T, npairs, (int)len, ld, kColPad, INFINITY, at<float>(ctx, o_cols), st));
+  BwdArgs b{};
+  b.rowsT = at<float>(ctx, o_rows);
+  b.colsT = at<float>(ctx, o_cols);
+  b.ckpt = static_cast<const float *>(ckpt);
+  b.dist = nullptr;
+  b.rowrng = at<unsigned>(ctx, o_rr);
+  b.colrng = at<unsigned>(ctx, o_cr);
+  b.npairs = npairs;
+  b.ld = ld;
+  b.len = (int)len;
+  HIPCHK(launch_dtw_bwd((int)r, b, st));
+  HIPCHK(launch_dtw_grad(S, T, npairs, (int)len, b.rowrng, b.colrng, nullptr, grad_out, grad_S,
+                         grad_T, st));
+  return EAPDTW_OK;
 }
 
 // --------------------------------------------------------------------------- exposed steps

@@ -111,36 +111,49 @@ __device__ __forceinline__ ConstF *opaque(ConstF *p) {
   return p;
 }
 __device__ __forceinline__ const float *opaque(const float *p) {
-  asm volatile("" : "+v"(p));
+  asm volatile("" : "+s"(p));
   return p;
 }
 
-// One group of U rows, swept column by column.  The value of group column s
-// (matrix column j = i0 + s - R) is base[s * stride].  Column values are
-// fetched one chunk of kColChunk columns ahead of their use, which bounds the
-// registers that hold them.
+// Column values of a group sweep: the value of group column s is
+// base[s * stride + lane_off].  base is wave-uniform (kept in SGPRs);
+// lane_off is 0 for a uniform column series (the query) and the lane's pair
+// index for per-lane series, so the loads use a scalar base and a 32-bit
+// lane offset.
+template <class Ptr>
+struct Cols {
+  Ptr base;
+  int64_t stride;
+  int lane_off;
+};
+
+// One group of U rows, swept column by column (group column s is matrix
+// column j = i0 + s - R).  Column values are fetched one chunk of kColChunk
+// columns ahead of their use, which bounds the registers that hold them.
 constexpr int kColChunk = 16;
 
 template <int R, int U, class Ptr>
-__device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (&rv)[U], Ptr base,
-                                            int64_t stride) {
+__device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (&rv)[U],
+                                            Cols<Ptr> cs) {
   constexpr int W = 2 * R + 1;
   constexpr int NS = W + U - 1;
   constexpr int CH = kColChunk;
   constexpr int NCH = (NS + CH - 1) / CH;
+  const int64_t stride = cs.stride;
   float cur[CH];
   {
-    Ptr p0 = opaque(base);
+    Ptr p0 = opaque(cs.base);
 #pragma unroll
-    for (int t = 0; t < CH; ++t) cur[t] = (t < NS) ? p0[t * stride] : 0.0f;
+    for (int t = 0; t < CH; ++t) cur[t] = (t < NS) ? p0[t * stride + cs.lane_off] : 0.0f;
   }
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     float nxt[CH];
     if (c + 1 < NCH) {
-      Ptr pn = opaque(base + (int64_t)(c + 1) * CH * stride);
+      Ptr pn = opaque(cs.base + (int64_t)(c + 1) * CH * stride);
 #pragma unroll
-      for (int t = 0; t < CH; ++t) nxt[t] = ((c + 1) * CH + t < NS) ? pn[t * stride] : 0.0f;
+      for (int t = 0; t < CH; ++t)
+        nxt[t] = ((c + 1) * CH + t < NS) ? pn[t * stride + cs.lane_off] : 0.0f;
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -258,7 +271,7 @@ __global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u) rv_next[u] = xk[i0 + U + u];
     }
-    sweep_group<R, U>(v, rv, as_const(a.qpad + kColPad + i0 - R), 1);
+    sweep_group<R, U>(v, rv, Cols<ConstF *>{as_const(a.qpad + kColPad + i0 - R), 1, 0});
     const int cells = rows_cells<U>(i0, m, R);
     evaluated += (uint64_t)cells * (uint64_t)__popcll(__ballot(alive));
     computed += (uint64_t)cells * kWave;
@@ -272,7 +285,7 @@ __global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
   // remaining rows, one at a time
   for (int i = mg; i < m && !stopped; ++i) {
     float rv1[1] = {znorm_value(xk[i], mu_hi, mu_lo, inv)};
-    sweep_group<R, 1>(v, rv1, as_const(a.qpad + kColPad + i - R), 1);
+    sweep_group<R, 1>(v, rv1, Cols<ConstF *>{as_const(a.qpad + kColPad + i - R), 1, 0});
     const int cells = row_cells(i, m, R);
     evaluated += (uint64_t)cells * (uint64_t)__popcll(__ballot(alive));
     computed += (uint64_t)cells * kWave;
@@ -312,6 +325,7 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
   const int lrow = a.lrow, lcol = a.lcol;
   const float *__restrict__ rows = a.rowsT + pc;
   const float *__restrict__ cols = a.colsT + (int64_t)kColPad * ld + pc;
+  const float *colu = a.colsT + (int64_t)kColPad * ld;  // wave-uniform column base
 
   float ub;
   float ed = kInf;
@@ -347,7 +361,7 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
     float rv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) rv[u] = rows[(int64_t)(i0 + u) * ld];
-    sweep_group<R, U>(v, rv, cols + (int64_t)(i0 - R) * ld, ld);
+    sweep_group<R, U>(v, rv, Cols<const float *>{colu + (int64_t)(i0 - R) * ld, ld, (int)pc});
     const int cells = rows_cells<U>(i0, lcol, R);
     evaluated += (uint64_t)cells * (uint64_t)__popcll(__ballot(alive));
     computed += (uint64_t)cells * kWave;
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
   }
   for (int i = mg; i < lrow && !stopped; ++i) {
     float rv1[1] = {rows[(int64_t)i * ld]};
-    sweep_group<R, 1>(v, rv1, cols + (int64_t)(i - R) * ld, ld);
+    sweep_group<R, 1>(v, rv1, Cols<const float *>{colu + (int64_t)(i - R) * ld, ld, (int)pc});
     const int cells = row_cells(i, lcol, R);
     evaluated += (uint64_t)cells * (uint64_t)__popcll(__ballot(alive));
     computed += (uint64_t)cells * kWave;
