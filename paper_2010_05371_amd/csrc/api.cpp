@@ -13,6 +13,10 @@
 #include "dispatch.h"
 #include "wide.h"
 #include "bwd.h"
+#include "batch.h"
+
+#include <algorithm>
+#include <vector>
 
 using namespace eapdtw;
 
@@ -36,6 +40,15 @@ struct eapdtw_ctx {
   int64_t force_wide = 0;
   int64_t seed_stride = 4;
   int64_t seed_window = 8;
+  int64_t batch_grid = 2048;
+  int64_t batch_chunk = 4;
+  int64_t batch_seed_stride = 16;
+  // batched search: dedicated device buffer and the captured graph
+  char *batch_buf = nullptr;
+  size_t batch_cap = 0;
+  hipGraphExec_t batch_exec = nullptr;
+  uint64_t batch_key = 0;
+  hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
 };
 
 static thread_local std::string g_create_error;
@@ -243,6 +256,9 @@ void eapdtw_destroy(eapdtw_ctx *ctx) {
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
+  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
+  if (ctx->batch_buf) (void)hipFree(ctx->batch_buf);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -271,6 +287,9 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "force_wide")) return &ctx->force_wide;
   if (!strcmp(key, "seed_stride")) return &ctx->seed_stride;
   if (!strcmp(key, "seed_window")) return &ctx->seed_window;
+  if (!strcmp(key, "batch_grid")) return &ctx->batch_grid;
+  if (!strcmp(key, "batch_chunk")) return &ctx->batch_chunk;
+  if (!strcmp(key, "batch_seed_stride")) return &ctx->batch_seed_stride;
   return nullptr;
 }
 
@@ -286,6 +305,9 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   else if (!strcmp(key, "lanes_per_problem")) ok = value == 1;
   else if (!strcmp(key, "seed_stride")) ok = value >= 1 && value <= 1024;
   else if (!strcmp(key, "seed_window")) ok = value >= 0 && value <= kBandRMax;
+  else if (!strcmp(key, "batch_grid")) ok = value >= 64 && value <= 65536;
+  else if (!strcmp(key, "batch_chunk")) ok = value >= 1 && value <= 1024;
+  else if (!strcmp(key, "batch_seed_stride")) ok = value >= 1 && value <= 1024;
   if (!ok) return fail(ctx, EAPDTW_EINVAL, std::string("bad value for option ") + key);
   *slot = value;
   return EAPDTW_OK;
@@ -684,12 +706,182 @@ int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
   return EAPDTW_OK;
 }
 
+static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+  const unsigned char *b = static_cast<const unsigned char *>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+// Queues the whole batched search on the context stream (used directly, or
+// once under stream capture to build the graph).
+static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid, hipStream_t st) {
+  HIPCHK(launch_fill_u64(ba.counters, 0ull, kCntWords, st));
+  HIPCHK(launch_batch_prep(ba, st));
+  HIPCHK(launch_check_finite(ba.x, ba.n, ba.counters, st));
+  if (ctx->seed) HIPCHK(launch_batch_seed(ba, st));
+  HIPCHK(launch_batch_main(ba, grid, st));
+  return EAPDTW_OK;
+}
+
 int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
                            const float *series, int64_t n, eapdtw_result *out,
                            eapdtw_stats *stats) {
   CHECK_CTX();
-  (void)qs; (void)nq; (void)series; (void)n; (void)out; (void)stats;
-  return fail(ctx, EAPDTW_EINVAL, "batch search: not built yet");
+  if (nq < 0 || (nq > 0 && (!qs || !out))) return fail(ctx, EAPDTW_EINVAL, "bad query array");
+  if (nq > 65536) return fail(ctx, EAPDTW_EINVAL, "too many queries");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (nq == 0) return EAPDTW_OK;
+  int64_t max_m = 0;
+  for (int64_t q = 0; q < nq; ++q) {
+    int rc = search_validate(ctx, qs[q].query, qs[q].m, series, n, qs[q].window);
+    if (rc) return rc;
+    max_m = std::max(max_m, qs[q].m);
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  // most expensive queries first (band cells per candidate x candidates)
+  std::vector<int64_t> order(nq);
+  std::vector<double> cost(nq);
+  uint64_t nominal = 0, problems = 0;
+  for (int64_t q = 0; q < nq; ++q) {
+    const int64_t m = qs[q].m, r = std::min(qs[q].window, m - 1), K = n - m + 1;
+    const int64_t bc = band_cells_total(m, m, r);
+    cost[q] = (double)bc * (double)K;
+    nominal += (uint64_t)(bc * K);
+    problems += (uint64_t)K;
+    order[q] = q;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+  const int grid = (int)ctx->batch_grid;
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_work = pl.add(sizeof(unsigned long long));
+  const size_t o_desc = pl.add(sizeof(BatchQuery) * nq);
+  const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2 * nq);
+  std::vector<size_t> o_q(nq);
+  for (int64_t i = 0; i < nq; ++i) o_q[i] = pl.add(sizeof(float) * (qs[order[i]].m + 2 * kColPad));
+  const size_t o_bnd = pl.add(sizeof(float) * (size_t)grid * (max_m + 1) * kWave);
+  if (pl.off > ctx->batch_cap) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->batch_exec) {
+      (void)hipGraphExecDestroy(ctx->batch_exec);
+      ctx->batch_exec = nullptr;
+    }
+    if (ctx->batch_buf) HIPCHK(hipFree(ctx->batch_buf));
+    ctx->batch_buf = nullptr;
+    ctx->batch_cap = 0;
+    if (hipMalloc((void **)&ctx->batch_buf, pl.off) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, EAPDTW_ENOMEM, "batch buffer allocation failed");
+    }
+    ctx->batch_cap = pl.off;
+  }
+  char *bb = ctx->batch_buf;
+  // descriptors in the sorted order
+  std::vector<BatchQuery> desc(nq);
+  int64_t units = 0, seeds = 0;
+  const int64_t sstr = ctx->batch_seed_stride;
+  for (int64_t i = 0; i < nq; ++i) {
+    const eapdtw_query &h = qs[order[i]];
+    BatchQuery &d = desc[i];
+    d.query = h.query;
+    d.qpad = reinterpret_cast<float *>(bb + o_q[i]);
+    d.bsf = reinterpret_cast<unsigned long long *>(bb + o_bsf) + 2 * i;
+    d.m = (int)h.m;
+    d.r = (int)std::min(h.window, h.m - 1);
+    d.K = n - h.m + 1;
+    d.unit_begin = units;
+    d.seed_begin = seeds;
+    const int64_t nblk = (d.K + kWave - 1) / kWave;
+    units += nblk;
+    seeds += (nblk + sstr - 1) / sstr;
+  }
+  BatchArgs ba{};
+  ba.qs = reinterpret_cast<const BatchQuery *>(bb + o_desc);
+  ba.nq = (int)nq;
+  ba.x = series;
+  ba.n = n;
+  ba.total_units = units;
+  ba.work = reinterpret_cast<unsigned long long *>(bb + o_work);
+  ba.chunk = (int)ctx->batch_chunk;
+  ba.total_seed_blocks = seeds;
+  ba.seed_stride = (int)sstr;
+  ba.seed_window = (int)std::min<int64_t>(ctx->seed_window, 8);
+  ba.bnd = reinterpret_cast<float *>(bb + o_bnd);
+  ba.bnd_stride = (max_m + 1) * kWave;
+  ba.counters = reinterpret_cast<unsigned long long *>(bb + o_cnt);
+  ba.check_interval = (int)ctx->check_interval;
+  // graph key: everything the captured launches depend on
+  uint64_t key = 1469598103934665603ull;
+  key = fnv1a(key, &bb, sizeof bb);
+  key = fnv1a(key, &ctx->stream, sizeof ctx->stream);
+  key = fnv1a(key, &ba, sizeof ba);
+  key = fnv1a(key, desc.data(), sizeof(BatchQuery) * nq);
+  key = fnv1a(key, &grid, sizeof grid);
+  key = fnv1a(key, &ctx->seed, sizeof ctx->seed);
+  const bool use_graph = ctx->graph != 0;
+  const bool rebuild = !use_graph || !ctx->batch_exec || ctx->batch_key != key;
+  if (rebuild) {
+    // descriptors are constant for a given key: upload them outside the graph
+    int rc = ensure_pinned(ctx, sizeof(BatchQuery) * nq);
+    if (rc) return rc;
+    std::memcpy(ctx->pinned, desc.data(), sizeof(BatchQuery) * nq);
+    HIPCHK(hipMemcpyAsync(bb + o_desc, ctx->pinned, sizeof(BatchQuery) * nq, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  if (use_graph) {
+    if (rebuild) {
+      if (ctx->batch_exec) {
+        (void)hipGraphExecDestroy(ctx->batch_exec);
+        ctx->batch_exec = nullptr;
+      }
+      // the caller's stream may be the null stream, which cannot be
+      // captured: record on a private stream, replay on the caller's
+      if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = batch_queue(ctx, ba, grid, ctx->cap_stream);
+      hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (ec != hipSuccess) return fail_hip(ctx, ec, "hipStreamEndCapture");
+      ec = hipGraphInstantiate(&ctx->batch_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ec != hipSuccess) {
+        ctx->batch_exec = nullptr;
+        return fail_hip(ctx, ec, "hipGraphInstantiate");
+      }
+      ctx->batch_key = key;
+    }
+    HIPCHK(hipGraphLaunch(ctx->batch_exec, st));
+  } else {
+    int rc = batch_queue(ctx, ba, grid, st);
+    if (rc) return rc;
+  }
+  if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
+  // counters, work counter, descriptors and best-so-far words read back at once
+  const size_t nbytes = o_bsf + sizeof(unsigned long long) * 2 * nq;
+  int rc = ensure_pinned(ctx, nbytes);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(ctx->pinned, bb, nbytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned + o_cnt);
+  if (counter_sum(hc, kCntNonFinite)) return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in a query or the series");
+  const unsigned long long *hb = reinterpret_cast<unsigned long long *>(ctx->pinned + o_bsf);
+  for (int64_t i = 0; i < nq; ++i) {
+    const unsigned long long b = hb[2 * i];
+    eapdtw_result &r = out[order[i]];
+    r.offset = best_offset(b) == 0xffffffffu ? -1 : (int64_t)best_offset(b);
+    r.dist = (double)best_dist(b);
+  }
+  if (stats) {
+    const float ms = elapsed(ctx->ev0, ctx->ev1);
+    fill_stats(stats, hc, nominal, problems, ms, ms);
+  }
+  return EAPDTW_OK;
 }
 
 // --------------------------------------------------------------------------- differentiable batch

@@ -2,6 +2,7 @@
 // checks, transposition into the coalesced pair layout, counters.
 #include "band.h"
 #include "dispatch.h"
+#include "znorm.h"
 
 namespace eapdtw {
 
@@ -16,49 +17,13 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
   return hipGetLastError();
 }
 
-__device__ __forceinline__ bool not_finite(float v) { return !(fabsf(v) <= 3.402823466e38f); }
-
-// Block-wide float64 sum (256 threads).
-__device__ double block_sum_f64(double v, double *sh) {
-  v = wave_sum_f64(v);
-  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += sh[i];
-  return t;
-}
-
-// z-normalisation of one short series by one workgroup (two passes in
-// float64, population sigma; zero sigma normalises to zeros).  Writes
-// out[pad + j] for j < m and +inf into the `pad` entries on each side when
-// pad > 0.  Counts non-finite inputs.
+// z-normalisation of one short series by one workgroup; counts non-finite
+// inputs into the counters.
 __global__ void znorm_kernel(const float *__restrict__ q, int m, float *__restrict__ out, int pad,
                              unsigned long long *counters) {
   __shared__ double sh[16];
-  double s = 0.0;
-  int bad = 0;
-  for (int j = threadIdx.x; j < m; j += blockDim.x) {
-    const float v = q[j];
-    bad += not_finite(v);
-    s += (double)v;
-  }
-  const double mean = block_sum_f64(s, sh) / (double)m;
-  double ss = 0.0;
-  for (int j = threadIdx.x; j < m; j += blockDim.x) {
-    const double dv = (double)q[j] - mean;
-    ss += dv * dv;
-  }
-  const double var = block_sum_f64(ss, sh) / (double)m;
-  const double sd = sqrt(var);
-  for (int j = threadIdx.x; j < m; j += blockDim.x)
-    out[pad + j] = sd > 0.0 ? (float)(((double)q[j] - mean) / sd) : 0.0f;
-  for (int j = threadIdx.x; j < pad; j += blockDim.x) {
-    out[j] = kInf;
-    out[pad + m + j] = kInf;
-  }
-  if (counters && bad) atomicAdd(&counters[kCntNonFinite], (unsigned long long)bad);
+  const int bad = znorm_block(q, m, out, pad, sh);
+  if (counters && bad && threadIdx.x == 0) atomicAdd(&counters[kCntNonFinite], (unsigned long long)bad);
 }
 
 hipError_t launch_query_prep(const float *q, int m, float *qpad, unsigned long long *counters,

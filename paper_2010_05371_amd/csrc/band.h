@@ -217,7 +217,7 @@ __device__ __forceinline__ float load_bsf_dist(const unsigned long long *bsf) {
 // DISTS = true writes every candidate's early-abandoned distance against the
 // fixed bound instead of updating the shared best-so-far.
 template <int R, int U, bool DISTS>
-__global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
+__device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   constexpr int W = 2 * R + 1;
   const int lane = threadIdx.x;
   int64_t kbeg = a.k_begin, kend = a.k_end;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
     kbeg = lo;
     if (a.bsf_init && lane == 0) atomicMin(a.bsf, pack_best(best_dist(*a.bsf_init), 0xffffffffu));
   }
-  const int64_t kb = kbeg + (int64_t)blockIdx.x * kWave * (a.block_stride > 1 ? a.block_stride : 1);
+  const int64_t kb = kbeg + blk * kWave * (a.block_stride > 1 ? a.block_stride : 1);
   if (kb >= kend) return;
   const int64_t k = kb + lane;
   const bool active = k < kend;
@@ -309,6 +309,11 @@ __global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
       atomicAdd(&c[kCntAbandoned], (unsigned long long)aband);
     }
   }
+}
+
+template <int R, int U, bool DISTS>
+__global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
+  nn_band_body<R, U, DISTS>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

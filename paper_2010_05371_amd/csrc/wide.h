@@ -289,6 +289,32 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
   return (alive && !stopped && ans <= ub) ? ans : kInf;
 }
 
+// One block of 64 consecutive candidate offsets of a search (task t covers
+// offsets k_begin + 64 t + lane).
+template <int H, bool BANDED>
+__device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task, float *Bw,
+                                                 int lane, uint64_t &evaluated, uint64_t &computed,
+                                                 uint64_t &abandoned) {
+  WideProblem p{};
+  const int64_t kb = a.k_begin + task * kWave;
+  const int64_t k = kb + lane;
+  p.active = k < a.k_end;
+  const int64_t kc = p.active ? k : a.k_end - 1;
+  double mean, sd;
+  wave_window_stats(a.x, a.n, a.lrow, kb, lane, mean, sd);
+  znorm_params(mean, sd, p.mu_hi, p.mu_lo, p.inv);
+  p.xk = a.x + kc;
+  p.ub = a.dists_mode ? a.fixed_ub : load_bsf_dist(a.bsf);
+  const float d = wide_problem<H, kWideSearch, BANDED>(a, p, Bw, lane, evaluated, computed);
+  const bool keep = p.active && d <= p.ub && d < kInf;
+  if (a.dists_mode) {
+    if (p.active) a.dists[k - a.k_begin] = d;
+  } else if (keep) {
+    atomicMin(a.bsf, pack_best(d, a.bound_only ? 0xffffffffu : (uint32_t)k));
+  }
+  abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
+}
+
 template <int H, int KIND, bool BANDED>
 __global__ __launch_bounds__(64) void wide_kernel(WideArgs a) {
   const int lane = threadIdx.x;
@@ -297,23 +323,7 @@ __global__ __launch_bounds__(64) void wide_kernel(WideArgs a) {
   for (int64_t task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
     WideProblem p{};
     if (KIND == kWideSearch) {
-      const int64_t kb = a.k_begin + task * kWave;
-      const int64_t k = kb + lane;
-      p.active = k < a.k_end;
-      const int64_t kc = p.active ? k : a.k_end - 1;
-      double mean, sd;
-      wave_window_stats(a.x, a.n, a.lrow, kb, lane, mean, sd);
-      znorm_params(mean, sd, p.mu_hi, p.mu_lo, p.inv);
-      p.xk = a.x + kc;
-      p.ub = a.dists_mode ? a.fixed_ub : load_bsf_dist(a.bsf);
-      const float d = wide_problem<H, KIND, BANDED>(a, p, Bw, lane, evaluated, computed);
-      const bool keep = p.active && d <= p.ub && d < kInf;
-      if (a.dists_mode) {
-        if (p.active) a.dists[k - a.k_begin] = d;
-      } else if (keep) {
-        atomicMin(a.bsf, pack_best(d, a.bound_only ? 0xffffffffu : (uint32_t)k));
-      }
-      abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
+      wide_search_task<H, BANDED>(a, task, Bw, lane, evaluated, computed, abandoned);
     } else if (KIND == kWidePairwise) {
       const int64_t i = task / a.nblk_j, jb = task % a.nblk_j;
       if (jb * kWave + kWave - 1 <= i) continue;  // block entirely on or below the diagonal
