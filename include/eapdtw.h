@@ -103,8 +103,13 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *   "seed"           : 1 = seed the best-so-far from a window-0 pass and one
  *                      workgroup of candidates around its best offset (default),
  *                      0 = start the search from +inf
- *   "rows_per_group" : rows handled per group by the band kernels (1,2,4,8; 0=auto)
- *   "wide_rows"      : rows per tile of the wide-window kernel (8,16,32; 0=auto)
+ *   "rows_per_group" : rows handled per group by the band search kernel (2,4,8; 0=auto)
+ *   "seed_stride"    : the window-0 seeding pass visits every seed_stride-th block
+ *   "seed_window"    : window of the seeding workgroup (<= search window)
+ *   "batch_grid"     : persistent workgroups of the batched search
+ *   "batch_chunk"    : work units taken per queue access in the batched search
+ *   "batch_seed_stride": seed_stride of the batched search
+ *   "wide_rows"      : rows per tile of the whole-matrix-window kernel (32, 64; 0=auto)
  *   "lanes_per_problem": reserved (1)
  *   "graph"          : 1 = replay batched searches from a captured hipGraph
  *   "force_wide"     : 1 = use the wide-window kernel even for narrow windows

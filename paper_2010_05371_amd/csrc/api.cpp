@@ -301,7 +301,7 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   if (!strcmp(key, "check_interval")) ok = value >= 1 && value <= (1 << 20);
   else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide")) ok = value == 0 || value == 1;
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
-  else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 8 || value == 16 || value == 32;
+  else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
   else if (!strcmp(key, "lanes_per_problem")) ok = value == 1;
   else if (!strcmp(key, "seed_stride")) ok = value >= 1 && value <= 1024;
   else if (!strcmp(key, "seed_window")) ok = value >= 0 && value <= kBandRMax;
@@ -389,7 +389,7 @@ static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
     w.bnd_stride = (lcol + 1) * kWave;
     w.counters = cnt;
     w.check_interval = 1;
-    HIPCHK(launch_wide(kWidePairs, 0, w, (int)grid, st));
+    HIPCHK(launch_wide(kWidePairs, (int)ctx->wide_rows, w, (int)grid, st));
   }
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
@@ -523,7 +523,7 @@ int eapdtw_pairwise(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int
   w.counters = cnt;
   w.check_interval = 1;
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
-  HIPCHK(launch_wide(kWidePairwise, 0, w, (int)grid, st));
+  HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -619,7 +619,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     w.bnd_stride = (m + 1) * kWave;
     w.counters = cnt;
     w.check_interval = (int)ctx->check_interval;
-    HIPCHK(launch_wide(kWideSearch, 0, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
+    HIPCHK(launch_wide(kWideSearch, (int)ctx->wide_rows, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev3, st));
   return EAPDTW_OK;

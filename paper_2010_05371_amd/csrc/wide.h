@@ -89,7 +89,9 @@ __device__ __forceinline__ float wide_row_value(const WideArgs &a, const WidePro
 
 template <int KIND>
 __device__ __forceinline__ float wide_col_value(const WideArgs &a, const WideProblem &p, int j) {
-  if (KIND == kWideSearch) return as_const(a.qpad + kColPad)[j];
+  // the query value is wave-uniform; it is loaded into a VGPR (one cache line
+  // per wave) so that the prefetch queue does not compete for SGPRs
+  if (KIND == kWideSearch) return (a.qpad + kColPad)[j];
   return p.colp[(int64_t)j * p.cstride];
 }
 
@@ -126,7 +128,11 @@ __device__ __forceinline__ float col_min(const float (&col)[H]) {
 
 namespace eapdtw {
 
-// Per-column bookkeeping state of one tile sweep.
+// Per-column bookkeeping state of one tile sweep.  The boundary value from
+// the tile above and the column value of the next PD columns are loaded ahead
+// of their use (a small queue in registers) so that the memory latency of a
+// column overlaps the cells of the columns before it.
+template <int PD>
 struct Sweep {
   int j;              // next column
   int jend;           // last column the tile may reach
@@ -140,16 +146,32 @@ struct Sweep {
   int64_t rows;       // admissible rows of the tile (<= H, last tile may be shorter)
   uint64_t evaluated, computed;
   unsigned long long alive_mask;
+  float qtop[PD], qcv[PD];  // prefetched values of columns j .. j+PD-1
 };
 
-template <int H, int KIND, int H_LO, int H_HI>
+template <int KIND, int PD>
+__device__ __forceinline__ void wide_fetch(const WideArgs &a, const WideProblem &p, const float *Bw,
+                                           int lane, const Sweep<PD> &s, int c, float &top,
+                                           float &cv) {
+  const bool in = c <= s.jend;
+  const bool have_top = in && s.t > 0 && c >= s.bv_lo && c <= s.bv_hi;
+  top = have_top ? Bw[(int64_t)(c + 1) * kWave + lane] : kInf;
+  cv = in ? wide_col_value<KIND>(a, p, c) : 0.0f;
+}
+
+template <int H, int KIND, int H_LO, int H_HI, int PD>
 __device__ __forceinline__ void wide_step(const WideArgs &a, const WideProblem &p, float *Bw,
                                           int lane, float (&col)[H], const float (&rv)[H],
-                                          Sweep &s, float ub, int tlast, int hans, float &ans) {
+                                          Sweep<PD> &s, float ub, int tlast, int hans, float &ans) {
   const int j = s.j;
-  const bool have_top = s.t > 0 && j >= s.bv_lo && j <= s.bv_hi;
-  const float top0 = have_top ? Bw[(int64_t)(j + 1) * kWave + lane] : kInf;
-  const float cv = wide_col_value<KIND>(a, p, j);
+  const float top0 = s.qtop[0];
+  const float cv = s.qcv[0];
+#pragma unroll
+  for (int k = 0; k + 1 < PD; ++k) {
+    s.qtop[k] = s.qtop[k + 1];
+    s.qcv[k] = s.qcv[k + 1];
+  }
+  wide_fetch<KIND, PD>(a, p, Bw, lane, s, j + PD, s.qtop[PD - 1], s.qcv[PD - 1]);
   wide_column<H, H_LO, H_HI, false>(col, rv, cv, top0, s.diag0);
   s.diag0 = top0;
   Bw[(int64_t)(j + 1) * kWave + lane] = col[H - 1];
@@ -180,40 +202,121 @@ __device__ __forceinline__ void wide_step(const WideArgs &a, const WideProblem &
   if (s.j > s.jend) s.go = false;
 }
 
+// Two full columns j, j+1 in one step: the cells of column j+1 trail those of
+// column j by one row, so the two dependency chains interleave.  Used where
+// neither column needs the answer capture or a right-border check.
+template <int H, int KIND, int PD>
+__device__ __forceinline__ void wide_step2(const WideArgs &a, const WideProblem &p, float *Bw,
+                                           int lane, float (&col)[H], const float (&rv)[H],
+                                           Sweep<PD> &s, float ub) {
+  const int j = s.j;
+  const float topA = s.qtop[0], cvA = s.qcv[0];
+  const float topB = s.qtop[1], cvB = s.qcv[1];
+#pragma unroll
+  for (int k = 0; k + 2 < PD; ++k) {
+    s.qtop[k] = s.qtop[k + 2];
+    s.qcv[k] = s.qcv[k + 2];
+  }
+  wide_fetch<KIND, PD>(a, p, Bw, lane, s, j + PD, s.qtop[PD - 2], s.qcv[PD - 2]);
+  wide_fetch<KIND, PD>(a, p, Bw, lane, s, j + PD + 1, s.qtop[PD - 1], s.qcv[PD - 1]);
+  // keep column j's last row for the boundary store before it is overwritten
+  float lastA;
+  {
+    float upA = topA, dgA = s.diag0;
+    float prevA = 0.0f;
+    float upB = topB, dgB = topA;
+#pragma unroll
+    for (int h = 0; h <= H; ++h) {
+      float nA = 0.0f;
+      if (h < H) {
+        const float left = col[h];
+        const float diff = cvA - rv[h];
+        nA = __builtin_fmaf(diff, diff, fmin3(left, upA, dgA));
+        dgA = left;
+        upA = nA;
+      }
+      if (h >= 1) {
+        const int hb = h - 1;
+        const float diff = cvB - rv[hb];
+        const float nB = __builtin_fmaf(diff, diff, fmin3(prevA, upB, dgB));
+        dgB = prevA;
+        upB = nB;
+        col[hb] = nB;
+      }
+      prevA = nA;
+    }
+    lastA = upA;
+  }
+  s.diag0 = topB;
+  Bw[(int64_t)(j + 1) * kWave + lane] = lastA;
+  Bw[(int64_t)(j + 2) * kWave + lane] = col[H - 1];
+  const bool lane_alive = (s.alive_mask >> lane) & 1ull;
+  const unsigned long long lmA = __ballot(lane_alive && lastA <= ub);
+  const unsigned long long lmB = __ballot(lane_alive && col[H - 1] <= ub);
+  if (lmA) {
+    if (s.first_live > j) s.first_live = j;
+    s.last_live = j;
+    s.lane_live |= lmA;
+  }
+  if (lmB) {
+    if (s.first_live > j + 1) s.first_live = j + 1;
+    s.last_live = j + 1;
+    s.lane_live |= lmB;
+  }
+  int hh = H - 1;
+  if (hh > s.rows - 1) hh = (int)s.rows - 1;
+  const int nc = hh + 1;
+  s.computed += (uint64_t)(2 * nc) * kWave;
+  s.evaluated += (uint64_t)(2 * nc) * (uint64_t)__popcll(s.alive_mask);
+  s.j = j + 2;
+  if (s.j > s.jend) s.go = false;
+}
+
+// True when columns j and j+1 are both full columns of the middle stretch,
+// neither holds the answer cell and neither is due for a right-border check.
+template <int PD>
+__device__ __forceinline__ bool wide_pair_ok(const Sweep<PD> &s, int jlast, int tlast, int lcol) {
+  const int j = s.j;
+  if (j + 1 > jlast || j + 1 > s.jend) return false;
+  if (s.t == tlast && j + 1 >= lcol - 1) return false;
+  if (j + 1 > s.jmand) return false;
+  return true;
+}
+
 // entering triangle: column c = j - (i0 - r) has rows 0..c admissible
-template <int H, int KIND, int C>
+template <int H, int KIND, int C, int PD>
 struct EnterPhase {
   __device__ __forceinline__ static void run(const WideArgs &a, const WideProblem &p, float *Bw,
                                              int lane, float (&col)[H], const float (&rv)[H],
-                                             Sweep &s, float ub, int tlast, int hans, float &ans,
+                                             Sweep<PD> &s, float ub, int tlast, int hans, float &ans,
                                              int jbase) {
-    if (s.go && s.j == jbase + C) wide_step<H, KIND, 0, C>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
-    EnterPhase<H, KIND, C + 1>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, jbase);
+    if (s.go && s.j == jbase + C) wide_step<H, KIND, 0, C, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+    EnterPhase<H, KIND, C + 1, PD>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, jbase);
   }
 };
-template <int H, int KIND>
-struct EnterPhase<H, KIND, H - 1> {
+template <int H, int KIND, int PD>
+struct EnterPhase<H, KIND, H - 1, PD> {
   __device__ __forceinline__ static void run(const WideArgs &, const WideProblem &, float *, int,
-                                             float (&)[H], const float (&)[H], Sweep &, float, int,
-                                             int, float &, int) {}
+                                             float (&)[H], const float (&)[H], Sweep<PD> &, float,
+                                             int, int, float &, int) {}
 };
 
 // exiting triangle: column c = j - (i0 + r + 1) has rows c+1..H-1 admissible
-template <int H, int KIND, int C>
+template <int H, int KIND, int C, int PD>
 struct ExitPhase {
   __device__ __forceinline__ static void run(const WideArgs &a, const WideProblem &p, float *Bw,
                                              int lane, float (&col)[H], const float (&rv)[H],
-                                             Sweep &s, float ub, int tlast, int hans, float &ans,
+                                             Sweep<PD> &s, float ub, int tlast, int hans, float &ans,
                                              int jbase) {
-    if (s.go && s.j == jbase + C) wide_step<H, KIND, C + 1, H - 1>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
-    ExitPhase<H, KIND, C + 1>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, jbase);
+    if (s.go && s.j == jbase + C) wide_step<H, KIND, C + 1, H - 1, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+    ExitPhase<H, KIND, C + 1, PD>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, jbase);
   }
 };
-template <int H, int KIND>
-struct ExitPhase<H, KIND, H - 1> {
+template <int H, int KIND, int PD>
+struct ExitPhase<H, KIND, H - 1, PD> {
   __device__ __forceinline__ static void run(const WideArgs &, const WideProblem &, float *, int,
-                                             float (&)[H], const float (&)[H], Sweep &, float, int,
-                                             int, float &, int) {}
+                                             float (&)[H], const float (&)[H], Sweep<PD> &, float,
+                                             int, int, float &, int) {}
 };
 
 // One problem per lane: all tiles.  Returns the lane's result (+inf if the
@@ -242,7 +345,8 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
     }
     const int jb_lo = i0 - r > 0 ? i0 - r : 0;
     const int jb_hi = i0 + H - 1 + r < lcol - 1 ? i0 + H - 1 + r : lcol - 1;
-    Sweep s;
+    constexpr int PD = H >= 64 ? 4 : 8;
+    Sweep<PD> s;
     s.j = jb_lo > lo ? jb_lo : lo;
     s.jend = jb_hi;
     s.jmand = hi + 1;
@@ -260,14 +364,24 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
     if (t == 0) s.diag0 = (s.j == 0) ? 0.0f : kInf;
     else s.diag0 = (s.j - 1 >= bv_lo && s.j - 1 <= bv_hi) ? Bw[(int64_t)s.j * kWave + lane] : kInf;
     const int jstart = s.j;
+#pragma unroll
+    for (int k = 0; k < PD; ++k) wide_fetch<KIND, PD>(a, p, Bw, lane, s, s.j + k, s.qtop[k], s.qcv[k]);
     // entering triangle [i0-r, i0-r+H-2], full columns up to i0+r, exiting triangle
     if (BANDED) {
-      EnterPhase<H, KIND, 0>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 - r);
-      while (s.go && s.j <= i0 + r) wide_step<H, KIND, 0, H - 1>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
-      ExitPhase<H, KIND, 0>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 + r + 1);
+      EnterPhase<H, KIND, 0, PD>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 - r);
+      while (s.go && s.j <= i0 + r) {
+        if (H <= 32 && wide_pair_ok(s, i0 + r, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ub);
+        else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+      }
+      ExitPhase<H, KIND, 0, PD>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 + r + 1);
     } else {
       // the window covers the whole matrix: every column is a full column
-      while (s.go) wide_step<H, KIND, 0, H - 1>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+      while (s.go) {
+        // (two-column steps only pay off while the doubled state still fits
+        // in registers at a useful occupancy)
+        if (H <= 32 && wide_pair_ok(s, s.jend, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ub);
+        else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+      }
     }
     evaluated += s.evaluated;
     computed += s.computed;

@@ -34,9 +34,11 @@ int wide_rows_for(int r, int lrow, int lcol) {
 // columns only; banded windows use the triangle-unrolled tiles.
 hipError_t launch_wide(int kind, int rows, const WideArgs &a, int grid, hipStream_t st) {
   if (grid <= 0 || a.ntasks <= 0) return hipSuccess;
-  (void)rows;
   switch (wide_rows_for(a.r, a.lrow, a.lcol)) {
-    case kWideFullRows: return launch_wide_h<kWideFullRows, false>(kind, a, grid, st);
+    case kWideFullRows:
+      // whole-matrix windows: 32- or 64-row tiles (rows option, default 64)
+      if (rows == 32) return launch_wide_h<32, false>(kind, a, grid, st);
+      return launch_wide_h<64, false>(kind, a, grid, st);
     case kWideBandRows: return launch_wide_h<kWideBandRows, true>(kind, a, grid, st);
     case 4: return launch_wide_h<4, true>(kind, a, grid, st);
     default: return launch_wide_h<2, true>(kind, a, grid, st);
