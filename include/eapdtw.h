@@ -113,6 +113,10 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *   "lanes_per_problem": reserved (1)
  *   "graph"          : 1 = replay batched searches from a captured hipGraph
  *   "force_wide"     : 1 = use the wide-window kernel even for narrow windows
+ *   "border"         : 1 = the band search sweeps each row group only between
+ *                      its pruning borders (windows >= 24; default), 0 = the
+ *                      whole band with row-minimum abandoning; both give the
+ *                      same bits for every distance at most the bound
  * Returns EINVAL for an unknown key or value. */
 int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
 int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);

@@ -38,7 +38,8 @@ struct eapdtw_ctx {
   int64_t lanes_per_problem = 1;
   int64_t graph = 1;
   int64_t force_wide = 0;
-  int64_t seed_stride = 4;
+  int64_t seed_stride = 16;
+  int64_t border = 1;
   int64_t seed_window = 8;
   int64_t batch_grid = 2048;
   int64_t batch_chunk = 4;
@@ -290,6 +291,7 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "batch_grid")) return &ctx->batch_grid;
   if (!strcmp(key, "batch_chunk")) return &ctx->batch_chunk;
   if (!strcmp(key, "batch_seed_stride")) return &ctx->batch_seed_stride;
+  if (!strcmp(key, "border")) return &ctx->border;
   return nullptr;
 }
 
@@ -299,7 +301,9 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   if (!slot) return fail(ctx, EAPDTW_EINVAL, std::string("unknown option ") + (key ? key : "(null)"));
   bool ok = true;
   if (!strcmp(key, "check_interval")) ok = value >= 1 && value <= (1 << 20);
-  else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide")) ok = value == 0 || value == 1;
+  else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide") ||
+           !strcmp(key, "border"))
+    ok = value == 0 || value == 1;
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
   else if (!strcmp(key, "lanes_per_problem")) ok = value == 1;
@@ -584,14 +588,14 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     NNArgs e = a;
     e.bsf = bsf + 1;
     e.block_stride = (int)sstr;
-    HIPCHK(nn_band_launcher(0)(e, (nblk + sstr - 1) / sstr, 8, false, st));
+    HIPCHK(nn_band_launcher(0)(e, (nblk + sstr - 1) / sstr, 8, false, false, st));
     const int64_t rs = r < ctx->seed_window ? r : ctx->seed_window;
     NNArgs s = a;
     s.bsf = bsf;
     s.center = bsf + 1;
     s.bsf_init = bsf + 1;
     s.bound_only = 1;
-    HIPCHK(nn_band_launcher((int)rs)(s, 1, pick_rows(ctx, (int)rs), false, st));
+    HIPCHK(nn_band_launcher((int)rs)(s, 1, pick_rows(ctx, (int)rs), false, false, st));
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev2, st));
   if (use_band(ctx, r)) {
@@ -599,7 +603,8 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     a.counters = cnt;
     a.fixed_ub = fixed_ub;
     a.dists = dists;
-    HIPCHK(nn_band_launcher((int)r)(a, nblk, dists ? 4 : pick_rows(ctx, (int)r), dists != nullptr, st));
+    HIPCHK(nn_band_launcher((int)r)(a, nblk, dists ? 4 : pick_rows(ctx, (int)r), dists != nullptr,
+                                    ctx->border != 0, st));
   } else {
     WideArgs w{};
     w.lrow = (int)m;

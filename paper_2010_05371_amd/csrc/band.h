@@ -19,11 +19,13 @@
 // dead stops.  The value of a cell <= ub never depends on a cell > ub, so the
 // surviving values are exactly those of the unpruned float32 recurrence.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 
 namespace eapdtw {
 
-__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0ull; }
 
 // Wave-uniform read-only data (the normalised query) is read through the
 // scalar cache: addresses in the constant address space select s_load.
@@ -50,6 +52,15 @@ __device__ __forceinline__ double wave_excl_scan_f64(double v, int lane) {
 }
 
 __device__ __forceinline__ float fmin3(float a, float b, float c) { return fminf(fminf(a, b), c); }
+
+// Minimum of cell values through their bit patterns: cells are never negative
+// (or NaN), and for such floats the unsigned order of the bits is the numeric
+// order, so the integer minimum needs no NaN quieting of its operands.
+__device__ __forceinline__ uint32_t cell_bits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ uint32_t umin3(uint32_t a, uint32_t b, uint32_t c) {
+  const uint32_t t = a < b ? a : b;
+  return t < c ? t : c;
+}
 
 // Window statistics of the 64 consecutive offsets kb..kb+63 (lane l <-> kb+l),
 // window length m.  Sums are taken in float64 relative to the pivot x[kb] so
@@ -127,6 +138,19 @@ struct Cols {
   int lane_off;
 };
 
+// Waits for the scalar loads of a column chunk before the next chunk's loads
+// are issued.  Scalar loads may return out of order, so a wait for an older
+// one is a wait for all; settling the chunk in use first leaves the next
+// chunk's loads in flight while it is computed.  Per-lane (vector) loads
+// complete in order and need no settling.
+template <class Ptr, int N>
+__device__ __forceinline__ void settle(const float (&c)[N]) {
+  if constexpr (std::is_same<Ptr, ConstF *>::value) {
+#pragma unroll
+    for (int t = 0; t < N; ++t) asm volatile("" ::"s"(c[t]));
+  }
+}
+
 // One group of U rows, swept column by column (group column s is matrix
 // column j = i0 + s - R).  Column values are fetched one chunk of kColChunk
 // columns ahead of their use, which bounds the registers that hold them.
@@ -149,6 +173,7 @@ __device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     float nxt[CH];
+    settle<Ptr>(cur);
     if (c + 1 < NCH) {
       Ptr pn = opaque(cs.base + (int64_t)(c + 1) * CH * stride);
 #pragma unroll
@@ -195,6 +220,201 @@ __device__ __forceinline__ float band_min(const float (&v)[2 * R + 1]) {
   return m;
 }
 
+// ---------------------------------------------------------------------------
+// Pruning borders kept per wave (Section 3: a cell above the bound can only
+// feed cells above the bound, so a row only needs the cells between the
+// first one reachable from the previous row's live cells and the last one
+// whose left neighbour is live).  The band of the last swept row is cut into
+// diagonal chunks of kBorderChunk cells; Border holds the first and last
+// chunk that hold a cell at most the bound in some live lane.  Every register
+// outside the swept range holds a value above the bound, and the recurrence
+// keeps cells at most the bound exact whatever those values are, so the
+// bordered sweep gives bit-identical results for every cell at most the bound.
+constexpr int kBorderChunk = 8;
+constexpr int kBorderMinR = 24;  // narrower bands gain too little to pay for the borders
+
+struct Border {
+  int lo, hi;  // diagonal chunks [kBorderChunk * lo, kBorderChunk * (hi + 1))
+};
+
+// One group of U rows swept over the group columns that can hold live cells.
+// Group column s (row u computes diagonal s - u) starts at kBorderChunk * lo - 1,
+// the column of the first diagonal a live cell of the previous row can reach;
+// the columns up to the one where row U - 1 passes the previous row's last
+// live chunk are always swept; after that the sweep stops at the first check
+// point (every half chunk) where the last cell of every row is above the
+// bound in every live lane.  Returns the last swept column.
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1, every index a
+// compile-time constant (register arrays stay statically indexed).
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Bitwise OR over the wave (row shifts, then row broadcasts into lane 63).
+__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// One group of U rows swept over the group columns that can hold live cells.
+// Columns are taken in units of kBorderChunk: unit k covers group columns
+// [CH k - 1, CH k + CH - 1) (row u computes diagonal s - u at column s).  The
+// first unit is b.lo: its first column reaches the diagonal just left of the
+// previous row's first live chunk.  Units up to the one where row U - 1
+// passes the previous row's last live chunk are always swept; after the last
+// unit the sweep extends by one unit while the last cell of some row is at
+// most the bound in some lane.  Returns the last swept column.
+template <int R, int U, class Ptr>
+__device__ __forceinline__ int sweep_group_border(float (&v)[2 * R + 1], const float (&rv)[U],
+                                                  Cols<Ptr> cs, const Border &b, uint32_t ubits,
+                                                  uint64_t amask) {
+  constexpr int W = 2 * R + 1;
+  constexpr int NS = W + U - 1;
+  constexpr int CH = kBorderChunk;
+  constexpr int NU = (NS + CH) / CH;
+  const int u0 = b.lo;
+  int uend = (CH * (b.hi + 1) + U - 1) / CH;  // unit holding column CH (hi + 1) + U - 2
+  uend = uend < NU - 1 ? uend : NU - 1;
+  // column values of even units in qa, odd units in qb
+  float qa[CH], qb[CH];
+  {
+    Ptr p0 = opaque(cs.base + (int64_t)(CH * u0 - 1) * cs.stride);
+    if (u0 & 1) {
+#pragma unroll
+      for (int t = 0; t < CH; ++t) qb[t] = p0[t * cs.stride + cs.lane_off];
+    } else {
+#pragma unroll
+      for (int t = 0; t < CH; ++t) qa[t] = p0[t * cs.stride + cs.lane_off];
+    }
+  }
+  static_for<NU>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if ((unsigned)(k - u0) > (unsigned)(uend - u0)) return;  // k outside [u0, uend]
+    float(&cur)[CH] = (k & 1) ? qb : qa;
+    float(&nxt)[CH] = (k & 1) ? qa : qb;
+    settle<Ptr>(cur);
+    if constexpr (k + 1 < NU) {
+      Ptr pn = opaque(cs.base + (int64_t)(CH * (k + 1) - 1) * cs.stride);
+#pragma unroll
+      for (int t = 0; t < CH; ++t) nxt[t] = pn[t * cs.stride + cs.lane_off];
+      // keeps the loads here: they are not sunk into the next unit's block
+      // (where their latency would be exposed)
+      asm volatile("" ::: "memory");
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr int sb = CH * k - 1;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int s = sb + t;
+      if (s < 0 || s >= NS) continue;
+      const float cvl = cur[t];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int d = s - u;
+        if (d < 0 || d >= W) continue;
+        const float left = (d > 0) ? v[d > 0 ? d - 1 : 0] : kInf;
+        const float top = (d < W - 1) ? v[d < W - 1 ? d + 1 : 0] : kInf;
+        const float diff = cvl - rv[u];
+        v[d] = __builtin_fmaf(diff, diff, fmin3(left, top, v[d]));
+      }
+    }
+    // volatile asm keeps its order, so the next unit's loads cannot be
+    // hoisted above these cells
+#pragma unroll
+    for (int j = 0; j < CH + U - 1; ++j) {
+      const int d = sb - (U - 1) + j;
+      if (d >= 0 && d < W) asm volatile("" : "+v"(v[d >= 0 && d < W ? d : 0]));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (k + 1 < NU) {
+      if (k == uend) {
+        // the last cells of the rows, at column sb + CH - 1
+        uint32_t mn = cell_bits(kInf);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int d = sb + CH - 1 - u;
+          if (d >= 0 && d < W) mn = min(mn, cell_bits(v[d >= 0 && d < W ? d : 0]));
+        }
+        if (__builtin_amdgcn_ballot_w64(mn <= ubits) & amask) uend = k + 1;
+      }
+    }
+  });
+  const int slast = CH * uend + CH - 2;
+  return slast < NS - 1 ? slast : NS - 1;
+}
+
+// Minimum of diagonal chunk C of the band (bit patterns).
+template <int R, int C>
+__device__ __forceinline__ uint32_t chunk_min_bits(const float (&v)[2 * R + 1]) {
+  constexpr int W = 2 * R + 1;
+  constexpr int CH = kBorderChunk;
+  uint32_t mn = cell_bits(v[CH * C < W ? CH * C : 0]);
+#pragma unroll
+  for (int t = 1; t < CH; t += 2) {
+    const int d0 = CH * C + t, d1 = d0 + 1;
+    if (d1 < W && t + 1 < CH)
+      mn = umin3(mn, cell_bits(v[d0 < W ? d0 : 0]), cell_bits(v[d1 < W ? d1 : 0]));
+    else if (d0 < W)
+      mn = min(mn, cell_bits(v[d0 < W ? d0 : 0]));
+  }
+  return mn;
+}
+
+// Borders of the last swept row.  Registers outside the swept range hold
+// values above the bound, so every chunk can be tested without a range
+// check.  Returns whether this lane still has a live cell; hi < 0 when no
+// lane has one.
+template <int R>
+__device__ __forceinline__ bool border_update(const float (&v)[2 * R + 1], Border &b,
+                                              uint32_t ubits, bool alive) {
+  constexpr int NCD = (2 * R + 1 + kBorderChunk - 1) / kBorderChunk;
+  static_assert(NCD <= 32, "chunk mask is 32 bits");
+  uint32_t mask = 0;
+  static_for<NCD>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    mask |= (chunk_min_bits<R, c>(v) <= ubits) ? (1u << c) : 0u;
+  });
+  mask = alive ? mask : 0u;
+  const uint32_t all = wave_or(mask);
+  b.lo = all ? __builtin_ctz(all) : -1;
+  b.hi = all ? 31 - __builtin_clz(all) : -1;
+  return mask != 0u;
+}
+
+// Cells of rows [i0, i0 + U) swept over group columns [s0, s1]: in the band,
+// and in the matrix (lcol columns) for the evaluated count.
+template <int U>
+__device__ __forceinline__ void swept_cells(int i0, int s0, int s1, int lcol, int r, int &band,
+                                            int &matrix) {
+  const int w = 2 * r + 1;
+  if (s0 >= U - 1 && s1 <= w - 1 && i0 >= r && i0 + U <= lcol - r) {
+    band = matrix = U * (s1 - s0 + 1);  // every row inside band and matrix
+    return;
+  }
+  band = matrix = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = i0 + u;
+    int lo = s0 - u, hi = s1 - u;
+    lo = lo > 0 ? lo : 0;
+    hi = hi < w - 1 ? hi : w - 1;
+    band += hi >= lo ? hi - lo + 1 : 0;
+    const int mlo = lo > r - i ? lo : r - i;
+    const int mhi = hi < r + lcol - 1 - i ? hi : r + lcol - 1 - i;
+    matrix += mhi >= mlo ? mhi - mlo + 1 : 0;
+  }
+}
+
 // In-matrix cells of rows [i0, i0+u) (scalar bookkeeping for the counters).
 template <int U>
 __device__ __forceinline__ int rows_cells(int i0, int lcol, int r) {
@@ -216,7 +436,7 @@ __device__ __forceinline__ float load_bsf_dist(const unsigned long long *bsf) {
 // value per column, read through the scalar cache).
 // DISTS = true writes every candidate's early-abandoned distance against the
 // fixed bound instead of updating the shared best-so-far.
-template <int R, int U, bool DISTS>
+template <int R, int U, bool DISTS, bool BORDER = false>
 __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   constexpr int W = 2 * R + 1;
   const int lane = threadIdx.x;
@@ -249,21 +469,61 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
 #pragma unroll
   for (int d = 0; d < W; ++d) v[d] = kInf;
   v[R] = 0.0f;  // M(0,0) lies on diagonal R of the row above the first row
+  Border bd{R / kBorderChunk, R / kBorderChunk};
 
-  float ub = DISTS ? a.fixed_ub : load_bsf_dist(a.bsf);
+  // (+ 0 turns a bound of -0 into +0, which the bit-pattern comparisons of
+  // the bordered sweep need)
+  float ub = (DISTS ? a.fixed_ub : load_bsf_dist(a.bsf)) + 0.0f;
   if (!DISTS && a.center && a.bsf_init) ub = fminf(ub, best_dist(*a.bsf_init));
   bool alive = active && ub >= 0.0f;
   int since = 0;
   uint64_t evaluated = 0, computed = 0;
   const int mg = m - m % U;  // rows covered by full groups
-  int i0 = 0;
   bool stopped = !wave_any(alive);
 
   float rv_next[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) rv_next[u] = (u < mg) ? xk[u] : 0.0f;
 
-  for (; i0 < mg && !stopped; i0 += U) {
+  // One group of G rows starting at row i: the shared best-so-far is read
+  // before the sweep and applied after it, so its latency hides behind the
+  // sweep.
+  auto group = [&](auto gtag, int i, const float *rvg) {
+    constexpr int G = decltype(gtag)::value;
+    const bool reload = !DISTS && ++since >= a.check_interval;
+    unsigned long long bnext = 0;
+    if (reload) bnext = __hip_atomic_load(a.bsf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const Cols<ConstF *> cols{as_const(a.qpad + kColPad + i - R), 1, 0};
+    int band, mat;
+    float rvl[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) rvl[u] = rvg[u];
+    int slast = W + G - 2;
+    if constexpr (BORDER) {
+      slast = sweep_group_border<R, G>(v, rvl, cols, bd, cell_bits(ub),
+                                       __builtin_amdgcn_ballot_w64(alive));
+      swept_cells<G>(i, kBorderChunk * bd.lo - 1, slast, m, R, band, mat);
+    } else {
+      sweep_group<R, G>(v, rvl, cols);
+      band = G * W;
+      mat = rows_cells<G>(i, m, R);
+    }
+    evaluated += (uint64_t)mat * (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(alive));
+    computed += (uint64_t)band * kWave;
+    if (reload) {
+      since = 0;
+      ub = fminf(ub, best_dist(bnext));
+    }
+    if constexpr (BORDER) {
+      alive = border_update<R>(v, bd, cell_bits(ub), alive);
+      if (bd.hi < 0) stopped = true;
+    } else {
+      alive = alive && band_min<R>(v) <= ub;
+      if (!wave_any(alive)) stopped = true;
+    }
+  };
+
+  for (int i0 = 0; i0 < mg && !stopped; i0 += U) {
     float rv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) rv[u] = znorm_value(rv_next[u], mu_hi, mu_lo, inv);
@@ -271,26 +531,12 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
 #pragma unroll
       for (int u = 0; u < U; ++u) rv_next[u] = xk[i0 + U + u];
     }
-    sweep_group<R, U>(v, rv, Cols<ConstF *>{as_const(a.qpad + kColPad + i0 - R), 1, 0});
-    const int cells = rows_cells<U>(i0, m, R);
-    evaluated += (uint64_t)cells * (uint64_t)__popcll(__ballot(alive));
-    computed += (uint64_t)cells * kWave;
-    if (!DISTS && ++since >= a.check_interval) {
-      since = 0;
-      ub = load_bsf_dist(a.bsf);
-    }
-    alive = alive && band_min<R>(v) <= ub;
-    if (!wave_any(alive)) stopped = true;
+    group(std::integral_constant<int, U>{}, i0, rv);
   }
   // remaining rows, one at a time
   for (int i = mg; i < m && !stopped; ++i) {
-    float rv1[1] = {znorm_value(xk[i], mu_hi, mu_lo, inv)};
-    sweep_group<R, 1>(v, rv1, Cols<ConstF *>{as_const(a.qpad + kColPad + i - R), 1, 0});
-    const int cells = row_cells(i, m, R);
-    evaluated += (uint64_t)cells * (uint64_t)__popcll(__ballot(alive));
-    computed += (uint64_t)cells * kWave;
-    alive = alive && band_min<R>(v) <= ub;
-    if (!wave_any(alive)) stopped = true;
+    const float rv1[1] = {znorm_value(xk[i], mu_hi, mu_lo, inv)};
+    group(std::integral_constant<int, 1>{}, i, rv1);
   }
 
   const float d = v[R];
@@ -311,9 +557,9 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   }
 }
 
-template <int R, int U, bool DISTS>
+template <int R, int U, bool DISTS, bool BORDER>
 __global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
-  nn_band_body<R, U, DISTS>(a, blockIdx.x);
+  nn_band_body<R, U, DISTS, BORDER>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,7 +666,7 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
 // Host-side launchers (explicitly instantiated per window in band_r*.hip).
 template <int R>
 hipError_t launch_nn_band(const NNArgs &a, int64_t nblocks, int rows_per_group, bool dists,
-                          hipStream_t st);
+                          bool border, hipStream_t st);
 template <int R>
 hipError_t launch_pair_band(const PairArgs &a, int64_t nblocks, int rows_per_group,
                             hipStream_t st);

@@ -12,16 +12,22 @@ namespace eapdtw {
 
 template <int R>
 hipError_t launch_nn_band(const NNArgs &a, int64_t nblocks, int rows_per_group, bool dists,
-                          hipStream_t st) {
+                          bool border, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)nblocks), block(kWave);
-  if (dists) {
-    hipLaunchKernelGGL((nn_band_kernel<R, 4, true>), grid, block, 0, st, a);
+  constexpr bool kB = R >= kBorderMinR;  // bordered variants exist from this window on
+  if (kB && border) {
+    if (dists)
+      hipLaunchKernelGGL((nn_band_kernel<R, 4, true, kB>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((nn_band_kernel<R, 4, false, kB>), grid, block, 0, st, a);
+  } else if (dists) {
+    hipLaunchKernelGGL((nn_band_kernel<R, 4, true, false>), grid, block, 0, st, a);
   } else {
     switch (rows_per_group) {
-      case 2: hipLaunchKernelGGL((nn_band_kernel<R, 2, false>), grid, block, 0, st, a); break;
-      case 8: hipLaunchKernelGGL((nn_band_kernel<R, 8, false>), grid, block, 0, st, a); break;
-      default: hipLaunchKernelGGL((nn_band_kernel<R, 4, false>), grid, block, 0, st, a); break;
+      case 2: hipLaunchKernelGGL((nn_band_kernel<R, 2, false, false>), grid, block, 0, st, a); break;
+      case 8: hipLaunchKernelGGL((nn_band_kernel<R, 8, false, false>), grid, block, 0, st, a); break;
+      default: hipLaunchKernelGGL((nn_band_kernel<R, 4, false, false>), grid, block, 0, st, a); break;
     }
   }
   return hipGetLastError();
@@ -37,7 +43,7 @@ hipError_t launch_pair_band(const PairArgs &a, int64_t nblocks, int rows_per_gro
 }
 
 #define EAPDTW_INST(R)                                                                       \
-  template hipError_t launch_nn_band<R>(const NNArgs &, int64_t, int, bool, hipStream_t); \
+  template hipError_t launch_nn_band<R>(const NNArgs &, int64_t, int, bool, bool, hipStream_t); \
   template hipError_t launch_pair_band<R>(const PairArgs &, int64_t, int, hipStream_t);
 
 #if EAPDTW_R_LO <= 0 && 0 <= EAPDTW_R_HI

@@ -5,7 +5,7 @@
 namespace eapdtw {
 
 #define EAPDTW_DECL(R)                                                                          \
-  extern template hipError_t launch_nn_band<R>(const NNArgs &, int64_t, int, bool, hipStream_t); \
+  extern template hipError_t launch_nn_band<R>(const NNArgs &, int64_t, int, bool, bool, hipStream_t); \
   extern template hipError_t launch_pair_band<R>(const PairArgs &, int64_t, int, hipStream_t);
 #define EAPDTW_ROW8(a) EAPDTW_DECL(a) EAPDTW_DECL(a + 1) EAPDTW_DECL(a + 2) EAPDTW_DECL(a + 3) \
   EAPDTW_DECL(a + 4) EAPDTW_DECL(a + 5) EAPDTW_DECL(a + 6) EAPDTW_DECL(a + 7)

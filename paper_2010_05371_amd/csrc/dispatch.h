@@ -4,8 +4,9 @@
 
 namespace eapdtw {
 
+// border selects the bordered sweep (windows of at least kBorderMinR only).
 typedef hipError_t (*NNLaunchFn)(const NNArgs &, int64_t nblocks, int rows_per_group, bool dists,
-                                 hipStream_t);
+                                 bool border, hipStream_t);
 typedef hipError_t (*PairLaunchFn)(const PairArgs &, int64_t nblocks, int rows_per_group,
                                    hipStream_t);
 
