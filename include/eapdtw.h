@@ -99,7 +99,8 @@ int eapdtw_set_stream(eapdtw_ctx *ctx, void *hip_stream);
 const char *eapdtw_last_error(const eapdtw_ctx *ctx);
 
 /* Tuning knobs (for tests and the autotuner).  Keys:
- *   "check_interval" : row groups between reloads of the shared best-so-far (>=1)
+ *   "check_interval" : row groups between reloads of the shared best-so-far
+ *                      (>= 1; 0 = chosen per window, the default)
  *   "seed"           : 1 = seed the best-so-far from a window-0 pass and one
  *                      workgroup of candidates around its best offset (default),
  *                      0 = start the search from +inf
@@ -117,6 +118,9 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *                      its pruning borders (windows >= 24; default), 0 = the
  *                      whole band with row-minimum abandoning; both give the
  *                      same bits for every distance at most the bound
+ *   "ed"             : 1 = window-0 searches and seeding passes use the
+ *                      squared-Euclidean kernel (default), 0 = the band kernel
+ *                      (same bits)
  * Returns EINVAL for an unknown key or value. */
 int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
 int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);

@@ -31,7 +31,7 @@ struct eapdtw_ctx {
   size_t pinned_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
   // options
-  int64_t check_interval = 1;
+  int64_t check_interval = 0;  // 0: chosen per window
   int64_t seed = 1;
   int64_t rows_per_group = 0;
   int64_t wide_rows = 0;
@@ -39,7 +39,9 @@ struct eapdtw_ctx {
   int64_t graph = 1;
   int64_t force_wide = 0;
   int64_t seed_stride = 16;
+  uint32_t epoch = 0;  // numbers the searches (non-finite flag values)
   int64_t border = 1;
+  int64_t ed = 1;
   int64_t seed_window = 8;
   int64_t batch_grid = 2048;
   int64_t batch_chunk = 4;
@@ -50,6 +52,9 @@ struct eapdtw_ctx {
   hipGraphExec_t batch_exec = nullptr;
   uint64_t batch_key = 0;
   hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
+  // second stream on which the seeding workgroup runs beside the search
+  hipStream_t seed_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 static thread_local std::string g_create_error;
@@ -109,6 +114,9 @@ int ensure_scratch(eapdtw_ctx *ctx, size_t need) {
     return fail(ctx, EAPDTW_ENOMEM, "device scratch allocation failed");
   }
   ctx->scratch_cap = cap;
+  // the non-finite flag word after the counters: no epoch matches zero
+  HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long *>(ctx->scratch) + kCntWords, 0ull, 1,
+                         ctx->stream));
   return EAPDTW_OK;
 }
 
@@ -260,6 +268,12 @@ void eapdtw_destroy(eapdtw_ctx *ctx) {
   if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
   if (ctx->batch_buf) (void)hipFree(ctx->batch_buf);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->seed_stream) {
+    if (!ctx->poisoned) (void)hipStreamSynchronize(ctx->seed_stream);
+    (void)hipStreamDestroy(ctx->seed_stream);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
 }
 
@@ -292,6 +306,7 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "batch_chunk")) return &ctx->batch_chunk;
   if (!strcmp(key, "batch_seed_stride")) return &ctx->batch_seed_stride;
   if (!strcmp(key, "border")) return &ctx->border;
+  if (!strcmp(key, "ed")) return &ctx->ed;
   return nullptr;
 }
 
@@ -300,9 +315,9 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   int64_t *slot = option_slot(ctx, key);
   if (!slot) return fail(ctx, EAPDTW_EINVAL, std::string("unknown option ") + (key ? key : "(null)"));
   bool ok = true;
-  if (!strcmp(key, "check_interval")) ok = value >= 1 && value <= (1 << 20);
+  if (!strcmp(key, "check_interval")) ok = value >= 0 && value <= (1 << 20);
   else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide") ||
-           !strcmp(key, "border"))
+           !strcmp(key, "border") || !strcmp(key, "ed"))
     ok = value == 0 || value == 1;
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
@@ -328,7 +343,8 @@ int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value) {
 // --------------------------------------------------------------------------- pair engine
 
 // Every call's scratch starts with the striped counters.
-constexpr size_t kCntBytes = sizeof(unsigned long long) * kCntWords;
+// ... followed by one 256-byte line holding the non-finite flag word.
+constexpr size_t kCntBytes = sizeof(unsigned long long) * kCntWords + 256;
 
 static bool use_band(const eapdtw_ctx *ctx, int64_t r) { return r <= kBandRMax && !ctx->force_wide; }
 
@@ -564,8 +580,10 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
   hipStream_t st = ctx->stream;
   const int64_t K = n - m + 1;
   const int64_t nblk = (K + kWave - 1) / kWave;
-  HIPCHK(launch_query_prep(query, (int)m, qpad, cnt, st));
-  if (!dists) HIPCHK(launch_check_finite(series, n, cnt, st));
+  if (++ctx->epoch == 0) ++ctx->epoch;
+  HIPCHK(launch_search_prep(query, (int)m, qpad, dists ? nullptr : series, n, cnt,
+                            dists ? nullptr : bsf, dists ? 0 : 2,
+                            reinterpret_cast<unsigned *>(cnt + kCntWords), ctx->epoch, st));
   NNArgs a{};
   a.x = series;
   a.n = n;
@@ -575,7 +593,8 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
   a.k_end = K;
   a.check_interval = (int)ctx->check_interval;
   a.block_stride = 1;
-  if (!dists && ctx->seed && r > 0) {
+  bool joined = true;
+  if (!dists && ctx->seed) {
     // Bound seeding.  A candidate's DTW under a narrower window is never below
     // its DTW under the search window (fewer admissible paths), so
     //  1. the window-0 (squared Euclidean) pass over every seed_stride-th
@@ -584,18 +603,43 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     //     min(r, seed_window), tightens it.
     // Both record distance-only bounds; the search itself then finds the
     // exact minimum and its offset (the true minimum is never abandoned).
+    // The band search starts from the window-0 bound and the seeding
+    // workgroup runs beside it on a second stream: its bound reaches the
+    // search's waves through their periodic reads of the best-so-far.
     const int64_t sstr = ctx->seed_stride;
     NNArgs e = a;
     e.bsf = bsf + 1;
     e.block_stride = (int)sstr;
-    HIPCHK(nn_band_launcher(0)(e, (nblk + sstr - 1) / sstr, 8, false, false, st));
+    if (ctx->ed)
+      HIPCHK(launch_ed_search(e, (nblk + sstr - 1) / sstr, false, st));
+    else
+      HIPCHK(nn_band_launcher(0)(e, (nblk + sstr - 1) / sstr, 8, false, false, st));
     const int64_t rs = r < ctx->seed_window ? r : ctx->seed_window;
     NNArgs s = a;
     s.bsf = bsf;
     s.center = bsf + 1;
     s.bsf_init = bsf + 1;
     s.bound_only = 1;
-    HIPCHK(nn_band_launcher((int)rs)(s, 1, pick_rows(ctx, (int)rs), false, false, st));
+    hipStream_t ss = st;
+    if (use_band(ctx, r)) {
+      if (!ctx->seed_stream) {
+        HIPCHK(hipStreamCreateWithFlags(&ctx->seed_stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+      }
+      HIPCHK(hipEventRecord(ctx->ev_fork, st));
+      HIPCHK(hipStreamWaitEvent(ctx->seed_stream, ctx->ev_fork, 0));
+      ss = ctx->seed_stream;
+      a.bsf_init = bsf + 1;  // the search's waves start from the window-0 bound
+    }
+    if (rs == 0 && ctx->ed)
+      HIPCHK(launch_ed_search(s, 1, false, ss));
+    else
+      HIPCHK(nn_band_launcher((int)rs)(s, 1, pick_rows(ctx, (int)rs), false, false, ss));
+    if (ss != st) {
+      HIPCHK(hipEventRecord(ctx->ev_join, ss));
+      joined = false;
+    }
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev2, st));
   if (use_band(ctx, r)) {
@@ -603,8 +647,11 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     a.counters = cnt;
     a.fixed_ub = fixed_ub;
     a.dists = dists;
-    HIPCHK(nn_band_launcher((int)r)(a, nblk, dists ? 4 : pick_rows(ctx, (int)r), dists != nullptr,
-                                    ctx->border != 0, st));
+    if (r == 0 && ctx->ed)
+      HIPCHK(launch_ed_search(a, nblk, dists != nullptr, st));
+    else
+      HIPCHK(nn_band_launcher((int)r)(a, nblk, dists ? 4 : pick_rows(ctx, (int)r), dists != nullptr,
+                                      ctx->border != 0, st));
   } else {
     WideArgs w{};
     w.lrow = (int)m;
@@ -627,6 +674,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     HIPCHK(launch_wide(kWideSearch, (int)ctx->wide_rows, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev3, st));
+  if (!joined) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
   return EAPDTW_OK;
 }
 
@@ -653,8 +701,6 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
   unsigned long long *bsf = at<unsigned long long>(ctx, o_bsf);
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
   if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
-  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
-  HIPCHK(launch_fill_u64(bsf, pack_best(INFINITY, 0xffffffffu), 2, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
                     grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr);
   if (rc) return rc;
@@ -664,7 +710,8 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
   if (rc) return rc;
   const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned);
   const unsigned long long best = *reinterpret_cast<unsigned long long *>(ctx->pinned + (o_bsf - o_cnt));
-  if (counter_sum(hc, kCntNonFinite)) return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
+  if (*reinterpret_cast<const unsigned *>(hc + kCntWords) == ctx->epoch)
+    return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
   *out_offset = best_offset(best) == 0xffffffffu ? -1 : (int64_t)best_offset(best);
   *out_dist = (double)best_dist(best);
   if (stats)
@@ -695,7 +742,6 @@ int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
   hipStream_t st = ctx->stream;
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
   if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
-  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q),
                     at<unsigned long long>(ctx, o_bsf), cnt, out, ub,
                     grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr);

@@ -26,15 +26,44 @@ __global__ void znorm_kernel(const float *__restrict__ q, int m, float *__restri
   if (counters && bad && threadIdx.x == 0) atomicAdd(&counters[kCntNonFinite], (unsigned long long)bad);
 }
 
-hipError_t launch_query_prep(const float *q, int m, float *qpad, unsigned long long *counters,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(znorm_kernel, dim3(1), dim3(256), 0, st, q, m, qpad, kColPad, counters);
-  return hipGetLastError();
-}
-
 hipError_t launch_znorm(const float *x, int m, float *out, hipStream_t st) {
   hipLaunchKernelGGL(znorm_kernel, dim3(1), dim3(256), 0, st, x, m, out, 0,
                      (unsigned long long *)nullptr);
+  return hipGetLastError();
+}
+
+// Everything a search needs before its first pass, in one launch: workgroup 0
+// clears the counters, sets the best-so-far words to +inf and z-normalises
+// the query into its padded buffer; every workgroup checks a share of the
+// series.  A non-finite input stores this call's epoch into *flag (a racy
+// store of one value; the word needs no clearing between calls).
+__global__ void search_prep_kernel(const float *__restrict__ q, int m, float *__restrict__ qpad,
+                                   const float *__restrict__ x, int64_t n,
+                                   unsigned long long *cnt, unsigned long long *bsf, int nbsf,
+                                   unsigned *flag, unsigned epoch) {
+  __shared__ double sh[16];
+  bool bad = false;
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < kCntWords; t += blockDim.x) cnt[t] = 0ull;
+    if ((int)threadIdx.x < nbsf) bsf[threadIdx.x] = pack_best(kInf, 0xffffffffu);
+    bad = znorm_block(q, m, qpad, kColPad, sh) != 0;
+  }
+  if (x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+      bad = bad || not_finite(x[i]);
+  }
+  if (bad) *flag = epoch;
+}
+
+hipError_t launch_search_prep(const float *q, int m, float *qpad, const float *x, int64_t n,
+                              unsigned long long *cnt, unsigned long long *bsf, int nbsf,
+                              unsigned *flag, unsigned epoch, hipStream_t st) {
+  int64_t blocks = x ? (n + 255) / 256 : 1;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(search_prep_kernel, dim3((unsigned)blocks), dim3(256), 0, st, q, m, qpad, x,
+                     n, cnt, bsf, nbsf, flag, epoch);
   return hipGetLastError();
 }
 

@@ -73,21 +73,33 @@ __device__ __forceinline__ void wave_window_stats(const float *__restrict__ x, i
                                                   int64_t kb, int lane, double &mean,
                                                   double &sd) {
   const double pivot = (double)x[kb];
-  double s1 = 0.0, s2 = 0.0;
-  for (int t = lane; t < m; t += kWave) {
-    int64_t idx = kb + t;
-    idx = idx < n ? idx : n - 1;
-    double y = (double)x[idx] - pivot;
-    s1 += y;
-    s2 += y * y;
-  }
-  s1 = wave_sum_f64(s1);
-  s2 = wave_sum_f64(s2);
   int64_t ia = kb + lane, ib = kb + m + lane;
   ia = ia < n ? ia : n - 1;
   ib = ib < n ? ib : n - 1;
-  const double ya = (double)x[ia] - pivot;
-  const double yb = (double)x[ib] - pivot;
+  const float xa = x[ia], xb = x[ib];
+  // four loads in flight per step (the sums keep the lane's order t, t + 64, ...)
+  double s1 = 0.0, s2 = 0.0;
+  for (int t0 = 0; t0 < m; t0 += 4 * kWave) {
+    float xv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int64_t idx = kb + t0 + j * kWave + lane;
+      idx = idx < n ? idx : n - 1;
+      xv[j] = x[idx];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (t0 + j * kWave + lane < m) {
+        const double y = (double)xv[j] - pivot;
+        s1 += y;
+        s2 += y * y;
+      }
+    }
+  }
+  s1 = wave_sum_f64(s1);
+  s2 = wave_sum_f64(s2);
+  const double ya = (double)xa - pivot;
+  const double yb = (double)xb - pivot;
   const double e1 = wave_excl_scan_f64(ya, lane), e2 = wave_excl_scan_f64(ya * ya, lane);
   const double f1 = wave_excl_scan_f64(yb, lane), f2 = wave_excl_scan_f64(yb * yb, lane);
   const double sum1 = s1 + f1 - e1, sum2 = s2 + f2 - e2;
@@ -156,20 +168,22 @@ __device__ __forceinline__ void settle(const float (&c)[N]) {
 // columns ahead of their use, which bounds the registers that hold them.
 constexpr int kColChunk = 16;
 
+// first[] holds the group's first chunk of column values on entry.  With
+// next_base set, the last chunk's step loads the next group's first chunk
+// (whose base is next_base) into first[], so no group starts by waiting for
+// its column values.
 template <int R, int U, class Ptr>
 __device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (&rv)[U],
-                                            Cols<Ptr> cs) {
+                                            Cols<Ptr> cs, float (&first)[kColChunk],
+                                            Ptr next_base) {
   constexpr int W = 2 * R + 1;
   constexpr int NS = W + U - 1;
   constexpr int CH = kColChunk;
   constexpr int NCH = (NS + CH - 1) / CH;
   const int64_t stride = cs.stride;
   float cur[CH];
-  {
-    Ptr p0 = opaque(cs.base);
 #pragma unroll
-    for (int t = 0; t < CH; ++t) cur[t] = (t < NS) ? p0[t * stride + cs.lane_off] : 0.0f;
-  }
+  for (int t = 0; t < CH; ++t) cur[t] = first[t];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     float nxt[CH];
@@ -179,6 +193,10 @@ __device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (
 #pragma unroll
       for (int t = 0; t < CH; ++t)
         nxt[t] = ((c + 1) * CH + t < NS) ? pn[t * stride + cs.lane_off] : 0.0f;
+    } else {
+      Ptr pn = opaque(next_base);
+#pragma unroll
+      for (int t = 0; t < CH; ++t) first[t] = pn[t * stride + cs.lane_off];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -212,6 +230,23 @@ __device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (
   }
 }
 
+// Loads the first chunk of a group's column values (see sweep_group).
+template <int U, class Ptr>
+__device__ __forceinline__ void load_first(float (&first)[kColChunk], Cols<Ptr> cs) {
+  Ptr p0 = opaque(cs.base);
+#pragma unroll
+  for (int t = 0; t < kColChunk; ++t) first[t] = p0[t * cs.stride + cs.lane_off];
+}
+
+// Without look-ahead: the group's first chunk is loaded on entry.
+template <int R, int U, class Ptr>
+__device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (&rv)[U],
+                                            Cols<Ptr> cs) {
+  float first[kColChunk];
+  load_first<U>(first, cs);
+  sweep_group<R, U>(v, rv, cs, first, cs.base);
+}
+
 template <int R>
 __device__ __forceinline__ float band_min(const float (&v)[2 * R + 1]) {
   float m = v[0];
@@ -231,6 +266,26 @@ __device__ __forceinline__ float band_min(const float (&v)[2 * R + 1]) {
 // keeps cells at most the bound exact whatever those values are, so the
 // bordered sweep gives bit-identical results for every cell at most the bound.
 constexpr int kBorderChunk = 8;
+constexpr int kStageRows = 512;  // rows of the series staged in LDS per copy
+
+// Copies src[min(t, lim)] to dst[t] for t < N: every lane's loads are issued
+// before the first store, so the copy costs one memory round trip.
+template <int N>
+__device__ __forceinline__ void stage_copy(float *dst, const float *__restrict__ src, int64_t lim,
+                                           int lane) {
+  constexpr int NJ = (N + kWave - 1) / kWave;
+  float tmp[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int t = lane + kWave * j;
+    tmp[j] = src[t < lim ? t : lim];
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int t = lane + kWave * j;
+    if (t < N) dst[t] = tmp[j];
+  }
+}
 constexpr int kBorderMinR = 24;  // narrower bands gain too little to pay for the borders
 
 struct Border {
@@ -274,10 +329,16 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
 // passes the previous row's last live chunk are always swept; after the last
 // unit the sweep extends by one unit while the last cell of some row is at
 // most the bound in some lane.  Returns the last swept column.
+//
+// qn / qn_unit: column values of unit qn_unit of this group, loaded during the
+// previous group; on return, those of unit b.lo of the next group (whose
+// columns start next_base), loaded while this group is swept.
 template <int R, int U, class Ptr>
 __device__ __forceinline__ int sweep_group_border(float (&v)[2 * R + 1], const float (&rv)[U],
                                                   Cols<Ptr> cs, const Border &b, uint32_t ubits,
-                                                  uint64_t amask) {
+                                                  uint64_t amask, float (&qn)[kColChunk],
+                                                  int &qn_unit, Ptr next_base) {
+  static_assert(kBorderChunk <= kColChunk, "look-ahead buffer too small");
   constexpr int W = 2 * R + 1;
   constexpr int NS = W + U - 1;
   constexpr int CH = kBorderChunk;
@@ -288,13 +349,14 @@ __device__ __forceinline__ int sweep_group_border(float (&v)[2 * R + 1], const f
   // column values of even units in qa, odd units in qb
   float qa[CH], qb[CH];
   {
+    const bool have = qn_unit == u0;
     Ptr p0 = opaque(cs.base + (int64_t)(CH * u0 - 1) * cs.stride);
     if (u0 & 1) {
 #pragma unroll
-      for (int t = 0; t < CH; ++t) qb[t] = p0[t * cs.stride + cs.lane_off];
+      for (int t = 0; t < CH; ++t) qb[t] = have ? qn[t] : p0[t * cs.stride + cs.lane_off];
     } else {
 #pragma unroll
-      for (int t = 0; t < CH; ++t) qa[t] = p0[t * cs.stride + cs.lane_off];
+      for (int t = 0; t < CH; ++t) qa[t] = have ? qn[t] : p0[t * cs.stride + cs.lane_off];
     }
   }
   static_for<NU>([&](auto kc) {
@@ -303,6 +365,13 @@ __device__ __forceinline__ int sweep_group_border(float (&v)[2 * R + 1], const f
     float(&cur)[CH] = (k & 1) ? qb : qa;
     float(&nxt)[CH] = (k & 1) ? qa : qb;
     settle<Ptr>(cur);
+    if (k == u0) {
+      // the next group most often starts at the same unit
+      Ptr pq = opaque(next_base + (int64_t)(CH * k - 1) * cs.stride);
+#pragma unroll
+      for (int t = 0; t < CH; ++t) qn[t] = pq[t * cs.stride + cs.lane_off];
+      qn_unit = k;
+    }
     if constexpr (k + 1 < NU) {
       Ptr pn = opaque(cs.base + (int64_t)(CH * (k + 1) - 1) * cs.stride);
 #pragma unroll
@@ -424,6 +493,27 @@ __device__ __forceinline__ int rows_cells(int i0, int lcol, int r) {
   return c;
 }
 
+// Row groups between reads of the shared best-so-far when none is chosen:
+// enough groups to cover an L2 round trip (about 2,400 cycles) with one
+// wave's own cell work (about 12 cycles per cell row of a group).
+template <int R, int U>
+__host__ __device__ constexpr int auto_check_interval() {
+  return (200 + U * (2 * R + U) - 1) / (U * (2 * R + U));
+}
+
+// Publishes the wave's best kept candidate: one atomic per wave instead of
+// one per lane (same-address atomics serialise in the L2).
+__device__ __forceinline__ void publish_best(unsigned long long *bsf, bool keep, float d,
+                                             uint32_t id) {
+  unsigned long long v = keep ? pack_best(d, id) : ~0ull;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long t = __shfl_xor(v, o, kWave);
+    v = t < v ? t : v;
+  }
+  if (threadIdx.x % kWave == 0 && v != ~0ull) atomicMin(bsf, v);
+}
+
 __device__ __forceinline__ float load_bsf_dist(const unsigned long long *bsf) {
   unsigned long long b = __hip_atomic_load(bsf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return best_dist(b);
@@ -463,7 +553,23 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   wave_window_stats(a.x, a.n, m, kb, lane, mean, sd);
   float mu_hi, mu_lo, inv;
   znorm_params(mean, sd, mu_hi, mu_lo, inv);
-  const float *__restrict__ xk = a.x + kc;
+  (void)kc;
+
+  // The wave's 64 candidates read rows of one stretch of the series: it is
+  // staged in LDS kStageRows rows at a time (one coalesced copy), so a row's
+  // values come from LDS instead of a dependent global load.
+  __shared__ float stage[kWave + kStageRows - 1];
+  int sbase = 0;  // first row held in stage
+  auto refill = [&](int i0) {
+    __syncthreads();
+    const float *__restrict__ xs = a.x + kb + i0;
+    const int64_t lim = a.n - 1 - (kb + i0);
+#pragma unroll 1
+    for (int t = lane; t < kWave + kStageRows - 1; t += kWave) stage[t] = xs[t < lim ? t : lim];
+    __syncthreads();
+  };
+  stage_copy<kWave + kStageRows - 1>(stage, a.x + kb, a.n - 1 - kb, lane);
+  __syncthreads();
 
   float v[W];
 #pragma unroll
@@ -474,25 +580,35 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   // (+ 0 turns a bound of -0 into +0, which the bit-pattern comparisons of
   // the bordered sweep need)
   float ub = (DISTS ? a.fixed_ub : load_bsf_dist(a.bsf)) + 0.0f;
-  if (!DISTS && a.center && a.bsf_init) ub = fminf(ub, best_dist(*a.bsf_init));
+  if (!DISTS && a.bsf_init) ub = fminf(ub, best_dist(*a.bsf_init));
   bool alive = active && ub >= 0.0f;
+  // The shared best-so-far is read once every ci groups; each read is
+  // issued ci groups before its value is applied, so its latency (an L2 round
+  // trip) hides behind that many groups even when a group is short.
+  const int ci = a.check_interval > 0 ? a.check_interval : auto_check_interval<R, U>();
   int since = 0;
+  bool pending = false;
+  unsigned long long bpend = 0;
   uint64_t evaluated = 0, computed = 0;
   const int mg = m - m % U;  // rows covered by full groups
   bool stopped = !wave_any(alive);
+  // column values the next group starts with, loaded one group ahead
+  float qfirst[kColChunk];
+  int qfirst_unit = -1;  // bordered sweep: the unit they belong to (-1: none)
+  if constexpr (!BORDER) load_first<U>(qfirst, Cols<ConstF *>{as_const(a.qpad + kColPad - R), 1, 0});
 
   float rv_next[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) rv_next[u] = (u < mg) ? xk[u] : 0.0f;
+  for (int u = 0; u < U; ++u) rv_next[u] = (u < mg) ? stage[lane + u] : 0.0f;
 
-  // One group of G rows starting at row i: the shared best-so-far is read
-  // before the sweep and applied after it, so its latency hides behind the
-  // sweep.
+  // One group of G rows starting at row i.
   auto group = [&](auto gtag, int i, const float *rvg) {
     constexpr int G = decltype(gtag)::value;
-    const bool reload = !DISTS && ++since >= a.check_interval;
-    unsigned long long bnext = 0;
-    if (reload) bnext = __hip_atomic_load(a.bsf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!DISTS && !pending) {
+      bpend = __hip_atomic_load(a.bsf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pending = true;
+      since = 0;
+    }
     const Cols<ConstF *> cols{as_const(a.qpad + kColPad + i - R), 1, 0};
     int band, mat;
     float rvl[G];
@@ -501,18 +617,19 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
     int slast = W + G - 2;
     if constexpr (BORDER) {
       slast = sweep_group_border<R, G>(v, rvl, cols, bd, cell_bits(ub),
-                                       __builtin_amdgcn_ballot_w64(alive));
+                                       __builtin_amdgcn_ballot_w64(alive), qfirst, qfirst_unit,
+                                       as_const(a.qpad + kColPad + i + G - R));
       swept_cells<G>(i, kBorderChunk * bd.lo - 1, slast, m, R, band, mat);
     } else {
-      sweep_group<R, G>(v, rvl, cols);
+      sweep_group<R, G>(v, rvl, cols, qfirst, as_const(a.qpad + kColPad + i + G - R));
       band = G * W;
       mat = rows_cells<G>(i, m, R);
     }
     evaluated += (uint64_t)mat * (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(alive));
     computed += (uint64_t)band * kWave;
-    if (reload) {
-      since = 0;
-      ub = fminf(ub, best_dist(bnext));
+    if (!DISTS && ++since >= ci) {
+      ub = fminf(ub, best_dist(bpend));
+      pending = false;
     }
     if constexpr (BORDER) {
       alive = border_update<R>(v, bd, cell_bits(ub), alive);
@@ -528,14 +645,22 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
 #pragma unroll
     for (int u = 0; u < U; ++u) rv[u] = znorm_value(rv_next[u], mu_hi, mu_lo, inv);
     if (i0 + U < mg) {
+      if (i0 + U - sbase >= kStageRows) {
+        sbase = i0 + U;
+        refill(sbase);
+      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) rv_next[u] = xk[i0 + U + u];
+      for (int u = 0; u < U; ++u) rv_next[u] = stage[lane + i0 + U + u - sbase];
     }
     group(std::integral_constant<int, U>{}, i0, rv);
   }
   // remaining rows, one at a time
   for (int i = mg; i < m && !stopped; ++i) {
-    const float rv1[1] = {znorm_value(xk[i], mu_hi, mu_lo, inv)};
+    if (i - sbase >= kStageRows) {
+      sbase = i;
+      refill(sbase);
+    }
+    const float rv1[1] = {znorm_value(stage[lane + i - sbase], mu_hi, mu_lo, inv)};
     group(std::integral_constant<int, 1>{}, i, rv1);
   }
 
@@ -543,8 +668,8 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   const bool keep = alive && !stopped && d <= ub;
   if (DISTS) {
     if (active) a.dists[k - a.k_begin] = keep ? d : kInf;
-  } else if (keep) {
-    atomicMin(a.bsf, pack_best(d, a.bound_only ? 0xffffffffu : (uint32_t)k));
+  } else {
+    publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }
   if (a.counters) {
     const uint64_t aband = (uint64_t)__popcll(__ballot(active && !keep));
@@ -557,8 +682,10 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   }
 }
 
+// At most 128 VGPRs where the band allows it, so that four waves share a SIMD
+// (the bordered sweep's bookkeeping otherwise pushes a few windows just past).
 template <int R, int U, bool DISTS, bool BORDER>
-__global__ __launch_bounds__(64) void nn_band_kernel(NNArgs a) {
+__global__ __launch_bounds__(64, (BORDER && R <= 52) ? 4 : 1) void nn_band_kernel(NNArgs a) {
   nn_band_body<R, U, DISTS, BORDER>(a, blockIdx.x);
 }
 

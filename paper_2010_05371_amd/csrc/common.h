@@ -59,7 +59,8 @@ struct NNArgs {
   unsigned long long *bsf;           // shared best-so-far (packed)
   int64_t k_begin, k_end;            // candidate offsets [k_begin, k_end)
   const unsigned long long *center;  // optional: restrict to 64 offsets around center's offset
-  const unsigned long long *bsf_init;// optional: seed bsf (distance part) from this word first
+  const unsigned long long *bsf_init;// optional: start from this word's distance as the bound
+                                     // (with center: also min it into bsf first)
   float fixed_ub;                    // per-candidate-distance mode: fixed bound
   float *dists;                      // per-candidate-distance mode: out[k - k_begin]
   unsigned long long *counters;      // kCntWords (nullable)

@@ -10,6 +10,9 @@ typedef hipError_t (*NNLaunchFn)(const NNArgs &, int64_t nblocks, int rows_per_g
 typedef hipError_t (*PairLaunchFn)(const PairArgs &, int64_t nblocks, int rows_per_group,
                                    hipStream_t);
 
+// Window 0: early-abandoned squared Euclidean distance (ed.hip).
+hipError_t launch_ed_search(const NNArgs &a, int64_t nblocks, bool dists, hipStream_t st);
+
 // Band-in-registers kernels for windows 0..kBandRMax (nullptr otherwise).
 NNLaunchFn nn_band_launcher(int r);
 PairLaunchFn pair_band_launcher(int r);
@@ -22,10 +25,13 @@ int wide_rows_for(int r, int lrow, int lcol);
 
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
-hipError_t launch_query_prep(const float *q, int m, float *qpad, unsigned long long *counters,
-                             hipStream_t st);
 hipError_t launch_check_finite(const float *x, int64_t n, unsigned long long *counters,
                                hipStream_t st);
+// Search set-up in one launch (counters, best-so-far words, padded query,
+// series check; x may be null to skip the check).
+hipError_t launch_search_prep(const float *q, int m, float *qpad, const float *x, int64_t n,
+                              unsigned long long *cnt, unsigned long long *bsf, int nbsf,
+                              unsigned *flag, unsigned epoch, hipStream_t st);
 hipError_t launch_transpose_pad(const float *src, int64_t npairs, int len, int64_t ld,
                                 int pad, float padval, float *dst, hipStream_t st);
 hipError_t launch_window_stats(const float *x, int64_t n, int m, double *mean, double *sd,

@@ -423,8 +423,8 @@ __device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task
   const bool keep = p.active && d <= p.ub && d < kInf;
   if (a.dists_mode) {
     if (p.active) a.dists[k - a.k_begin] = d;
-  } else if (keep) {
-    atomicMin(a.bsf, pack_best(d, a.bound_only ? 0xffffffffu : (uint32_t)k));
+  } else {
+    publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }
   abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
 }

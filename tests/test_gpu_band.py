@@ -160,13 +160,14 @@ def test_nn_dists_bounded_contract():
 def test_nn_search_c1_full(seed_opt, interval):
     """C1 at full size: 19,873 candidates; the brute-force oracle is the definition."""
     q32, x32, w = gen.c1()
+    old_interval = eap.get_option("check_interval")
     eap.set_option("seed", seed_opt)
     eap.set_option("check_interval", interval)
     try:
         (k, d), st = eap.nn_search(torch.from_numpy(q32), torch.from_numpy(x32), w, stats=True)
     finally:
         eap.set_option("seed", 1)
-        eap.set_option("check_interval", 1)
+        eap.set_option("check_interval", old_interval)
     q, x = gen.as_oracle(q32), gen.as_oracle(x32)
     ko, do = oracle.nn_search(q, x, w)
     at = oracle.nn_dists(q, x, w, [k])[0]
