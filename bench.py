@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of CPU oracle work for cpu_baseline (0 = skip)")
     ap.add_argument("--n", type=int, default=N_SERIES)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-mebibyte buffer once (a plain copy of known size "
+                         "that calibrates HBM byte counters in a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -108,6 +111,11 @@ def main():
     q = torch.from_numpy(q32).to(dev)
     x = torch.from_numpy(x32).to(dev)
     K = x32.size - q32.size + 1
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe * (1 << 18), device=dev, dtype=torch.float32)
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(record):
         for w in windows:

@@ -765,12 +765,35 @@ static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
 
 // Queues the whole batched search on the context stream (used directly, or
 // once under stream capture to build the graph).
-static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid, hipStream_t st) {
+// Queries with band windows (the descriptors from nband_first on) each get
+// one launch of their band (or window-0) kernel after the batched seeding;
+// the others share the persistent tiled launch.
+static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid,
+                       const std::vector<BatchQuery> &desc, int64_t nband_first, hipStream_t st) {
   HIPCHK(launch_fill_u64(ba.counters, 0ull, kCntWords, st));
   HIPCHK(launch_batch_prep(ba, st));
   HIPCHK(launch_check_finite(ba.x, ba.n, ba.counters, st));
   if (ctx->seed) HIPCHK(launch_batch_seed(ba, st));
-  HIPCHK(launch_batch_main(ba, grid, st));
+  for (int64_t i = nband_first; i < (int64_t)desc.size(); ++i) {
+    const BatchQuery &d = desc[i];
+    NNArgs a{};
+    a.x = ba.x;
+    a.n = ba.n;
+    a.m = d.m;
+    a.qpad = d.qpad;
+    a.bsf = d.bsf;
+    a.k_begin = 0;
+    a.k_end = d.K;
+    a.counters = ba.counters;
+    a.check_interval = ba.check_interval;
+    a.block_stride = 1;
+    const int64_t nblk = (d.K + kWave - 1) / kWave;
+    if (d.r == 0 && ctx->ed)
+      HIPCHK(launch_ed_search(a, nblk, false, st));
+    else
+      HIPCHK(nn_band_launcher(d.r)(a, nblk, pick_rows(ctx, d.r), false, ctx->border != 0, st));
+  }
+  if (ba.total_units > 0) HIPCHK(launch_batch_main(ba, grid, st));
   return EAPDTW_OK;
 }
 
@@ -802,7 +825,13 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     problems += (uint64_t)K;
     order[q] = q;
   }
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+  // tiled-kernel queries first (they share the persistent launch's work
+  // queue), then band-window queries; each part most expensive first
+  auto banded = [&](int64_t q) { return use_band(ctx, std::min(qs[q].window, qs[q].m - 1)); };
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    if (banded(a) != banded(b)) return !banded(a);
+    return cost[a] > cost[b];
+  });
   const int grid = (int)ctx->batch_grid;
   Plan pl;
   const size_t o_cnt = pl.add(kCntBytes);
@@ -830,7 +859,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   char *bb = ctx->batch_buf;
   // descriptors in the sorted order
   std::vector<BatchQuery> desc(nq);
-  int64_t units = 0, seeds = 0;
+  int64_t units = 0, seeds = 0, nband_first = nq;
   const int64_t sstr = ctx->batch_seed_stride;
   for (int64_t i = 0; i < nq; ++i) {
     const eapdtw_query &h = qs[order[i]];
@@ -844,7 +873,11 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     d.unit_begin = units;
     d.seed_begin = seeds;
     const int64_t nblk = (d.K + kWave - 1) / kWave;
-    units += nblk;
+    if (use_band(ctx, d.r)) {
+      if (nband_first == nq) nband_first = i;
+    } else {
+      units += nblk;  // band queries own no units (their unit_begin is past the last)
+    }
     seeds += (nblk + sstr - 1) / sstr;
   }
   BatchArgs ba{};
@@ -870,6 +903,10 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   key = fnv1a(key, desc.data(), sizeof(BatchQuery) * nq);
   key = fnv1a(key, &grid, sizeof grid);
   key = fnv1a(key, &ctx->seed, sizeof ctx->seed);
+  key = fnv1a(key, &ctx->border, sizeof ctx->border);
+  key = fnv1a(key, &ctx->ed, sizeof ctx->ed);
+  key = fnv1a(key, &ctx->rows_per_group, sizeof ctx->rows_per_group);
+  key = fnv1a(key, &ctx->force_wide, sizeof ctx->force_wide);
   const bool use_graph = ctx->graph != 0;
   const bool rebuild = !use_graph || !ctx->batch_exec || ctx->batch_key != key;
   if (rebuild) {
@@ -892,7 +929,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
       if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-      int rc = batch_queue(ctx, ba, grid, ctx->cap_stream);
+      int rc = batch_queue(ctx, ba, grid, desc, nband_first, ctx->cap_stream);
       hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
       if (rc) {
         if (g) (void)hipGraphDestroy(g);
@@ -909,7 +946,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     }
     HIPCHK(hipGraphLaunch(ctx->batch_exec, st));
   } else {
-    int rc = batch_queue(ctx, ba, grid, st);
+    int rc = batch_queue(ctx, ba, grid, desc, nband_first, st);
     if (rc) return rc;
   }
   if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));

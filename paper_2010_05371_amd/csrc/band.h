@@ -686,7 +686,7 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
 // (the bordered sweep's bookkeeping otherwise pushes a few windows just past).
 template <int R, int U, bool DISTS, bool BORDER>
 __global__ __launch_bounds__(64, (BORDER && R <= 52) ? 4 : 1) void nn_band_kernel(NNArgs a) {
-  nn_band_body<R, U, DISTS, BORDER>(a, blockIdx.x);
+  nn_band_body<R, U, DISTS, BORDER>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------

@@ -39,6 +39,22 @@ __host__ __device__ inline unsigned long long *counter_stripe(unsigned long long
   return c + (b % kCntStripes) * kCntStride;
 }
 
+// Workgroups are dealt to the chip's eight XCDs (each with its own L2) in
+// turn: workgroup b runs on XCD b % 8.  xcd_block maps the dispatch index to
+// a logical block so that each XCD works through runs of kXcdRun consecutive
+// logical blocks (runs dealt to the XCDs in turn): a run's waves share one
+// stretch of the series in one L2, while the work along the series stays
+// spread evenly over the XCDs.  A bijection on [0, nblocks): blocks past the
+// last whole round of runs keep their index.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 64;
+__host__ __device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
+  const int64_t round = (int64_t)kXcds * kXcdRun;
+  if (b >= nblocks / round * round) return b;
+  const int64_t x = b % kXcds, j = b / kXcds;
+  return (j / kXcdRun) * round + x * kXcdRun + j % kXcdRun;
+}
+
 // The shared best-so-far of a search packs (distance, offset) into one u64 so
 // that a single 64-bit atomic min keeps the lexicographic minimum: distances
 // are non-negative float32, whose bit patterns order like unsigned integers.

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(64) void ed_search_kernel(NNArgs a) {
     kbeg = lo;
     if (a.bsf_init && lane == 0) atomicMin(a.bsf, pack_best(best_dist(*a.bsf_init), 0xffffffffu));
   }
-  const int64_t kb = kbeg + (int64_t)blockIdx.x * kWave * (a.block_stride > 1 ? a.block_stride : 1);
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t kb = kbeg + blk * kWave * (a.block_stride > 1 ? a.block_stride : 1);
   if (kb >= kend) return;
   const int64_t k = kb + lane;
   const bool active = k < kend;

@@ -68,3 +68,20 @@ def test_create_without_device_is_enodev():
 def test_ckpt_bytes_is_host_arithmetic():
     lib = _lib.load()
     assert lib.eapdtw_dtw_ckpt_bytes(-1, 10, 2) < 0
+
+
+def test_xcd_block_mapping_is_a_bijection():
+    """The dispatch-index to logical-block map of the search kernels (runs of
+    64 consecutive logical blocks dealt to the eight XCDs in turn) permutes
+    [0, n) for any n, and dispatch b of a whole round lands on XCD b % 8."""
+    def xcd_block(b, n, run=64):
+        rnd = 8 * run
+        if b >= n // rnd * rnd:
+            return b
+        x, j = b % 8, b // 8
+        return (j // run) * rnd + x * run + j % run
+    for n in list(range(1, 70)) + [511, 512, 513, 1953, 4097, 31250]:
+        assert sorted(xcd_block(b, n) for b in range(n)) == list(range(n)), n
+    n = 31250
+    for b in range(0, n // 512 * 512, 97):
+        assert (xcd_block(b, n) // 64) % 8 == b % 8
