@@ -1,0 +1,89 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (default options): whole answers where the FP64 oracle can
+brute-force them, sampled outputs and size-independent properties otherwise."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2010_05371_amd as eap
+from parity import assert_close_array, check_nn, close
+
+pytestmark = pytest.mark.gpu
+
+
+def _cpu(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    q32, x32, windows = gen.c2()
+    return q32, x32, windows, torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda()
+
+
+@pytest.mark.parametrize("w", [0, 13, 26, 52])
+def test_c2_full_search_vs_brute_force(c2, w):
+    """2,000,000-point series, query 256: the oracle scans every offset."""
+    q32, x32, _, q, x = c2
+    k, d = eap.nn_search(q, x, w)
+    qo, xo = gen.as_oracle(q32), gen.as_oracle(x32)
+    ko, do = oracle.nn_search(qo, xo, w)
+    check_nn(k, d, ko, do, oracle.nn_dists(qo, xo, w, [k])[0])
+
+
+def test_c2_full_dists_sampled(c2):
+    """Every candidate's distance at window 52 (no bound), 4,096 sampled
+    against the oracle, the rest against the search's minimum."""
+    q32, x32, _, q, x = c2
+    d = _cpu(eap.nn_dists(q, x, 52))
+    offs = np.sort(gen.rng(4000).choice(d.size, 4096, replace=False))
+    want = oracle.nn_dists(gen.as_oracle(q32), gen.as_oracle(x32), 52, offs)
+    assert_close_array(d[offs], want, what="c2 window 52 sampled")
+    k, dk = eap.nn_search(q, x, 52)
+    assert np.isfinite(d).all()
+    assert d.min() == np.float32(dk) and int(np.argmin(d)) == k
+
+
+def test_c3_full_pairwise_sampled():
+    """1,999,000 pairs of length 512, full window: 512 sampled pairs against
+    the oracle; DTW <= squared Euclidean distance on the same sample."""
+    X, w = gen.c3()
+    D = _cpu(eap.pairwise(torch.from_numpy(X).cuda(), w))
+    N = X.shape[0]
+    assert D.size == N * (N - 1) // 2
+    g = gen.rng(4001)
+    ia = g.integers(0, N - 1, 512)
+    ib = np.array([g.integers(i + 1, N) for i in ia])
+    k = np.array([eap.pairwise_index(N, int(i), int(j)) for i, j in zip(ia, ib)])
+    Xo = gen.as_oracle(X)
+    want = oracle.dtw_pairs(Xo, Xo, w, ia, ib)
+    assert_close_array(D[k], want, what="c3 sampled")
+    ed = np.sum((Xo[ia] - Xo[ib]) ** 2, axis=1)
+    assert np.all(D[k] <= ed * (1 + 1e-6))
+    assert np.isfinite(D).all() and (D >= 0).all()
+
+
+def test_c4_full_batch_properties():
+    """64 uneven queries against 10,000,000 points: the batched answers equal
+    the single-query answers; each reported distance is the oracle's DTW at
+    the reported offset; no sampled offset (64 random plus the 64 around the
+    answer) beats it."""
+    qs, ws, x32 = gen.c4()
+    x = torch.from_numpy(x32).cuda()
+    qt = [(torch.from_numpy(q).cuda(), w) for q, w in zip(qs, ws)]
+    batch = eap.nn_search_batch(qt, x)
+    single = [eap.nn_search(q, x, w) for q, w in qt]
+    assert batch == single
+    xo = gen.as_oracle(x32)
+    g = gen.rng(4002)
+    for (q32, w), (k, d) in zip(zip(qs, ws), batch):
+        qo = gen.as_oracle(q32)
+        K = x32.size - q32.size + 1
+        at = oracle.nn_dists(qo, xo, w, [k])[0]
+        assert close(d, at), (q32.size, w, k, d, at)
+        offs = np.unique(np.concatenate([g.integers(0, K, 64),
+                                         np.clip(np.arange(k - 32, k + 32), 0, K - 1)]))
+        others = oracle.nn_dists(qo, xo, w, offs)
+        assert others.min() >= at * (1 - 1e-5) - 1e-6, (q32.size, w)
