@@ -118,6 +118,7 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *                      its pruning borders (windows >= 24; default), 0 = the
  *                      whole band with row-minimum abandoning; both give the
  *                      same bits for every distance at most the bound
+ *   "autotune"       : 1 = searches apply the tuning cache (see eapdtw_autotune)
  *   "ed"             : 1 = window-0 searches and seeding passes use the
  *                      squared-Euclidean kernel (default), 0 = the band kernel
  *                      (same bits)
@@ -189,6 +190,44 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
 int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
                            const float *series, int64_t n, eapdtw_result *out,
                            eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning of the search kernels (a tuning aid; the paper has no
+ * counterpart).  Choices are kept per bucket of (query length, window):
+ * length bucket = bit length of m; window bucket = 0 for r = 0, bit length of
+ * r for 1 <= r <= 64 (band kernels), 8 + bit length of r beyond (tiled
+ * kernel), 31 for a window covering the whole query; bucket = 32 x length
+ * bucket + window bucket.
+ *   rows_per_group : band kernel rows per group (2, 4, 8; 0 = default)
+ *   border         : bordered band sweep on/off (windows >= 24)
+ *   check_interval : row groups between best-so-far reads (0 = automatic)
+ *   wide_rows      : tile height of the whole-window tiled kernel (0, 32, 64)
+ *   ms             : measured time of the sample search with these choices */
+typedef struct {
+  int64_t rows_per_group, border, check_interval, wide_rows;
+  float ms;
+} eapdtw_tune;
+
+/* Times every candidate choice for `query` [m] (DEVICE) under `window` on the
+ * first sample_n points of `series` (DEVICE; at least m + 64 Ki points are
+ * used when available), records the fastest in the context's cache under the
+ * query's bucket and returns it in *out (may be NULL).  With option
+ * "autotune" = 1, eapdtw_nn_search, eapdtw_nn_dists and eapdtw_nn_search_batch
+ * apply the recorded choices of each query's bucket, and the batch tunes a
+ * bucket it has no record for on first use.  Synchronous. */
+int eapdtw_autotune(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                    int64_t n, int64_t window, int64_t sample_n, eapdtw_tune *out);
+
+/* Bucket of (m, window) as described above, and the cached record of a bucket
+ * (EINVAL when none). */
+int64_t eapdtw_tune_bucket(int64_t m, int64_t window);
+int eapdtw_tune_get(const eapdtw_ctx *ctx, int64_t bucket, eapdtw_tune *out);
+
+/* The cache as JSON, {"arch": "gfx950", "entries": [{"bucket": b, ...}, ...]}:
+ * save writes the file; load merges a file written for the same arch
+ * (EINVAL for another arch or an unreadable file).  Host-only. */
+int eapdtw_tune_save(const eapdtw_ctx *ctx, const char *path);
+int eapdtw_tune_load(eapdtw_ctx *ctx, const char *path);
 
 /* ---------------------------------------------------------------------------
  * Forward of the differentiable batch (Section 2: DTW value; the gradient

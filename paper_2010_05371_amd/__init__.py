@@ -17,6 +17,8 @@ Functions (names follow the C ABI):
 * ``window_stats(series, m)``, ``znorm(x)`` -- exposed steps of the search
 * ``DTWFunction.apply(S, T, window)``      -- differentiable batch (autograd)
 * ``window_from_ratio(ratio, m)``          -- integer window, rounded up
+* ``autotune(query, series, window)``, ``tune_get``, ``tune_save``,
+  ``tune_load``                            -- the kernel-choice tuning cache
 """
 from __future__ import annotations
 
@@ -27,11 +29,12 @@ import threading
 import torch
 
 from . import _lib
-from ._lib import EapdtwError, Query, Result, Stats
+from ._lib import EapdtwError, Query, Result, Stats, Tune
 
 __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_dists",
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
-           "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index"]
+           "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
+           "tune_bucket", "tune_get", "tune_save", "tune_load"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -223,6 +226,40 @@ def nn_dists(query, series, window: int, ub: float = math.inf, stats: bool = Fal
                                        int(window), float(ub), _ptr(out),
                                        ctypes.byref(st) if stats else None))
     return (out, st.as_dict()) if stats else out
+
+
+def autotune(query, series, window: int, sample_n: int = 1 << 18) -> dict:
+    """Times the kernel choices for (len(query), window) on a sample of the
+    series, records the fastest in the context's cache and returns it."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    t = Tune()
+    ctx.check(ctx._lib.eapdtw_autotune(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                       int(window), int(sample_n), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def tune_bucket(m: int, window: int) -> int:
+    return int(_lib.load().eapdtw_tune_bucket(int(m), int(window)))
+
+
+def tune_get(m: int, window: int, device: int | None = None):
+    """The cached choices of (m, window)'s bucket, or None."""
+    ctx = context(device)
+    t = Tune()
+    rc = ctx._lib.eapdtw_tune_get(ctx.handle, tune_bucket(m, window), ctypes.byref(t))
+    return t.as_dict() if rc == 0 else None
+
+
+def tune_save(path: str, device: int | None = None):
+    ctx = context(device)
+    ctx.check(ctx._lib.eapdtw_tune_save(ctx.handle, str(path).encode()))
+
+
+def tune_load(path: str, device: int | None = None):
+    ctx = context(device)
+    ctx.check(ctx._lib.eapdtw_tune_load(ctx.handle, str(path).encode()))
 
 
 def window_stats(series, m: int):

@@ -39,6 +39,15 @@ class Result(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_int64), ("dist", ctypes.c_double)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("rows_per_group", ctypes.c_int64), ("border", ctypes.c_int64),
+                ("check_interval", ctypes.c_int64), ("wide_rows", ctypes.c_int64),
+                ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -76,6 +85,11 @@ def load():
         "eapdtw_window_stats": ([vp, vp, i64, i64, vp, vp], i32),
         "eapdtw_znorm": ([vp, vp, i64, vp], i32),
         "eapdtw_nn_dists": ([vp, vp, i64, vp, i64, i64, f32, vp, sp], i32),
+        "eapdtw_autotune": ([vp, vp, i64, vp, i64, i64, i64, ctypes.POINTER(Tune)], i32),
+        "eapdtw_tune_bucket": ([i64, i64], i64),
+        "eapdtw_tune_get": ([vp, i64, ctypes.POINTER(Tune)], i32),
+        "eapdtw_tune_save": ([vp, ctypes.c_char_p], i32),
+        "eapdtw_tune_load": ([vp, ctypes.c_char_p], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -16,6 +16,7 @@
 #include "batch.h"
 
 #include <algorithm>
+#include <map>
 #include <vector>
 
 using namespace eapdtw;
@@ -42,6 +43,8 @@ struct eapdtw_ctx {
   uint32_t epoch = 0;  // numbers the searches (non-finite flag values)
   int64_t border = 1;
   int64_t ed = 1;
+  int64_t autotune = 0;
+  std::map<int64_t, eapdtw_tune> tune;  // autotuning cache, by (length, window) bucket
   int64_t seed_window = 8;
   int64_t batch_grid = 2048;
   int64_t batch_chunk = 4;
@@ -307,6 +310,7 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "batch_seed_stride")) return &ctx->batch_seed_stride;
   if (!strcmp(key, "border")) return &ctx->border;
   if (!strcmp(key, "ed")) return &ctx->ed;
+  if (!strcmp(key, "autotune")) return &ctx->autotune;
   return nullptr;
 }
 
@@ -317,7 +321,7 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   bool ok = true;
   if (!strcmp(key, "check_interval")) ok = value >= 0 && value <= (1 << 20);
   else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide") ||
-           !strcmp(key, "border") || !strcmp(key, "ed"))
+           !strcmp(key, "border") || !strcmp(key, "ed") || !strcmp(key, "autotune"))
     ok = value == 0 || value == 1;
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
@@ -678,10 +682,57 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
   return EAPDTW_OK;
 }
 
+// --------------------------------------------------------------------------- tuning
+
+int64_t eapdtw_tune_bucket(int64_t m, int64_t window) {
+  if (m < 1 || window < 0) return -1;
+  auto bits = [](int64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return (int64_t)b; };
+  const int64_t r = window < m - 1 ? window : m - 1;
+  int64_t rb;
+  if (m > 1 && r >= m - 1) rb = 31;
+  else if (r == 0) rb = 0;
+  else if (r <= kBandRMax) rb = bits(r);
+  else rb = 8 + bits(r);
+  return 32 * bits(m) + rb;
+}
+
+namespace {
+
+// Applies a bucket's tuned choices to the context for one call and restores
+// the previous ones afterwards.
+struct KnobGuard {
+  eapdtw_ctx *ctx;
+  int64_t rows, border, ci, wide;
+  explicit KnobGuard(eapdtw_ctx *c)
+      : ctx(c), rows(c->rows_per_group), border(c->border), ci(c->check_interval),
+        wide(c->wide_rows) {}
+  void apply(const eapdtw_tune &t) {
+    ctx->rows_per_group = t.rows_per_group;
+    ctx->border = t.border;
+    ctx->check_interval = t.check_interval;
+    ctx->wide_rows = t.wide_rows;
+  }
+  void apply_cached(int64_t m, int64_t window) {
+    if (!ctx->autotune) return;
+    auto it = ctx->tune.find(eapdtw_tune_bucket(m, window));
+    if (it != ctx->tune.end()) apply(it->second);
+  }
+  ~KnobGuard() {
+    ctx->rows_per_group = rows;
+    ctx->border = border;
+    ctx->check_interval = ci;
+    ctx->wide_rows = wide;
+  }
+};
+
+}  // namespace
+
 int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                      int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
                      eapdtw_stats *stats) {
   CHECK_CTX();
+  KnobGuard knobs(ctx);
+  knobs.apply_cached(m, window);
   if (!out_offset || !out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL output");
   int rc = search_validate(ctx, query, m, series, n, window);
   if (rc) return rc;
@@ -723,6 +774,8 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
 int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                     int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats) {
   CHECK_CTX();
+  KnobGuard knobs(ctx);
+  knobs.apply_cached(m, window);
   if (!out) return fail(ctx, EAPDTW_EINVAL, "NULL output");
   if (std::isnan(ub)) return fail(ctx, EAPDTW_EINVAL, "ub is NaN");
   int rc = search_validate(ctx, query, m, series, n, window);
@@ -769,7 +822,8 @@ static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
 // one launch of their band (or window-0) kernel after the batched seeding;
 // the others share the persistent tiled launch.
 static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid,
-                       const std::vector<BatchQuery> &desc, int64_t nband_first, hipStream_t st) {
+                       const std::vector<BatchQuery> &desc, const std::vector<eapdtw_tune> &knob,
+                       int64_t nband_first, hipStream_t st) {
   HIPCHK(launch_fill_u64(ba.counters, 0ull, kCntWords, st));
   HIPCHK(launch_batch_prep(ba, st));
   HIPCHK(launch_check_finite(ba.x, ba.n, ba.counters, st));
@@ -788,10 +842,13 @@ static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid,
     a.check_interval = ba.check_interval;
     a.block_stride = 1;
     const int64_t nblk = (d.K + kWave - 1) / kWave;
+    const eapdtw_tune &t = knob[i];
+    a.check_interval = (int)t.check_interval;
+    const int rows = t.rows_per_group ? (int)t.rows_per_group : pick_rows(ctx, d.r);
     if (d.r == 0 && ctx->ed)
       HIPCHK(launch_ed_search(a, nblk, false, st));
     else
-      HIPCHK(nn_band_launcher(d.r)(a, nblk, pick_rows(ctx, d.r), false, ctx->border != 0, st));
+      HIPCHK(nn_band_launcher(d.r)(a, nblk, rows, false, t.border != 0, st));
   }
   if (ba.total_units > 0) HIPCHK(launch_batch_main(ba, grid, st));
   return EAPDTW_OK;
@@ -810,6 +867,14 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     int rc = search_validate(ctx, qs[q].query, qs[q].m, series, n, qs[q].window);
     if (rc) return rc;
     max_m = std::max(max_m, qs[q].m);
+  }
+  if (ctx->autotune) {
+    // tune each (length, window) bucket the cache has no record for
+    for (int64_t q = 0; q < nq; ++q) {
+      if (ctx->tune.count(eapdtw_tune_bucket(qs[q].m, qs[q].window))) continue;
+      int rc = eapdtw_autotune(ctx, qs[q].query, qs[q].m, series, n, qs[q].window, 1 << 18, nullptr);
+      if (rc) return rc;
+    }
   }
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
@@ -880,6 +945,17 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     }
     seeds += (nblk + sstr - 1) / sstr;
   }
+  // per-query choices for the band launches: the tuned ones of the query's
+  // bucket when autotuning, else the context's
+  std::vector<eapdtw_tune> knob(nq, eapdtw_tune{ctx->rows_per_group, ctx->border,
+                                                ctx->check_interval, ctx->wide_rows, 0.f});
+  if (ctx->autotune) {
+    for (int64_t i = 0; i < nq; ++i) {
+      auto it = ctx->tune.find(eapdtw_tune_bucket(qs[order[i]].m, qs[order[i]].window));
+      if (it != ctx->tune.end()) knob[i] = it->second;
+      knob[i].ms = 0.f;
+    }
+  }
   BatchArgs ba{};
   ba.qs = reinterpret_cast<const BatchQuery *>(bb + o_desc);
   ba.nq = (int)nq;
@@ -907,6 +983,10 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   key = fnv1a(key, &ctx->ed, sizeof ctx->ed);
   key = fnv1a(key, &ctx->rows_per_group, sizeof ctx->rows_per_group);
   key = fnv1a(key, &ctx->force_wide, sizeof ctx->force_wide);
+  for (const eapdtw_tune &t : knob) {
+    const int64_t f[4] = {t.rows_per_group, t.border, t.check_interval, t.wide_rows};
+    key = fnv1a(key, f, sizeof f);
+  }
   const bool use_graph = ctx->graph != 0;
   const bool rebuild = !use_graph || !ctx->batch_exec || ctx->batch_key != key;
   if (rebuild) {
@@ -929,7 +1009,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
       if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-      int rc = batch_queue(ctx, ba, grid, desc, nband_first, ctx->cap_stream);
+      int rc = batch_queue(ctx, ba, grid, desc, knob, nband_first, ctx->cap_stream);
       hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
       if (rc) {
         if (g) (void)hipGraphDestroy(g);
@@ -946,7 +1026,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     }
     HIPCHK(hipGraphLaunch(ctx->batch_exec, st));
   } else {
-    int rc = batch_queue(ctx, ba, grid, desc, nband_first, st);
+    int rc = batch_queue(ctx, ba, grid, desc, knob, nband_first, st);
     if (rc) return rc;
   }
   if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -969,6 +1049,121 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     const float ms = elapsed(ctx->ev0, ctx->ev1);
     fill_stats(stats, hc, nominal, problems, ms, ms);
   }
+  return EAPDTW_OK;
+}
+
+int eapdtw_autotune(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                    int64_t n, int64_t window, int64_t sample_n, eapdtw_tune *out) {
+  CHECK_CTX();
+  int rc = search_validate(ctx, query, m, series, n, window);
+  if (rc) return rc;
+  int64_t ns = std::max<int64_t>(sample_n, m + 65536);
+  ns = std::min(ns, n);
+  const int64_t r = window < m - 1 ? window : m - 1;
+  std::vector<eapdtw_tune> cand;
+  const int64_t cis[3] = {0, 1, 4};
+  if (use_band(ctx, r)) {
+    for (int64_t ci : cis) {
+      if (r >= kBorderMinR) {
+        for (int64_t b : {1, 0}) cand.push_back({0, b, ci, 0, 0.f});
+      } else {
+        for (int64_t u : {4, 2, 8}) cand.push_back({u, 1, ci, 0, 0.f});
+      }
+    }
+  } else {
+    const bool full = m > 1 && r >= m - 1;
+    for (int64_t ci : cis) {
+      if (full) {
+        for (int64_t h : {64, 32}) cand.push_back({0, 1, ci, h, 0.f});
+      } else {
+        cand.push_back({0, 1, ci, 0, 0.f});
+      }
+    }
+  }
+  KnobGuard knobs(ctx);
+  const int64_t at = ctx->autotune;
+  ctx->autotune = 0;
+  eapdtw_tune best{};
+  best.ms = INFINITY;
+  for (eapdtw_tune &t : cand) {
+    knobs.apply(t);
+    float ms = INFINITY;
+    for (int rep = 0; rep < 3 && rc == 0; ++rep) {
+      int64_t off;
+      double d;
+      eapdtw_stats st;
+      rc = eapdtw_nn_search(ctx, query, m, series, ns, window, &off, &d, &st);
+      if (rep > 0) ms = std::min(ms, st.kernel_ms);  // the first run warms up
+    }
+    if (rc) break;
+    t.ms = ms;
+    if (ms < best.ms) best = t;
+  }
+  ctx->autotune = at;
+  if (rc) return rc;
+  ctx->tune[eapdtw_tune_bucket(m, window)] = best;
+  if (out) *out = best;
+  return EAPDTW_OK;
+}
+
+int eapdtw_tune_get(const eapdtw_ctx *ctx, int64_t bucket, eapdtw_tune *out) {
+  if (!ctx || !out) return EAPDTW_EINVAL;
+  auto it = ctx->tune.find(bucket);
+  if (it == ctx->tune.end()) return EAPDTW_EINVAL;
+  *out = it->second;
+  return EAPDTW_OK;
+}
+
+int eapdtw_tune_save(const eapdtw_ctx *ctx, const char *path) {
+  if (!ctx || !path) return EAPDTW_EINVAL;
+  FILE *f = std::fopen(path, "w");
+  if (!f) return EAPDTW_EINVAL;
+  std::fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [");
+  bool first = true;
+  for (const auto &kv : ctx->tune) {
+    const eapdtw_tune &t = kv.second;
+    std::fprintf(f,
+                 "%s\n  {\"bucket\": %lld, \"rows_per_group\": %lld, \"border\": %lld, "
+                 "\"check_interval\": %lld, \"wide_rows\": %lld, \"ms\": %.6g}",
+                 first ? "" : ",", (long long)kv.first, (long long)t.rows_per_group,
+                 (long long)t.border, (long long)t.check_interval, (long long)t.wide_rows,
+                 (double)t.ms);
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  return std::fclose(f) == 0 ? EAPDTW_OK : EAPDTW_EINVAL;
+}
+
+// Reads the file written by eapdtw_tune_save: the arch string, then one
+// entry per object; every value must be in the range its option accepts.
+int eapdtw_tune_load(eapdtw_ctx *ctx, const char *path) {
+  if (!ctx || !path) return EAPDTW_EINVAL;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(ctx, EAPDTW_EINVAL, "cannot open tuning file");
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  if (text.find("\"arch\": \"gfx950\"") == std::string::npos)
+    return fail(ctx, EAPDTW_EINVAL, "tuning file is not for gfx950");
+  std::map<int64_t, eapdtw_tune> add;
+  size_t pos = 0;
+  while ((pos = text.find("{\"bucket\"", pos)) != std::string::npos) {
+    long long b, u, bo, ci, w;
+    double ms;
+    if (std::sscanf(text.c_str() + pos,
+                    "{\"bucket\": %lld, \"rows_per_group\": %lld, \"border\": %lld, "
+                    "\"check_interval\": %lld, \"wide_rows\": %lld, \"ms\": %lf}",
+                    &b, &u, &bo, &ci, &w, &ms) != 6)
+      return fail(ctx, EAPDTW_EINVAL, "malformed tuning entry");
+    const bool ok = b >= 0 && (u == 0 || u == 2 || u == 4 || u == 8) && (bo == 0 || bo == 1) &&
+                    ci >= 0 && ci <= (1 << 20) && (w == 0 || w == 32 || w == 64);
+    if (!ok) return fail(ctx, EAPDTW_EINVAL, "tuning entry out of range");
+    add[b] = eapdtw_tune{u, bo, ci, w, (float)ms};
+    ++pos;
+  }
+  for (const auto &kv : add) ctx->tune[kv.first] = kv.second;
   return EAPDTW_OK;
 }
 

@@ -85,3 +85,16 @@ def test_xcd_block_mapping_is_a_bijection():
     n = 31250
     for b in range(0, n // 512 * 512, 97):
         assert (xcd_block(b, n) // 64) % 8 == b % 8
+
+
+def test_tune_bucket():
+    """Autotuning buckets: 32 x bit length of m + window class."""
+    import paper_2010_05371_amd as eap
+    assert eap.tune_bucket(256, 0) == 9 * 32
+    assert eap.tune_bucket(256, 13) == 9 * 32 + 4
+    assert eap.tune_bucket(256, 52) == 9 * 32 + 6
+    assert eap.tune_bucket(256, 64) == 9 * 32 + 7
+    assert eap.tune_bucket(256, 65) == 9 * 32 + 8 + 7
+    assert eap.tune_bucket(256, 255) == eap.tune_bucket(256, 10_000) == 9 * 32 + 31
+    assert eap.tune_bucket(512, 100) == 10 * 32 + 8 + 7
+    assert eap.tune_bucket(0, 3) == -1 and eap.tune_bucket(5, -1) == -1
