@@ -106,6 +106,7 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *                      0 = start the search from +inf
  *   "rows_per_group" : rows handled per group by the band search kernel (2,4,8; 0=auto)
  *   "seed_stride"    : the window-0 seeding pass visits every seed_stride-th block
+ *                      of 64 candidates (0 = about 128 blocks per search, the default)
  *   "seed_window"    : window of the seeding workgroup (<= search window)
  *   "batch_grid"     : persistent workgroups of the batched search
  *   "batch_chunk"    : work units taken per queue access in the batched search

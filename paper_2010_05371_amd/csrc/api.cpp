@@ -39,7 +39,7 @@ struct eapdtw_ctx {
   int64_t lanes_per_problem = 1;
   int64_t graph = 1;
   int64_t force_wide = 0;
-  int64_t seed_stride = 16;
+  int64_t seed_stride = 0;  // 0: about kSeedBlocks blocks per search
   uint32_t epoch = 0;  // numbers the searches (non-finite flag values)
   int64_t border = 1;
   int64_t ed = 1;
@@ -48,7 +48,7 @@ struct eapdtw_ctx {
   int64_t seed_window = 8;
   int64_t batch_grid = 2048;
   int64_t batch_chunk = 4;
-  int64_t batch_seed_stride = 16;
+  int64_t batch_seed_stride = 0;
   // batched search: dedicated device buffer and the captured graph
   char *batch_buf = nullptr;
   size_t batch_cap = 0;
@@ -326,11 +326,11 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
   else if (!strcmp(key, "lanes_per_problem")) ok = value == 1;
-  else if (!strcmp(key, "seed_stride")) ok = value >= 1 && value <= 1024;
+  else if (!strcmp(key, "seed_stride")) ok = value >= 0 && value <= (1 << 20);
   else if (!strcmp(key, "seed_window")) ok = value >= 0 && value <= kBandRMax;
   else if (!strcmp(key, "batch_grid")) ok = value >= 64 && value <= 65536;
   else if (!strcmp(key, "batch_chunk")) ok = value >= 1 && value <= 1024;
-  else if (!strcmp(key, "batch_seed_stride")) ok = value >= 1 && value <= 1024;
+  else if (!strcmp(key, "batch_seed_stride")) ok = value >= 0 && value <= (1 << 20);
   if (!ok) return fail(ctx, EAPDTW_EINVAL, std::string("bad value for option ") + key);
   *slot = value;
   return EAPDTW_OK;
@@ -351,6 +351,17 @@ int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value) {
 constexpr size_t kCntBytes = sizeof(unsigned long long) * kCntWords + 256;
 
 static bool use_band(const eapdtw_ctx *ctx, int64_t r) { return r <= kBandRMax && !ctx->force_wide; }
+
+// The window-0 seeding pass visits about this many blocks of 64 candidates
+// (spread evenly over the series) unless a stride is set: one wave's
+// 256-row pass costs ~11 us whatever the grid, so a pass over more blocks
+// only adds waves, while the seeding workgroup tightens the bound anyway.
+constexpr int64_t kSeedBlocks = 128;
+static int64_t seed_stride_for(int64_t opt, int64_t nblk) {
+  if (opt > 0) return opt;
+  const int64_t s = nblk / kSeedBlocks;
+  return s > 1 ? s : 1;
+}
 
 // DTW of pairs (rows X[p] of length lrow, columns Y[p] of length lcol), window
 // r (already clipped to max(lrow,lcol)-1), bound per ub_mode.  Queues all
@@ -610,7 +621,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     // The band search starts from the window-0 bound and the seeding
     // workgroup runs beside it on a second stream: its bound reaches the
     // search's waves through their periodic reads of the best-so-far.
-    const int64_t sstr = ctx->seed_stride;
+    const int64_t sstr = seed_stride_for(ctx->seed_stride, nblk);
     NNArgs e = a;
     e.bsf = bsf + 1;
     e.block_stride = (int)sstr;
@@ -925,7 +936,6 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   // descriptors in the sorted order
   std::vector<BatchQuery> desc(nq);
   int64_t units = 0, seeds = 0, nband_first = nq;
-  const int64_t sstr = ctx->batch_seed_stride;
   for (int64_t i = 0; i < nq; ++i) {
     const eapdtw_query &h = qs[order[i]];
     BatchQuery &d = desc[i];
@@ -938,6 +948,8 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     d.unit_begin = units;
     d.seed_begin = seeds;
     const int64_t nblk = (d.K + kWave - 1) / kWave;
+    const int64_t sstr = seed_stride_for(ctx->batch_seed_stride, nblk);
+    d.seed_stride = (int)sstr;
     if (use_band(ctx, d.r)) {
       if (nband_first == nq) nband_first = i;
     } else {
@@ -965,7 +977,6 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   ba.work = reinterpret_cast<unsigned long long *>(bb + o_work);
   ba.chunk = (int)ctx->batch_chunk;
   ba.total_seed_blocks = seeds;
-  ba.seed_stride = (int)sstr;
   ba.seed_window = (int)std::min<int64_t>(ctx->seed_window, 8);
   ba.bnd = reinterpret_cast<float *>(bb + o_bnd);
   ba.bnd_stride = (max_m + 1) * kWave;

@@ -14,6 +14,7 @@ struct BatchQuery {
   int64_t K;                   // candidate offsets n - m + 1
   int64_t unit_begin;          // first work unit (64 offsets each) of the main pass
   int64_t seed_begin;          // first workgroup of the window-0 seeding pass
+  int seed_stride;             // that pass visits every seed_stride-th block of the query
 };
 
 struct BatchArgs {
@@ -25,7 +26,6 @@ struct BatchArgs {
   unsigned long long *work;    // work-queue counter (cleared by the graph)
   int chunk;                   // units taken per queue access
   int64_t total_seed_blocks;
-  int seed_stride;
   int seed_window;
   float *bnd;
   int64_t bnd_stride;

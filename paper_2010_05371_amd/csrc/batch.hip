@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64) void batch_seed0_kernel(BatchArgs a) {
   if (bq.r == 0) return;
   NNArgs n = batch_nnargs(a, bq);
   n.bsf = bq.bsf + 1;
-  n.block_stride = a.seed_stride;
+  n.block_stride = bq.seed_stride;
   nn_band_body<0, 8, false>(n, blockIdx.x - bq.seed_begin);
 }
 
