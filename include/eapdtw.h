@@ -112,7 +112,6 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *   "batch_chunk"    : work units taken per queue access in the batched search
  *   "batch_seed_stride": seed_stride of the batched search
  *   "wide_rows"      : rows per tile of the whole-matrix-window kernel (32, 64; 0=auto)
- *   "lanes_per_problem": reserved (1)
  *   "graph"          : 1 = replay batched searches from a captured hipGraph
  *   "force_wide"     : 1 = use the wide-window kernel even for narrow windows
  *   "border"         : 1 = the band search sweeps each row group only between
@@ -123,6 +122,12 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *   "ed"             : 1 = window-0 searches and seeding passes use the
  *                      squared-Euclidean kernel (default), 0 = the band kernel
  *                      (same bits)
+ *   "lanes"          : 1 = band searches (windows 1-64, query length a multiple
+ *                      of 4 up to 2048) give each lane its own stream of
+ *                      candidates, refilling a lane as soon as its candidate is
+ *                      abandoned, over the whole band; 0 = wave-synchronous
+ *                      row groups (default).  Same answers; the refill kernel
+ *                      keeps more lanes busy but is slower on this hardware
  * Returns EINVAL for an unknown key or value. */
 int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
 int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);

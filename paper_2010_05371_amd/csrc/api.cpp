@@ -36,7 +36,6 @@ struct eapdtw_ctx {
   int64_t seed = 1;
   int64_t rows_per_group = 0;
   int64_t wide_rows = 0;
-  int64_t lanes_per_problem = 1;
   int64_t graph = 1;
   int64_t force_wide = 0;
   int64_t seed_stride = 0;  // 0: about kSeedBlocks blocks per search
@@ -44,6 +43,7 @@ struct eapdtw_ctx {
   int64_t border = 1;
   int64_t ed = 1;
   int64_t autotune = 0;
+  int64_t lanes = 0;  // band search with lane refill where it applies
   std::map<int64_t, eapdtw_tune> tune;  // autotuning cache, by (length, window) bucket
   int64_t seed_window = 8;
   int64_t batch_grid = 2048;
@@ -300,7 +300,6 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "seed")) return &ctx->seed;
   if (!strcmp(key, "rows_per_group")) return &ctx->rows_per_group;
   if (!strcmp(key, "wide_rows")) return &ctx->wide_rows;
-  if (!strcmp(key, "lanes_per_problem")) return &ctx->lanes_per_problem;
   if (!strcmp(key, "graph")) return &ctx->graph;
   if (!strcmp(key, "force_wide")) return &ctx->force_wide;
   if (!strcmp(key, "seed_stride")) return &ctx->seed_stride;
@@ -311,6 +310,7 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "border")) return &ctx->border;
   if (!strcmp(key, "ed")) return &ctx->ed;
   if (!strcmp(key, "autotune")) return &ctx->autotune;
+  if (!strcmp(key, "lanes")) return &ctx->lanes;
   return nullptr;
 }
 
@@ -321,11 +321,11 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   bool ok = true;
   if (!strcmp(key, "check_interval")) ok = value >= 0 && value <= (1 << 20);
   else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide") ||
-           !strcmp(key, "border") || !strcmp(key, "ed") || !strcmp(key, "autotune"))
+           !strcmp(key, "border") || !strcmp(key, "ed") || !strcmp(key, "autotune") ||
+           !strcmp(key, "lanes"))
     ok = value == 0 || value == 1;
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
-  else if (!strcmp(key, "lanes_per_problem")) ok = value == 1;
   else if (!strcmp(key, "seed_stride")) ok = value >= 0 && value <= (1 << 20);
   else if (!strcmp(key, "seed_window")) ok = value >= 0 && value <= kBandRMax;
   else if (!strcmp(key, "batch_grid")) ok = value >= 64 && value <= 65536;
@@ -664,6 +664,8 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     a.dists = dists;
     if (r == 0 && ctx->ed)
       HIPCHK(launch_ed_search(a, nblk, dists != nullptr, st));
+    else if (!dists && ctx->lanes && lane_search_supported((int)r, (int)m))
+      HIPCHK(launch_lane_search((int)r, a, st));
     else
       HIPCHK(nn_band_launcher((int)r)(a, nblk, dists ? 4 : pick_rows(ctx, (int)r), dists != nullptr,
                                       ctx->border != 0, st));

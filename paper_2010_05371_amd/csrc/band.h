@@ -69,9 +69,11 @@ __device__ __forceinline__ uint32_t umin3(uint32_t a, uint32_t b, uint32_t c) {
 // with P(m) = sum of y[0..m) reduced over the wave and the two partial sums
 // from wave scans.  Loads past the end of the series are clamped; they only
 // reach lanes whose offset is itself past the end.
-__device__ __forceinline__ void wave_window_stats(const float *__restrict__ x, int64_t n, int m,
-                                                  int64_t kb, int lane, double &mean,
-                                                  double &sd) {
+// X: anything indexable by a series position (a global pointer, or a view of
+// a stretch staged in LDS); every caller gets the same float64 arithmetic.
+template <class X>
+__device__ __forceinline__ void wave_window_stats(X x, int64_t n, int m, int64_t kb, int lane,
+                                                  double &mean, double &sd) {
   const double pivot = (double)x[kb];
   int64_t ia = kb + lane, ib = kb + m + lane;
   ia = ia < n ? ia : n - 1;

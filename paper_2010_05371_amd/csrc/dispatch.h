@@ -10,6 +10,12 @@ typedef hipError_t (*NNLaunchFn)(const NNArgs &, int64_t nblocks, int rows_per_g
 typedef hipError_t (*PairLaunchFn)(const PairArgs &, int64_t nblocks, int rows_per_group,
                                    hipStream_t);
 
+// Band search with lane refill (lanes.hip): windows 1..kBandRMax, query
+// lengths that are multiples of 4 up to kLaneMaxM, offsets from 0.
+constexpr int kLaneMaxM = 2048;
+bool lane_search_supported(int r, int m);
+hipError_t launch_lane_search(int r, const NNArgs &a, hipStream_t st);
+
 // Window 0: early-abandoned squared Euclidean distance (ed.hip).
 hipError_t launch_ed_search(const NNArgs &a, int64_t nblocks, bool dists, hipStream_t st);
 
