@@ -18,7 +18,13 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
 * ``dtw_grad``    -- optimal warping path (Section 2) and the gradient of the
   path cost with respect to both series;
 * ``eap_model``   -- a model of Algorithm 3 (Section 4), kept only to check the
-  threshold contract and the worked example (never a reference value).
+  threshold contract and the worked example (never a reference value);
+* ``envelope``, ``lb_kim``, ``lb_keogh``, ``nn_lower_bounds`` -- the lower
+  bounds of Section 2.2 that the search experiments of Section 5 put in front
+  of the DTW (LB_Kim, LB_Keogh with the query's and with the candidate's
+  envelope);
+* ``nn_search_lb`` -- the search with that cascade (a sequential scan; it must
+  return the brute-force answer).
 """
 from __future__ import annotations
 
@@ -77,6 +83,16 @@ def _load():
     lib.oracle_dtw_pairs.restype = ctypes.c_int
     lib.oracle_eap_model.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double, ip, ip, ip, ip]
     lib.oracle_eap_model.restype = ctypes.c_double
+    lib.oracle_envelope.argtypes = [dp, i64, i64, dp, dp]
+    lib.oracle_envelope.restype = None
+    lib.oracle_lb_kim.argtypes = [dp, dp, i64]
+    lib.oracle_lb_kim.restype = ctypes.c_double
+    lib.oracle_lb_keogh.argtypes = [dp, dp, dp, i64]
+    lib.oracle_lb_keogh.restype = ctypes.c_double
+    lib.oracle_nn_lower_bounds.argtypes = [dp, i64, dp, i64, i64, ip, i64, dp, dp, dp]
+    lib.oracle_nn_lower_bounds.restype = ctypes.c_int
+    lib.oracle_nn_search_lb.argtypes = [dp, i64, dp, i64, i64, ip, dp, ip]
+    lib.oracle_nn_search_lb.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -206,3 +222,51 @@ def eap_model(S, T, window: int | None, ub: float):
     v = _load().oracle_eap_model(_ptr(S), S.size, _ptr(T), T.size, r, float(ub), _ptr(cells),
                                  _ptr(trace), _ptr(ai), _ptr(aj))
     return float(v), int(cells[0]), trace[:nl].tolist(), (int(ai[0]), int(aj[0]))
+
+
+def envelope(a, window: int):
+    """(U, L): running max and min of a over [t - r, t + r], clipped to the series."""
+    a = _f64(a)
+    U, L = np.empty_like(a), np.empty_like(a)
+    _load().oracle_envelope(_ptr(a), a.size, int(window), _ptr(U), _ptr(L))
+    return U, L
+
+
+def lb_kim(q, c) -> float:
+    """LB_Kim of two equal-length series (three levels from each end)."""
+    q, c = _f64(q), _f64(c)
+    assert q.size == c.size
+    return float(_load().oracle_lb_kim(_ptr(q), _ptr(c), q.size))
+
+
+def lb_keogh(a, U, L) -> float:
+    """Sum of squared distances from a[t] to [L[t], U[t]]."""
+    a, U, L = _f64(a), _f64(U), _f64(L)
+    return float(_load().oracle_lb_keogh(_ptr(a), _ptr(U), _ptr(L), a.size))
+
+
+def nn_lower_bounds(query, series, window: int, offsets):
+    """(kim, eq, ec) arrays of the listed candidates of the z-normalised search."""
+    q, x = _f64(query), _f64(series)
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    kim, eq, ec = np.empty(offs.size), np.empty(offs.size), np.empty(offs.size)
+    rc = _load().oracle_nn_lower_bounds(_ptr(q), q.size, _ptr(x), x.size, int(window),
+                                        _ptr(offs), offs.size, _ptr(kim), _ptr(eq), _ptr(ec))
+    if rc != 0:
+        raise ValueError(f"oracle_nn_lower_bounds failed ({rc})")
+    return kim, eq, ec
+
+
+def nn_search_lb(query, series, window: int):
+    """(best offset, best distance, counts) of the cascade search; counts =
+    (skipped by LB_Kim, by LB_Keogh query envelope, by LB_Keogh candidate
+    envelope, DTW computed)."""
+    q, x = _f64(query), _f64(series)
+    bk = np.empty(1, dtype=np.int64)
+    bd = np.empty(1)
+    counts = np.empty(4, dtype=np.int64)
+    rc = _load().oracle_nn_search_lb(_ptr(q), q.size, _ptr(x), x.size, int(window), _ptr(bk),
+                                     _ptr(bd), _ptr(counts))
+    if rc != 0:
+        raise ValueError(f"oracle_nn_search_lb failed ({rc})")
+    return int(bk[0]), float(bd[0]), tuple(int(c) for c in counts)

@@ -457,3 +457,163 @@ double oracle_eap_model(const double *S, int64_t lS, const double *T, int64_t lT
   free(b);
   return result;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Lower bounds for the search (Section 2.2: a cheap lb <= DTW lets a        */
+/* candidate be skipped when lb is strictly above ub; the paper names        */
+/* LB_Kim and LB_Keogh, and its experiments (Section 5) keep the UCR Suite's */
+/* three: LB_Kim, LB_Keogh with the query's envelope and LB_Keogh with the   */
+/* candidate's).  The paper gives no formulas; these are the plain           */
+/* definitions, each a sum of costs that every admissible warping path pays. */
+/* ------------------------------------------------------------------------- */
+
+/* Envelope of a[0..n) under window r: U[t] = max a[t-r..t+r], L[t] = min,
+ * the window clipped to [0, n). */
+void oracle_envelope(const double *a, int64_t n, int64_t r, double *U, double *L) {
+  for (int64_t t = 0; t < n; ++t) {
+    int64_t lo = t - r < 0 ? 0 : t - r;
+    int64_t hi = t + r > n - 1 ? n - 1 : t + r;
+    double u = a[lo], l = a[lo];
+    for (int64_t s = lo + 1; s <= hi; ++s) {
+      if (a[s] > u) u = a[s];
+      if (a[s] < l) l = a[s];
+    }
+    U[t] = u;
+    L[t] = l;
+  }
+}
+
+static inline double sqd(double a, double b) { return (a - b) * (a - b); }
+
+/* LB_Kim over two series of equal length m (cells (i, j), 0-based, cost
+ * (q_i - c_j)^2).  Every warping path from (0,0) to (m-1,m-1) moves max(i,j)
+ * and min(i,j) up by at most one per step, so for each level a = 1..L it
+ * visits a cell with max(i,j) = a-1 (front set F_a) and a cell with
+ * min(i,j) = m-a (back set B_a, both coordinates >= m-a).  Those 2L sets are
+ * pairwise disjoint when 2L <= m, so the sum over them of the cheapest cell is
+ * a lower bound for any window (a set's cells outside the window only lower
+ * its minimum).  L = min(3, m/2). */
+double oracle_lb_kim(const double *q, const double *c, int64_t m) {
+  int64_t L = m / 2 < 3 ? m / 2 : 3;
+  double lb = 0.0;
+  for (int64_t a = 1; a <= L; ++a) {
+    int64_t f = a - 1, b = m - a;
+    double mf = INFINITY, mb = INFINITY;
+    for (int64_t s = 0; s <= f; ++s) {
+      /* front: (s, f) and (f, s) */
+      if (sqd(q[s], c[f]) < mf) mf = sqd(q[s], c[f]);
+      if (sqd(q[f], c[s]) < mf) mf = sqd(q[f], c[s]);
+    }
+    for (int64_t s = b; s < m; ++s) {
+      /* back: (s, b) and (b, s) */
+      if (sqd(q[s], c[b]) < mb) mb = sqd(q[s], c[b]);
+      if (sqd(q[b], c[s]) < mb) mb = sqd(q[b], c[s]);
+    }
+    lb += mf + mb;
+  }
+  return lb;
+}
+
+/* LB_Keogh: sum over t of the squared distance from a[t] to [L[t], U[t]].
+ * With U, L the envelope of the other series under window r, every path
+ * visits each t of `a` at least once, paired with a point of the other series
+ * within r of t, so this is a lower bound of DTW under window r. */
+double oracle_lb_keogh(const double *a, const double *U, const double *L, int64_t m) {
+  double lb = 0.0;
+  for (int64_t t = 0; t < m; ++t) {
+    if (a[t] > U[t]) lb += sqd(a[t], U[t]);
+    else if (a[t] < L[t]) lb += sqd(a[t], L[t]);
+  }
+  return lb;
+}
+
+/* The three bounds of each listed candidate k of the z-normalised search:
+ *  kim[t] = LB_Kim(z(q), z(x[k..k+m)))
+ *  eq[t]  = LB_Keogh(z(x[k..k+m)); envelope of z(q) under r)
+ *  ec[t]  = LB_Keogh(z(q); candidate envelope), where the candidate envelope is
+ *           the envelope of the whole series x under r at positions k..k+m-1,
+ *           z-normalised with the candidate's mean and sigma (all zeros when
+ *           sigma is zero).  Near the candidate's ends that window reaches
+ *           past the candidate, which only widens the envelope.
+ * Returns 0 on success. */
+int oracle_nn_lower_bounds(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                           const int64_t *offsets, int64_t noff, double *kim, double *eq,
+                           double *ec) {
+  if (m <= 0 || n < m || r < 0) return -2;
+  for (int64_t t = 0; t < noff; ++t)
+    if (offsets[t] < 0 || offsets[t] + m > n) return -2;
+  double *zq = malloc((size_t)m * sizeof(double)), *zc = malloc((size_t)m * sizeof(double));
+  double *Uq = malloc((size_t)m * sizeof(double)), *Lq = malloc((size_t)m * sizeof(double));
+  double *Uc = malloc((size_t)m * sizeof(double)), *Lc = malloc((size_t)m * sizeof(double));
+  double *Ux = malloc((size_t)n * sizeof(double)), *Lx = malloc((size_t)n * sizeof(double));
+  int rc = -1;
+  if (!zq || !zc || !Uq || !Lq || !Uc || !Lc || !Ux || !Lx) goto done;
+  oracle_znorm(q, m, zq);
+  oracle_envelope(zq, m, r, Uq, Lq);
+  oracle_envelope(x, n, r, Ux, Lx);
+  for (int64_t t = 0; t < noff; ++t) {
+    const int64_t k = offsets[t];
+    double mean = 0.0, var = 0.0;
+    for (int64_t s = 0; s < m; ++s) mean += x[k + s];
+    mean /= (double)m;
+    for (int64_t s = 0; s < m; ++s) var += sqd(x[k + s], mean);
+    const double sd = sqrt(var / (double)m);
+    for (int64_t s = 0; s < m; ++s) {
+      zc[s] = sd > 0.0 ? (x[k + s] - mean) / sd : 0.0;
+      Uc[s] = sd > 0.0 ? (Ux[k + s] - mean) / sd : 0.0;
+      Lc[s] = sd > 0.0 ? (Lx[k + s] - mean) / sd : 0.0;
+    }
+    kim[t] = oracle_lb_kim(zq, zc, m);
+    eq[t] = oracle_lb_keogh(zc, Uq, Lq, m);
+    ec[t] = oracle_lb_keogh(zq, Uc, Lc, m);
+  }
+  rc = 0;
+done:
+  free(zq); free(zc); free(Uq); free(Lq); free(Uc); free(Lc); free(Ux); free(Lx);
+  return rc;
+}
+
+/* Nearest-neighbour search with the lower-bound cascade in front of the DTW
+ * (the UCR Suite arrangement the paper's experiments use, Section 5): a
+ * sequential scan of every offset that skips a candidate as soon as one of
+ * LB_Kim, LB_Keogh(query envelope), LB_Keogh(candidate envelope), in that
+ * order, is strictly above the best distance so far; the others get the full
+ * DTW under window r.  Since every bound is a lower bound, the answer is the
+ * brute-force answer (same lexicographic minimum of (distance, offset)).
+ * counts[0..3] = candidates skipped by each bound, then candidates whose DTW
+ * was computed.  Single-threaded; for small inputs.  Returns 0 on success. */
+int oracle_nn_search_lb(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                        int64_t *best_k, double *best_d, int64_t *counts) {
+  if (m <= 0 || n < m || r < 0) return -2;
+  const int64_t K = n - m + 1;
+  double *kim = malloc((size_t)K * sizeof(double)), *eq = malloc((size_t)K * sizeof(double));
+  double *ec = malloc((size_t)K * sizeof(double)), *zq = malloc((size_t)m * sizeof(double));
+  double *zc = malloc((size_t)m * sizeof(double));
+  int64_t *offs = malloc((size_t)K * sizeof(int64_t));
+  dtw_ws w = {0, 0};
+  int rc = -1;
+  if (!kim || !eq || !ec || !zq || !zc || !offs) goto done;
+  for (int64_t k = 0; k < K; ++k) offs[k] = k;
+  if ((rc = oracle_nn_lower_bounds(q, m, x, n, r, offs, K, kim, eq, ec)) != 0) goto done;
+  rc = -1;
+  oracle_znorm(q, m, zq);
+  for (int i = 0; i < 4; ++i) counts[i] = 0;
+  double bd = INFINITY;
+  int64_t bk = -1;
+  for (int64_t k = 0; k < K; ++k) {
+    if (kim[k] > bd) { ++counts[0]; continue; }
+    if (eq[k] > bd) { ++counts[1]; continue; }
+    if (ec[k] > bd) { ++counts[2]; continue; }
+    ++counts[3];
+    oracle_znorm(x + k, m, zc);
+    const double d = dtw_matrix(&w, zq, m, zc, m, r);
+    if (!w.M) goto done;
+    if (bk < 0 || d < bd) { bd = d; bk = k; }
+  }
+  *best_k = bk;
+  *best_d = bd;
+  rc = 0;
+done:
+  free(kim); free(eq); free(ec); free(zq); free(zc); free(offs); free(w.M);
+  return rc;
+}
