@@ -535,11 +535,14 @@ double oracle_lb_keogh(const double *a, const double *U, const double *L, int64_
  *           z-normalised with the candidate's mean and sigma (all zeros when
  *           sigma is zero).  Near the candidate's ends that window reaches
  *           past the candidate, which only widens the envelope.
- * Returns 0 on success. */
+ * Between two series of length m a window of m-1 already admits every path
+ * (Section 2.1), so a wider window is taken as m-1 (it would only widen the
+ * series envelope).  Returns 0 on success. */
 int oracle_nn_lower_bounds(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
                            const int64_t *offsets, int64_t noff, double *kim, double *eq,
                            double *ec) {
   if (m <= 0 || n < m || r < 0) return -2;
+  if (r > m - 1) r = m - 1;
   for (int64_t t = 0; t < noff; ++t)
     if (offsets[t] < 0 || offsets[t] + m > n) return -2;
   double *zq = malloc((size_t)m * sizeof(double)), *zc = malloc((size_t)m * sizeof(double));
