@@ -278,6 +278,73 @@ int eapdtw_znorm(eapdtw_ctx *ctx, const float *x, int64_t m, float *out);
 int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                     int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats);
 
+/* ---------------------------------------------------------------------------
+ * Search with the lower-bound cascade in front of the DTW (Section 2.2: a
+ * lower bound strictly above the bound skips the candidate; Section 5: the
+ * search experiments' configuration with the UCR Suite's bounds, and the bound
+ * tightened row by row with the cumulative lower bound).
+ *
+ * Per candidate k, on z-normalised values, in this order:
+ *   LB_Kim   : three levels from each end: level a adds the cheapest cell with
+ *              max(i,j) = a-1 and the cheapest with min(i,j) = m-a (every warping
+ *              path crosses both sets; they are disjoint for 2a <= m);
+ *   LB_Keogh : sum over t of the squared distance from z(c_t) to
+ *              [L_t, U_t], the envelope (running min / max over t-r..t+r, clipped)
+ *              of z(query);
+ *   LB_Keogh : sum over t of the squared distance from z(q_t) to the
+ *              candidate's envelope: the envelope of the whole series at k+t,
+ *              z-normalised with the candidate's mean and sigma (near the
+ *              candidate's ends it covers values past them: a wider, still valid
+ *              envelope).
+ * Bounds are computed in float32 and lowered by a relative 2^-18 before the
+ * comparison (their sums round differently from the DP's).  A candidate that
+ * passes all three gets the pruned, early-abandoned DTW, whose bound in row t
+ * is the best-so-far minus the rest of its query-envelope LB_Keogh (the terms
+ * of the rows below t).  The answer is the eapdtw_nn_search answer; a
+ * candidate whose distance is within float32 rounding of the best-so-far may be
+ * skipped, which can only change which of two such near-equal candidates is
+ * reported.
+ *
+ * Windows 1..64 with the band kernels take the cascade; window 0 (where
+ * LB_Keogh is the squared Euclidean distance the window-0 kernel computes
+ * anyway), wider windows and option force_wide run eapdtw_nn_search's path,
+ * reported as every candidate reaching the DTW.
+ *
+ * Counters of one call (lbstats may be NULL):
+ *   pruned_kim, pruned_keogh_eq, pruned_keogh_ec : candidates skipped by
+ *     LB_Kim, by LB_Keogh with the query's envelope, with the candidate's
+ *     (the bound pass compares with the best-so-far at its start);
+ *   pruned_recheck : candidates that passed, skipped when the DTW pass
+ *     compares their largest bound with its own, tighter, best-so-far;
+ *   dtw_candidates : candidates whose DTW was started;
+ *   lb_ms          : device time of the envelopes and the bound pass.
+ * In eapdtw_stats, main_kernel_ms is then the DTW pass over the survivors. */
+typedef struct {
+  uint64_t pruned_kim, pruned_keogh_eq, pruned_keogh_ec, pruned_recheck, dtw_candidates;
+  float lb_ms;
+} eapdtw_lb_stats;
+
+/* As eapdtw_nn_search, with the cascade.  Synchronous. */
+int eapdtw_nn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                        int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
+                        eapdtw_stats *stats, eapdtw_lb_stats *lbstats);
+
+/* As eapdtw_nn_dists, with the cascade against the fixed bound ub: a skipped
+ * candidate reads +inf (its distance is above ub).  Asynchronous unless stats
+ * or lbstats are requested. */
+int eapdtw_nn_dists_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                       int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats,
+                       eapdtw_lb_stats *lbstats);
+
+/* The three bounds of every candidate k in [0, n-m], in full (no skipping):
+ *   out_kim, out_eq, out_ec [n-m+1] : DEVICE float32 (LB_Kim, LB_Keogh with
+ *   the query's envelope, LB_Keogh with the candidate's envelope).
+ * window above 64 (after clamping to m-1): EINVAL.  Non-finite values:
+ * ENONFINITE.  Synchronous. */
+int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                           int64_t n, int64_t window, float *out_kim, float *out_eq,
+                           float *out_ec);
+
 #ifdef __cplusplus
 }
 #endif

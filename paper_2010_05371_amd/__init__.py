@@ -29,12 +29,13 @@ import threading
 import torch
 
 from . import _lib
-from ._lib import EapdtwError, Query, Result, Stats, Tune
+from ._lib import EapdtwError, LbStats, Query, Result, Stats, Tune
 
 __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_dists",
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
-           "tune_bucket", "tune_get", "tune_save", "tune_load"]
+           "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
+           "nn_lower_bounds", "LbStats"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -226,6 +227,53 @@ def nn_dists(query, series, window: int, ub: float = math.inf, stats: bool = Fal
                                        int(window), float(ub), _ptr(out),
                                        ctypes.byref(st) if stats else None))
     return (out, st.as_dict()) if stats else out
+
+
+def nn_search_lb(query, series, window: int, stats: bool = False):
+    """nn_search with the lower-bound cascade (LB_Kim, LB_Keogh with the query's
+    and with the candidate's envelope) in front of the DTW.  With stats=True
+    returns ((offset, distance), stats) where stats also holds the cascade's
+    counters."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    off = ctypes.c_int64()
+    dist = ctypes.c_double()
+    st, ls = Stats(), LbStats()
+    ctx.check(ctx._lib.eapdtw_nn_search_lb(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                           int(window), ctypes.byref(off), ctypes.byref(dist),
+                                           ctypes.byref(st) if stats else None,
+                                           ctypes.byref(ls) if stats else None))
+    res = (off.value, dist.value)
+    return (res, {**st.as_dict(), **ls.as_dict()}) if stats else res
+
+
+def nn_dists_lb(query, series, window: int, ub: float = math.inf, stats: bool = False):
+    """nn_dists with the lower-bound cascade against the fixed bound ub."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    out = torch.empty(x.numel() - q.numel() + 1, device=x.device, dtype=torch.float32)
+    st, ls = Stats(), LbStats()
+    ctx.check(ctx._lib.eapdtw_nn_dists_lb(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                          int(window), float(ub), _ptr(out),
+                                          ctypes.byref(st) if stats else None,
+                                          ctypes.byref(ls) if stats else None))
+    return (out, {**st.as_dict(), **ls.as_dict()}) if stats else out
+
+
+def nn_lower_bounds(query, series, window: int):
+    """(LB_Kim, LB_Keogh query envelope, LB_Keogh candidate envelope) of every
+    candidate offset, float32 tensors on the series' device."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    K = x.numel() - q.numel() + 1
+    out = [torch.empty(max(K, 0), device=x.device, dtype=torch.float32) for _ in range(3)]
+    ctx.check(ctx._lib.eapdtw_nn_lower_bounds(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                              int(window), _ptr(out[0]), _ptr(out[1]),
+                                              _ptr(out[2])))
+    return tuple(out)
 
 
 def autotune(query, series, window: int, sample_n: int = 1 << 18) -> dict:

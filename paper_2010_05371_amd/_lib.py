@@ -31,6 +31,16 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class LbStats(ctypes.Structure):
+    _fields_ = [("pruned_kim", ctypes.c_uint64), ("pruned_keogh_eq", ctypes.c_uint64),
+                ("pruned_keogh_ec", ctypes.c_uint64), ("pruned_recheck", ctypes.c_uint64),
+                ("dtw_candidates", ctypes.c_uint64),
+                ("lb_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Query(ctypes.Structure):
     _fields_ = [("query", ctypes.c_void_p), ("m", ctypes.c_int64), ("window", ctypes.c_int64)]
 
@@ -64,6 +74,7 @@ def load():
     vp, i64, i32, f32, f64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_float,
                               ctypes.c_double)
     sp = ctypes.POINTER(Stats)
+    lp = ctypes.POINTER(LbStats)
     sig = {
         "eapdtw_version": ([], ctypes.c_char_p),
         "eapdtw_create": ([i32, vp, ctypes.POINTER(vp)], i32),
@@ -90,6 +101,10 @@ def load():
         "eapdtw_tune_get": ([vp, i64, ctypes.POINTER(Tune)], i32),
         "eapdtw_tune_save": ([vp, ctypes.c_char_p], i32),
         "eapdtw_tune_load": ([vp, ctypes.c_char_p], i32),
+        "eapdtw_nn_search_lb": ([vp, vp, i64, vp, i64, i64, ctypes.POINTER(i64),
+                                 ctypes.POINTER(f64), sp, lp], i32),
+        "eapdtw_nn_dists_lb": ([vp, vp, i64, vp, i64, i64, f32, vp, sp, lp], i32),
+        "eapdtw_nn_lower_bounds": ([vp, vp, i64, vp, i64, i64, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

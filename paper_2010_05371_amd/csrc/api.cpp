@@ -30,7 +30,7 @@ struct eapdtw_ctx {
   size_t scratch_cap = 0;
   char *pinned = nullptr;
   size_t pinned_cap = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
   // options
   int64_t check_interval = 0;  // 0: chosen per window
   int64_t seed = 1;
@@ -249,7 +249,8 @@ int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-      hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess) {
+      hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess ||
+      hipEventCreate(&c->ev4) != hipSuccess) {
     g_create_error = "hipEventCreate failed";
     delete c;
     return EAPDTW_EDEVICE;
@@ -268,6 +269,7 @@ void eapdtw_destroy(eapdtw_ctx *ctx) {
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
+  if (ctx->ev4) (void)hipEventDestroy(ctx->ev4);
   if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
   if (ctx->batch_buf) (void)hipFree(ctx->batch_buf);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -588,10 +590,36 @@ static int search_validate(eapdtw_ctx *ctx, const float *query, int64_t m, const
 // seeding, and the DP pass over offsets [0, n-m].  dists != nullptr selects the
 // per-candidate mode against fixed_ub (no best-so-far).  bsf points at two
 // words (search, seeding pass); cnt at cleared counters.
+// Device buffers of the lower-bound cascade (see LBArgs / NNArgs list mode).
+struct LbBufs {
+  float *ux, *lx, *uq, *lq;                           // envelopes [n], [n], [m], [m]
+  uint32_t *lk;                                       // survivor list [K]
+  float *lmh, *lml, *linv, *lbq, *lbmax;              // [K] each
+};
+
+static void lb_plan(Plan &pl, size_t *offs, int64_t n, int64_t m, int64_t K) {
+  offs[0] = pl.add(sizeof(float) * n);
+  offs[1] = pl.add(sizeof(float) * n);
+  offs[2] = pl.add(sizeof(float) * m);
+  offs[3] = pl.add(sizeof(float) * m);
+  for (int i = 0; i < 6; ++i) offs[4 + i] = pl.add(sizeof(float) * K);
+}
+
+static LbBufs lb_bind(eapdtw_ctx *ctx, const size_t *offs) {
+  return LbBufs{at<float>(ctx, offs[0]), at<float>(ctx, offs[1]), at<float>(ctx, offs[2]),
+                at<float>(ctx, offs[3]), at<uint32_t>(ctx, offs[4]), at<float>(ctx, offs[5]),
+                at<float>(ctx, offs[6]), at<float>(ctx, offs[7]), at<float>(ctx, offs[8]),
+                at<float>(ctx, offs[9])};
+}
+
+// The cascade serves band windows from 1 on (at window 0 LB_Keogh is the
+// squared Euclidean distance itself, which the window-0 kernel computes).
+static bool lb_applies(const eapdtw_ctx *ctx, int64_t r) { return r >= 1 && use_band(ctx, r); }
+
 static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                         int64_t n, int64_t r, float *qpad, unsigned long long *bsf,
                         unsigned long long *cnt, float *dists, float fixed_ub, float *bnd,
-                        int64_t bnd_waves, bool time_main) {
+                        int64_t bnd_waves, bool time_main, const LbBufs *lb = nullptr) {
   hipStream_t st = ctx->stream;
   const int64_t K = n - m + 1;
   const int64_t nblk = (K + kWave - 1) / kWave;
@@ -657,7 +685,51 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     }
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev2, st));
-  if (use_band(ctx, r)) {
+  if (lb && lb_applies(ctx, r)) {
+    // envelopes, the bound pass (survivor list), then the DP over the list
+    HIPCHK(launch_envelopes(series, n, qpad + kColPad, (int)m, (int)r, lb->ux, lb->lx, lb->uq,
+                            lb->lq, st));
+    LBArgs la{};
+    la.x = series;
+    la.n = n;
+    la.m = (int)m;
+    la.r = (int)r;
+    la.qz = qpad + kColPad;
+    la.uq = lb->uq;
+    la.lq = lb->lq;
+    la.ux = lb->ux;
+    la.lx = lb->lx;
+    la.k_begin = 0;
+    la.k_end = K;
+    la.mode = dists ? 1 : 0;
+    la.bsf = bsf;
+    la.bsf_init = a.bsf_init;
+    la.fixed_ub = fixed_ub;
+    la.dists = dists;
+    la.counters = cnt;
+    la.list_k = lb->lk;
+    la.list_mh = lb->lmh;
+    la.list_ml = lb->lml;
+    la.list_inv = lb->linv;
+    la.list_lbq = lb->lbq;
+    la.list_lbmax = lb->lbmax;
+    HIPCHK(launch_lb_pass(la, st));
+    if (time_main) HIPCHK(hipEventRecord(ctx->ev4, st));
+    a.bsf = bsf;
+    a.counters = cnt;
+    a.fixed_ub = fixed_ub;
+    a.dists = dists;
+    a.list_n = cnt + kCntListN;
+    a.list_k = lb->lk;
+    a.list_mh = lb->lmh;
+    a.list_ml = lb->lml;
+    a.list_inv = lb->linv;
+    a.list_lbq = lb->lbq;
+    a.list_lbmax = lb->lbmax;
+    a.uq = lb->uq;
+    a.lq = lb->lq;
+    HIPCHK(nn_list_launcher((int)r)(a, nblk, dists != nullptr, ctx->border != 0, st));
+  } else if (use_band(ctx, r)) {
     a.bsf = bsf;
     a.counters = cnt;
     a.fixed_ub = fixed_ub;
@@ -740,9 +812,25 @@ struct KnobGuard {
 
 }  // namespace
 
-int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
-                     int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
-                     eapdtw_stats *stats) {
+static void fill_lb_stats(eapdtw_lb_stats *ls, const unsigned long long *cnt, bool applied,
+                          uint64_t K, float lb_ms) {
+  if (!ls) return;
+  std::memset(ls, 0, sizeof *ls);
+  if (!applied) {
+    ls->dtw_candidates = K;
+    return;
+  }
+  ls->pruned_kim = counter_sum(cnt, kCntLbKim);
+  ls->pruned_keogh_eq = counter_sum(cnt, kCntLbEq);
+  ls->pruned_keogh_ec = counter_sum(cnt, kCntLbEc);
+  ls->pruned_recheck = counter_sum(cnt, kCntLbRecheck);
+  ls->dtw_candidates = counter_sum(cnt, kCntListN) - ls->pruned_recheck;
+  ls->lb_ms = lb_ms;
+}
+
+static int nn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                          int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
+                          eapdtw_stats *stats, bool use_lb, eapdtw_lb_stats *lbstats) {
   CHECK_CTX();
   KnobGuard knobs(ctx);
   knobs.apply_cached(m, window);
@@ -753,22 +841,28 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
   const int64_t r = window < m - 1 ? window : m - 1;
   const int64_t K = n - m + 1;
   const int64_t grid = use_band(ctx, r) ? 0 : wide_grid((K + kWave - 1) / kWave);
+  const bool lb_on = use_lb && lb_applies(ctx, r);
+  const bool timed = stats != nullptr || lbstats != nullptr;
   Plan pl;
   const size_t o_cnt = pl.add(kCntBytes);
   const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);  // [0] search, [1] seeding pass
   const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
   const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
+  size_t o_lb[10];
+  if (lb_on) lb_plan(pl, o_lb, n, m, K);
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   unsigned long long *bsf = at<unsigned long long>(ctx, o_bsf);
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
-  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  LbBufs lbb{};
+  if (lb_on) lbb = lb_bind(ctx, o_lb);
+  if (timed) HIPCHK(hipEventRecord(ctx->ev0, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
-                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr);
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr);
   if (rc) return rc;
-  if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
+  if (timed) HIPCHK(hipEventRecord(ctx->ev1, st));
   // counters and the two best-so-far words are contiguous
   rc = readback(ctx, o_cnt, o_bsf + 2 * sizeof(unsigned long long) - o_cnt);
   if (rc) return rc;
@@ -780,12 +874,29 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
   *out_dist = (double)best_dist(best);
   if (stats)
     fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
-               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+               elapsed(ctx->ev0, ctx->ev1),
+               lb_on ? elapsed(ctx->ev4, ctx->ev3) : elapsed(ctx->ev2, ctx->ev3));
+  fill_lb_stats(lbstats, hc, lb_on, (uint64_t)K, lb_on ? elapsed(ctx->ev2, ctx->ev4) : 0.f);
   return EAPDTW_OK;
 }
 
-int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
-                    int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats) {
+int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                     int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
+                     eapdtw_stats *stats) {
+  return nn_search_impl(ctx, query, m, series, n, window, out_offset, out_dist, stats, false,
+                        nullptr);
+}
+
+int eapdtw_nn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                        int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
+                        eapdtw_stats *stats, eapdtw_lb_stats *lbstats) {
+  return nn_search_impl(ctx, query, m, series, n, window, out_offset, out_dist, stats, true,
+                        lbstats);
+}
+
+static int nn_dists_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                         int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats,
+                         bool use_lb, eapdtw_lb_stats *lbstats) {
   CHECK_CTX();
   KnobGuard knobs(ctx);
   knobs.apply_cached(m, window);
@@ -797,29 +908,100 @@ int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
   const int64_t r = window < m - 1 ? window : m - 1;
   const int64_t K = n - m + 1;
   const int64_t grid = use_band(ctx, r) ? 0 : wide_grid((K + kWave - 1) / kWave);
+  const bool lb_on = use_lb && lb_applies(ctx, r);
+  const bool timed = stats != nullptr || lbstats != nullptr;
   Plan pl;
   const size_t o_cnt = pl.add(kCntBytes);
   const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
   const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
   const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
+  size_t o_lb[10];
+  if (lb_on) lb_plan(pl, o_lb, n, m, K);
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
-  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  LbBufs lbb{};
+  if (lb_on) lbb = lb_bind(ctx, o_lb);
+  if (timed) HIPCHK(hipEventRecord(ctx->ev0, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q),
                     at<unsigned long long>(ctx, o_bsf), cnt, out, ub,
-                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr);
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr);
   if (rc) return rc;
-  if (stats) {
+  if (timed) {
     HIPCHK(hipEventRecord(ctx->ev1, st));
     rc = readback(ctx, o_cnt, kCntBytes);
     if (rc) return rc;
-    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned),
-               (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
-               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+    const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned);
+    fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
+               elapsed(ctx->ev0, ctx->ev1),
+               lb_on ? elapsed(ctx->ev4, ctx->ev3) : elapsed(ctx->ev2, ctx->ev3));
+    fill_lb_stats(lbstats, hc, lb_on, (uint64_t)K, lb_on ? elapsed(ctx->ev2, ctx->ev4) : 0.f);
   }
+  return EAPDTW_OK;
+}
+
+int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                    int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats) {
+  return nn_dists_impl(ctx, query, m, series, n, window, ub, out, stats, false, nullptr);
+}
+
+int eapdtw_nn_dists_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                       int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats,
+                       eapdtw_lb_stats *lbstats) {
+  return nn_dists_impl(ctx, query, m, series, n, window, ub, out, stats, true, lbstats);
+}
+
+int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                           int64_t n, int64_t window, float *out_kim, float *out_eq,
+                           float *out_ec) {
+  CHECK_CTX();
+  if (!out_kim || !out_eq || !out_ec) return fail(ctx, EAPDTW_EINVAL, "NULL output");
+  int rc = search_validate(ctx, query, m, series, n, window);
+  if (rc) return rc;
+  const int64_t r = window < m - 1 ? window : m - 1;
+  if (r > kBandRMax) return fail(ctx, EAPDTW_EINVAL, "lower bounds: window above 64");
+  const int64_t K = n - m + 1;
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  size_t o_lb[10];
+  lb_plan(pl, o_lb, n, m, K);
+  rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  float *qpad = at<float>(ctx, o_q);
+  const LbBufs lbb = lb_bind(ctx, o_lb);
+  if (++ctx->epoch == 0) ++ctx->epoch;
+  HIPCHK(launch_search_prep(query, (int)m, qpad, series, n, cnt, nullptr, 0,
+                            reinterpret_cast<unsigned *>(cnt + kCntWords), ctx->epoch, st));
+  HIPCHK(launch_envelopes(series, n, qpad + kColPad, (int)m, (int)r, lbb.ux, lbb.lx, lbb.uq, lbb.lq,
+                          st));
+  LBArgs la{};
+  la.x = series;
+  la.n = n;
+  la.m = (int)m;
+  la.r = (int)r;
+  la.qz = qpad + kColPad;
+  la.uq = lbb.uq;
+  la.lq = lbb.lq;
+  la.ux = lbb.ux;
+  la.lx = lbb.lx;
+  la.k_begin = 0;
+  la.k_end = K;
+  la.mode = 2;
+  la.out_kim = out_kim;
+  la.out_eq = out_eq;
+  la.out_ec = out_ec;
+  HIPCHK(launch_lb_pass(la, st));
+  rc = readback(ctx, o_cnt, kCntBytes);
+  if (rc) return rc;
+  if (*reinterpret_cast<const unsigned *>(reinterpret_cast<unsigned long long *>(ctx->pinned) +
+                                          kCntWords) == ctx->epoch)
+    return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
   return EAPDTW_OK;
 }
 

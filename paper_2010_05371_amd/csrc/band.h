@@ -528,38 +528,57 @@ __device__ __forceinline__ float load_bsf_dist(const unsigned long long *bsf) {
 // value per column, read through the scalar cache).
 // DISTS = true writes every candidate's early-abandoned distance against the
 // fixed bound instead of updating the shared best-so-far.
-template <int R, int U, bool DISTS, bool BORDER = false>
+template <int R, int U, bool DISTS, bool BORDER = false, bool LIST = false>
 __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   constexpr int W = 2 * R + 1;
   const int lane = threadIdx.x;
-  int64_t kbeg = a.k_begin, kend = a.k_end;
-  if (a.center) {
-    // seed launch: 64 offsets centred on the best offset of an earlier pass
-    const unsigned long long c = *a.center;
-    int64_t ck = (int64_t)best_offset(c);
-    if (ck > kend - 1) ck = kend - 1;
-    int64_t lo = ck - 32;
-    if (lo < kbeg) lo = kbeg;
-    if (lo + 64 < kend) kend = lo + 64;
-    kbeg = lo;
-    if (a.bsf_init && lane == 0) atomicMin(a.bsf, pack_best(best_dist(*a.bsf_init), 0xffffffffu));
-  }
-  const int64_t kb = kbeg + blk * kWave * (a.block_stride > 1 ? a.block_stride : 1);
-  if (kb >= kend) return;
-  const int64_t k = kb + lane;
-  const bool active = k < kend;
-  const int64_t kc = active ? k : kend - 1;
   const int m = a.m;
-
-  double mean, sd;
-  wave_window_stats(a.x, a.n, m, kb, lane, mean, sd);
+  int64_t kb = 0, k;
+  bool active;
   float mu_hi, mu_lo, inv;
-  znorm_params(mean, sd, mu_hi, mu_lo, inv);
-  (void)kc;
+  // list mode: the candidate's series, its LB_Keogh (query envelope) total
+  // lowered by the margin, and its largest lower bound
+  const float *xk = nullptr;
+  float lb_total = 0.0f, lb_max = 0.0f;
+  if constexpr (LIST) {
+    const int64_t nl = (int64_t)*a.list_n;
+    const int64_t e0 = blk * kWave;
+    if (e0 >= nl) return;
+    active = e0 + lane < nl;
+    const int64_t e = active ? e0 + lane : nl - 1;
+    k = (int64_t)a.list_k[e];
+    mu_hi = a.list_mh[e];
+    mu_lo = a.list_ml[e];
+    inv = a.list_inv[e];
+    lb_total = a.list_lbq[e] * (1.0f - kLbMargin);
+    lb_max = a.list_lbmax[e];
+    xk = a.x + k;
+  } else {
+    int64_t kbeg = a.k_begin, kend = a.k_end;
+    if (a.center) {
+      // seed launch: 64 offsets centred on the best offset of an earlier pass
+      const unsigned long long c = *a.center;
+      int64_t ck = (int64_t)best_offset(c);
+      if (ck > kend - 1) ck = kend - 1;
+      int64_t lo = ck - 32;
+      if (lo < kbeg) lo = kbeg;
+      if (lo + 64 < kend) kend = lo + 64;
+      kbeg = lo;
+      if (a.bsf_init && lane == 0) atomicMin(a.bsf, pack_best(best_dist(*a.bsf_init), 0xffffffffu));
+    }
+    kb = kbeg + blk * kWave * (a.block_stride > 1 ? a.block_stride : 1);
+    if (kb >= kend) return;
+    k = kb + lane;
+    active = k < kend;
+    double mean, sd;
+    wave_window_stats(a.x, a.n, m, kb, lane, mean, sd);
+    znorm_params(mean, sd, mu_hi, mu_lo, inv);
+  }
 
   // The wave's 64 candidates read rows of one stretch of the series: it is
   // staged in LDS kStageRows rows at a time (one coalesced copy), so a row's
-  // values come from LDS instead of a dependent global load.
+  // values come from LDS instead of a dependent global load.  (List mode:
+  // the lanes' candidates lie anywhere, each lane reads its own rows.)
   __shared__ float stage[kWave + kStageRows - 1];
   int sbase = 0;  // first row held in stage
   auto refill = [&](int i0) {
@@ -570,8 +589,14 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
     for (int t = lane; t < kWave + kStageRows - 1; t += kWave) stage[t] = xs[t < lim ? t : lim];
     __syncthreads();
   };
-  stage_copy<kWave + kStageRows - 1>(stage, a.x + kb, a.n - 1 - kb, lane);
-  __syncthreads();
+  if constexpr (!LIST) {
+    stage_copy<kWave + kStageRows - 1>(stage, a.x + kb, a.n - 1 - kb, lane);
+    __syncthreads();
+  }
+  auto row_value = [&](int i) -> float {
+    if constexpr (LIST) return xk[i];
+    else return stage[lane + i - sbase];
+  };
 
   float v[W];
 #pragma unroll
@@ -584,6 +609,39 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   float ub = (DISTS ? a.fixed_ub : load_bsf_dist(a.bsf)) + 0.0f;
   if (!DISTS && a.bsf_init) ub = fminf(ub, best_dist(*a.bsf_init));
   bool alive = active && ub >= 0.0f;
+  uint64_t rechecked = 0;  // list mode: entries whose bound now exceeds the best-so-far
+  if constexpr (LIST) {
+    alive = alive && !(lb_max * (1.0f - kLbMargin) > ub);
+    rechecked = (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(active && !alive));
+  }
+  // List mode tightens the bound row by row (the UCR Suite's use of LB_Keogh):
+  // every path still has to pay, in each row t below the current one, at
+  // least the squared distance from z(c_t) to the query envelope [L_t, U_t]
+  // (the columns of row t lie within r of t), so a cell above
+  // ub - (sum of those terms) cannot reach a result <= ub.  The remaining sum
+  // is the lowered total minus the running prefix; the envelope is read one
+  // group ahead with vector loads (all lanes, one address).
+  float lb_prefix = 0.0f;
+  const float *uqv = a.uq, *lqv = a.lq;
+  if constexpr (LIST) {
+    int vz;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+    uqv += vz;
+    lqv += vz;
+  }
+  auto lb_term = [&](float z, float lo, float hi) {
+    const float dd = z - __builtin_amdgcn_fmed3f(z, lo, hi);
+    lb_prefix = __builtin_fmaf(dd, dd, lb_prefix);
+  };
+  // the bound for cells of rows up to the last one folded into lb_prefix
+  auto row_bound = [&]() -> float {
+    if constexpr (LIST) {
+      const float rest = lb_total - lb_prefix;
+      return ub - (rest > 0.0f ? rest : 0.0f);
+    } else {
+      return ub;
+    }
+  };
   // The shared best-so-far is read once every ci groups; each read is
   // issued ci groups before its value is applied, so its latency (an L2 round
   // trip) hides behind that many groups even when a group is short.
@@ -599,13 +657,31 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   int qfirst_unit = -1;  // bordered sweep: the unit they belong to (-1: none)
   if constexpr (!BORDER) load_first<U>(qfirst, Cols<ConstF *>{as_const(a.qpad + kColPad - R), 1, 0});
 
-  float rv_next[U];
+  float rv_next[U], uq_next[U], lq_next[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) rv_next[u] = (u < mg) ? stage[lane + u] : 0.0f;
+  for (int u = 0; u < U; ++u) {
+    rv_next[u] = (u < mg) ? row_value(u) : 0.0f;
+    uq_next[u] = 0.0f;
+    lq_next[u] = 0.0f;
+    if constexpr (LIST) {
+      if (u < mg) {
+        uq_next[u] = uqv[u];
+        lq_next[u] = lqv[u];
+      }
+    }
+  }
 
   // One group of G rows starting at row i.
-  auto group = [&](auto gtag, int i, const float *rvg) {
+  auto group = [&](auto gtag, int i, const float *rvg, const float *uqg, const float *lqg) {
     constexpr int G = decltype(gtag)::value;
+    float thr = ub;
+    if constexpr (LIST) {
+#pragma unroll
+      for (int u = 0; u < G; ++u) lb_term(rvg[u], lqg[u], uqg[u]);
+      thr = row_bound();
+      alive = alive && thr >= 0.0f;
+      thr = thr > 0.0f ? thr : 0.0f;
+    }
     if (!DISTS && !pending) {
       bpend = __hip_atomic_load(a.bsf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       pending = true;
@@ -618,7 +694,7 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
     for (int u = 0; u < G; ++u) rvl[u] = rvg[u];
     int slast = W + G - 2;
     if constexpr (BORDER) {
-      slast = sweep_group_border<R, G>(v, rvl, cols, bd, cell_bits(ub),
+      slast = sweep_group_border<R, G>(v, rvl, cols, bd, cell_bits(thr),
                                        __builtin_amdgcn_ballot_w64(alive), qfirst, qfirst_unit,
                                        as_const(a.qpad + kColPad + i + G - R));
       swept_cells<G>(i, kBorderChunk * bd.lo - 1, slast, m, R, band, mat);
@@ -632,38 +708,64 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
     if (!DISTS && ++since >= ci) {
       ub = fminf(ub, best_dist(bpend));
       pending = false;
+      if constexpr (LIST) {
+        thr = row_bound();
+        alive = alive && thr >= 0.0f;
+        thr = thr > 0.0f ? thr : 0.0f;
+      } else {
+        thr = ub;
+      }
     }
     if constexpr (BORDER) {
-      alive = border_update<R>(v, bd, cell_bits(ub), alive);
+      alive = border_update<R>(v, bd, cell_bits(thr), alive);
       if (bd.hi < 0) stopped = true;
     } else {
-      alive = alive && band_min<R>(v) <= ub;
+      alive = alive && band_min<R>(v) <= thr;
       if (!wave_any(alive)) stopped = true;
     }
   };
 
   for (int i0 = 0; i0 < mg && !stopped; i0 += U) {
-    float rv[U];
+    float rv[U], uqg[U], lqg[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) rv[u] = znorm_value(rv_next[u], mu_hi, mu_lo, inv);
+    for (int u = 0; u < U; ++u) {
+      rv[u] = znorm_value(rv_next[u], mu_hi, mu_lo, inv);
+      uqg[u] = uq_next[u];
+      lqg[u] = lq_next[u];
+    }
     if (i0 + U < mg) {
-      if (i0 + U - sbase >= kStageRows) {
-        sbase = i0 + U;
-        refill(sbase);
+      if constexpr (!LIST) {
+        if (i0 + U - sbase >= kStageRows) {
+          sbase = i0 + U;
+          refill(sbase);
+        }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) rv_next[u] = stage[lane + i0 + U + u - sbase];
+      for (int u = 0; u < U; ++u) {
+        rv_next[u] = row_value(i0 + U + u);
+        if constexpr (LIST) {
+          uq_next[u] = uqv[i0 + U + u];
+          lq_next[u] = lqv[i0 + U + u];
+        }
+      }
     }
-    group(std::integral_constant<int, U>{}, i0, rv);
+    group(std::integral_constant<int, U>{}, i0, rv, uqg, lqg);
   }
   // remaining rows, one at a time
   for (int i = mg; i < m && !stopped; ++i) {
-    if (i - sbase >= kStageRows) {
-      sbase = i;
-      refill(sbase);
+    if constexpr (!LIST) {
+      if (i - sbase >= kStageRows) {
+        sbase = i;
+        refill(sbase);
+      }
     }
-    const float rv1[1] = {znorm_value(stage[lane + i - sbase], mu_hi, mu_lo, inv)};
-    group(std::integral_constant<int, 1>{}, i, rv1);
+    const float rv1[1] = {znorm_value(row_value(i), mu_hi, mu_lo, inv)};
+    float uq1[1] = {0.0f}, lq1[1] = {0.0f};
+    if constexpr (LIST) {
+      uq1[0] = uqv[i];
+      lq1[0] = lqv[i];
+    }
+    group(std::integral_constant<int, 1>{}, i, rv1, uq1, lq1);
   }
 
   const float d = v[R];
@@ -680,6 +782,7 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
       atomicAdd(&c[kCntEvaluated], (unsigned long long)evaluated);
       atomicAdd(&c[kCntComputed], (unsigned long long)computed);
       atomicAdd(&c[kCntAbandoned], (unsigned long long)aband);
+      if (LIST) atomicAdd(&c[kCntLbRecheck], (unsigned long long)rechecked);
     }
   }
 }
@@ -689,6 +792,12 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
 template <int R, int U, bool DISTS, bool BORDER>
 __global__ __launch_bounds__(64, (BORDER && R <= 52) ? 4 : 1) void nn_band_kernel(NNArgs a) {
   nn_band_body<R, U, DISTS, BORDER>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// The candidates that passed the lower bounds (list mode of the same sweep).
+template <int R, int U, bool DISTS, bool BORDER>
+__global__ __launch_bounds__(64, (BORDER && R <= 48) ? 4 : 1) void nn_list_kernel(NNArgs a) {
+  nn_band_body<R, U, DISTS, BORDER, true>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -796,6 +905,9 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
 template <int R>
 hipError_t launch_nn_band(const NNArgs &a, int64_t nblocks, int rows_per_group, bool dists,
                           bool border, hipStream_t st);
+template <int R>
+hipError_t launch_nn_list(const NNArgs &a, int64_t nblocks, bool dists, bool border,
+                          hipStream_t st);
 template <int R>
 hipError_t launch_pair_band(const PairArgs &a, int64_t nblocks, int rows_per_group,
                             hipStream_t st);

@@ -29,7 +29,12 @@ enum Counter : int {
   kCntComputed = 1,   // all lane-cells computed
   kCntAbandoned = 2,  // problems finished as +inf
   kCntNonFinite = 3,  // non-finite input values seen
-  kCntSlots = 8
+  kCntLbKim = 4,      // candidates skipped by LB_Kim
+  kCntLbEq = 5,       // ... by LB_Keogh with the query's envelope
+  kCntLbEc = 6,       // ... by LB_Keogh with the candidate's envelope
+  kCntListN = 7,      // length of the survivor list (stripe 0 only: one address)
+  kCntLbRecheck = 8,  // list entries dropped when the DP pass re-checks their bound
+  kCntSlots = 9
 };
 constexpr int kCntStripes = 64;
 constexpr int kCntStride = 16;
@@ -83,6 +88,39 @@ struct NNArgs {
   int check_interval;                // row groups between best-so-far reloads
   int block_stride;                  // workgroup b covers offsets from k_begin + 64 b stride
   int bound_only;                    // record distance-only bounds (offset field all ones)
+  // List mode (candidates that passed the lower bounds): lane l of workgroup b
+  // takes list entry 64 b + l of list_n entries; the entry carries the offset,
+  // the z-normalisation constants and the lower bounds of the candidate.
+  const unsigned long long *list_n;
+  const uint32_t *list_k;
+  const float *list_mh, *list_ml, *list_inv;
+  const float *list_lbq;             // LB_Keogh with the query's envelope (full sum)
+  const float *list_lbmax;           // largest of the three bounds
+  const float *uq, *lq;              // envelope of z(query) [m]: tightening of the bound per row
+};
+
+// Relative margin by which float32 lower bounds are lowered before they are
+// compared with a distance: their sums round differently from the DP's.
+constexpr float kLbMargin = 1.0f / 262144.0f;  // 2^-18
+
+// Arguments of the lower-bound pass (lb.hip).
+struct LBArgs {
+  const float *x;                    // series [n]
+  int64_t n;
+  int m, r;
+  const float *qz;                   // z(query) [m]
+  const float *uq, *lq;              // envelope of z(query) under r [m]
+  const float *ux, *lx;              // envelope of the series under r [n]
+  int64_t k_begin, k_end;
+  int mode;                          // 0 search (bound = best-so-far), 1 fixed bound, 2 bounds only
+  unsigned long long *bsf;           // mode 0
+  const unsigned long long *bsf_init;// mode 0, optional
+  float fixed_ub;                    // mode 1
+  float *dists;                      // mode 1: +inf written for skipped candidates
+  float *out_kim, *out_eq, *out_ec;  // mode 2: [k - k_begin]
+  unsigned long long *counters;      // kCntWords; kCntListN of stripe 0 counts the list
+  uint32_t *list_k;                  // modes 0, 1: survivor list
+  float *list_mh, *list_ml, *list_inv, *list_lbq, *list_lbmax;
 };
 
 // Arguments of the pair band kernel.  Row and column series are stored

@@ -7,6 +7,10 @@ namespace eapdtw {
 // border selects the bordered sweep (windows of at least kBorderMinR only).
 typedef hipError_t (*NNLaunchFn)(const NNArgs &, int64_t nblocks, int rows_per_group, bool dists,
                                  bool border, hipStream_t);
+// List mode: the candidates of the survivor list (see NNArgs); nblocks covers
+// the largest possible list, workgroups past its end return at once.
+typedef hipError_t (*NNListLaunchFn)(const NNArgs &, int64_t nblocks, bool dists, bool border,
+                                     hipStream_t);
 typedef hipError_t (*PairLaunchFn)(const PairArgs &, int64_t nblocks, int rows_per_group,
                                    hipStream_t);
 
@@ -21,7 +25,14 @@ hipError_t launch_ed_search(const NNArgs &a, int64_t nblocks, bool dists, hipStr
 
 // Band-in-registers kernels for windows 0..kBandRMax (nullptr otherwise).
 NNLaunchFn nn_band_launcher(int r);
+NNListLaunchFn nn_list_launcher(int r);
 PairLaunchFn pair_band_launcher(int r);
+
+// Lower bounds (lb.hip): envelopes of the series and of z(query) under window
+// r, then the per-candidate LB_Kim / LB_Keogh pass.
+hipError_t launch_envelopes(const float *x, int64_t n, const float *qz, int m, int r, float *ux,
+                            float *lx, float *uq, float *lq, hipStream_t st);
+hipError_t launch_lb_pass(const LBArgs &a, hipStream_t st);
 
 // Wide-window kernels (wide_inst.hip): kind is a WideKind, rows the tile height
 // (16, 32 or 64), grid the number of persistent single-wave workgroups.
