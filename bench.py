@@ -82,6 +82,37 @@ def cpu_baseline(q32, x32, windows, budget_s: float):
                       f"z-normalisation ({dt:.1f} s on {threads} threads)"}
 
 
+def lb_cascade(eap, q, x, windows, K, steps, plain_rec):
+    """The same searches with the lower-bound cascade in front of the DTW
+    (reported beside the plain search, outside its timed steps): wall time per
+    window, the cascade's counters, and the answer check against the plain
+    search."""
+    import time as _t
+
+    import torch
+
+    out = {}
+    tot_ms = 0.0
+    for w in windows:
+        eap.nn_search_lb(q, x, w)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        for _ in range(steps):
+            (k, d), st = eap.nn_search_lb(q, x, w, stats=True)
+        torch.cuda.synchronize()
+        ms = (_t.perf_counter() - t0) * 1e3 / steps
+        tot_ms += ms
+        kp, dp = plain_rec[w][-1][0], plain_rec[w][-1][1]
+        out[str(w)] = {"offset": k, "dist": d, "same_as_plain": (k, d) == (kp, dp), "wall_ms": round(ms, 4),
+                       "gpu_ms": round(st["kernel_ms"], 4), "bounds_ms": round(st["lb_ms"], 4),
+                       "dtw_ms": round(st["main_kernel_ms"], 4),
+                       "pruned_kim": st["pruned_kim"], "pruned_keogh_eq": st["pruned_keogh_eq"],
+                       "pruned_recheck": st["pruned_recheck"], "dtw_candidates": st["dtw_candidates"],
+                       "cells_evaluated": st["cells_evaluated"]}
+    return {"candidates_per_s": K * len(windows) / (tot_ms / 1e3), "ms_per_step": round(tot_ms, 4),
+            "per_window": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +121,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of CPU oracle work for cpu_baseline (0 = skip)")
     ap.add_argument("--n", type=int, default=N_SERIES)
+    ap.add_argument("--lb-steps", type=int, default=5,
+                    help="repetitions of the lower-bound cascade searches reported beside "
+                         "the plain ones (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-mebibyte buffer once (a plain copy of known size "
                          "that calibrates HBM byte counters in a profiler run)")
@@ -182,6 +216,8 @@ def main():
                      "cells_per_launch": dw["cells_evaluated"],
                      "launch_ms": dw["main_kernel_ms"]},
     }
+    if args.lb_steps > 0:
+        line["lb_cascade"] = lb_cascade(eap, q, x, windows, K, args.lb_steps, rec)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(q32, x32, windows, args.cpu_budget)
     else:

@@ -128,6 +128,19 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *                      abandoned, over the whole band; 0 = wave-synchronous
  *                      row groups (default).  Same answers; the refill kernel
  *                      keeps more lanes busy but is slower on this hardware
+ *   "lb_ec"          : 1 = the cascade searches (eapdtw_nn_search_lb,
+ *                      eapdtw_nn_dists_lb) also apply LB_Keogh with the
+ *                      candidate's envelope; 0 = LB_Kim and LB_Keogh with the
+ *                      query's envelope only (default: a wave evaluates the third
+ *                      bound whenever one of its lanes passed the second, for
+ *                      few additional skips)
+ *   "lb_probe_div"   : the cascade search first runs bounds and DTW over the
+ *                      first K / lb_probe_div candidates, so that the bound pass
+ *                      over the rest compares with a tightened best-so-far
+ *                      (2..4096; 0 = one pass over all candidates, the default:
+ *                      the DTW pass re-checks each survivor's bounds against
+ *                      its own best-so-far anyway, and a second pair of
+ *                      launches costs more than the probe saves)
  * Returns EINVAL for an unknown key or value. */
 int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
 int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);
@@ -296,6 +309,8 @@ int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
  *              z-normalised with the candidate's mean and sigma (near the
  *              candidate's ends it covers values past them: a wider, still valid
  *              envelope).
+ * The third bound is applied with option "lb_ec" = 1 (it is always reported by
+ * eapdtw_nn_lower_bounds).
  * Bounds are computed in float32 and lowered by a relative 2^-18 before the
  * comparison (their sums round differently from the DP's).  A candidate that
  * passes all three gets the pruned, early-abandoned DTW, whose bound in row t

@@ -30,7 +30,8 @@ struct eapdtw_ctx {
   size_t scratch_cap = 0;
   char *pinned = nullptr;
   size_t pinned_cap = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  hipEvent_t ev_lb[4] = {nullptr, nullptr, nullptr, nullptr};  // cascade: pass boundaries
   // options
   int64_t check_interval = 0;  // 0: chosen per window
   int64_t seed = 1;
@@ -44,6 +45,10 @@ struct eapdtw_ctx {
   int64_t ed = 1;
   int64_t autotune = 0;
   int64_t lanes = 0;  // band search with lane refill where it applies
+  int64_t lb_ec = 0;         // cascade: apply the candidate-envelope LB_Keogh
+  int64_t lb_probe_div = 0;  // cascade: first pass over K / div candidates (0: one pass)
+  float lb_ms = 0.f, lb_dp_ms = 0.f;  // cascade timing of the last timed call
+  bool lb_probe_two = false;          // the last cascade ran a probe range first
   std::map<int64_t, eapdtw_tune> tune;  // autotuning cache, by (length, window) bucket
   int64_t seed_window = 8;
   int64_t batch_grid = 2048;
@@ -250,7 +255,8 @@ int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out) {
   c->stream = (hipStream_t)hip_stream;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess ||
-      hipEventCreate(&c->ev4) != hipSuccess) {
+      hipEventCreate(&c->ev_lb[0]) != hipSuccess || hipEventCreate(&c->ev_lb[1]) != hipSuccess ||
+      hipEventCreate(&c->ev_lb[2]) != hipSuccess || hipEventCreate(&c->ev_lb[3]) != hipSuccess) {
     g_create_error = "hipEventCreate failed";
     delete c;
     return EAPDTW_EDEVICE;
@@ -269,7 +275,8 @@ void eapdtw_destroy(eapdtw_ctx *ctx) {
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
-  if (ctx->ev4) (void)hipEventDestroy(ctx->ev4);
+  for (hipEvent_t e : ctx->ev_lb)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
   if (ctx->batch_buf) (void)hipFree(ctx->batch_buf);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -313,6 +320,8 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "ed")) return &ctx->ed;
   if (!strcmp(key, "autotune")) return &ctx->autotune;
   if (!strcmp(key, "lanes")) return &ctx->lanes;
+  if (!strcmp(key, "lb_ec")) return &ctx->lb_ec;
+  if (!strcmp(key, "lb_probe_div")) return &ctx->lb_probe_div;
   return nullptr;
 }
 
@@ -324,8 +333,9 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   if (!strcmp(key, "check_interval")) ok = value >= 0 && value <= (1 << 20);
   else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide") ||
            !strcmp(key, "border") || !strcmp(key, "ed") || !strcmp(key, "autotune") ||
-           !strcmp(key, "lanes"))
+           !strcmp(key, "lanes") || !strcmp(key, "lb_ec"))
     ok = value == 0 || value == 1;
+  else if (!strcmp(key, "lb_probe_div")) ok = value == 0 || (value >= 2 && value <= 4096);
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
   else if (!strcmp(key, "seed_stride")) ok = value >= 0 && value <= (1 << 20);
@@ -686,49 +696,69 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev2, st));
   if (lb && lb_applies(ctx, r)) {
-    // envelopes, the bound pass (survivor list), then the DP over the list
+    // envelopes, then per range of candidates the bound pass (survivor list)
+    // and the DP over the list.  A search first takes a probe range of
+    // K / lb_probe_div candidates: its DP brings the best-so-far near its
+    // final value before the bound pass over the remaining candidates, which
+    // compares with the best-so-far of its start.
     HIPCHK(launch_envelopes(series, n, qpad + kColPad, (int)m, (int)r, lb->ux, lb->lx, lb->uq,
                             lb->lq, st));
-    LBArgs la{};
-    la.x = series;
-    la.n = n;
-    la.m = (int)m;
-    la.r = (int)r;
-    la.qz = qpad + kColPad;
-    la.uq = lb->uq;
-    la.lq = lb->lq;
-    la.ux = lb->ux;
-    la.lx = lb->lx;
-    la.k_begin = 0;
-    la.k_end = K;
-    la.mode = dists ? 1 : 0;
-    la.bsf = bsf;
-    la.bsf_init = a.bsf_init;
-    la.fixed_ub = fixed_ub;
-    la.dists = dists;
-    la.counters = cnt;
-    la.list_k = lb->lk;
-    la.list_mh = lb->lmh;
-    la.list_ml = lb->lml;
-    la.list_inv = lb->linv;
-    la.list_lbq = lb->lbq;
-    la.list_lbmax = lb->lbmax;
-    HIPCHK(launch_lb_pass(la, st));
-    if (time_main) HIPCHK(hipEventRecord(ctx->ev4, st));
-    a.bsf = bsf;
-    a.counters = cnt;
-    a.fixed_ub = fixed_ub;
-    a.dists = dists;
-    a.list_n = cnt + kCntListN;
-    a.list_k = lb->lk;
-    a.list_mh = lb->lmh;
-    a.list_ml = lb->lml;
-    a.list_inv = lb->linv;
-    a.list_lbq = lb->lbq;
-    a.list_lbmax = lb->lbmax;
-    a.uq = lb->uq;
-    a.lq = lb->lq;
-    HIPCHK(nn_list_launcher((int)r)(a, nblk, dists != nullptr, ctx->border != 0, st));
+    int64_t cut = 0;
+    if (!dists && ctx->lb_probe_div > 0) {
+      cut = (K / ctx->lb_probe_div + kWave - 1) / kWave * kWave;
+      if (cut >= K) cut = 0;
+    }
+    const int64_t edges[3] = {0, cut ? cut : K, K};
+    const int nranges = cut ? 2 : 1;
+    ctx->lb_probe_two = cut != 0;
+    for (int pi = 0, e = 0; pi < nranges; ++pi) {
+      const int64_t lo = edges[pi], hi = edges[pi + 1];
+      LBArgs la{};
+      la.x = series;
+      la.n = n;
+      la.m = (int)m;
+      la.r = (int)r;
+      la.qz = qpad + kColPad;
+      la.uq = lb->uq;
+      la.lq = lb->lq;
+      la.ux = lb->ux;
+      la.lx = lb->lx;
+      la.k_begin = lo;
+      la.k_end = hi;
+      la.mode = dists ? 1 : 0;
+      la.bsf = bsf;
+      la.bsf_init = a.bsf_init;
+      la.fixed_ub = fixed_ub;
+      la.dists = dists;
+      la.use_ec = ctx->lb_ec != 0;
+      la.counters = cnt;
+      la.list_n = cnt + pi * kCntStride + kCntListN;
+      la.list_k = lb->lk + lo;
+      la.list_mh = lb->lmh + lo;
+      la.list_ml = lb->lml + lo;
+      la.list_inv = lb->linv + lo;
+      la.list_lbq = lb->lbq + lo;
+      la.list_lbmax = lb->lbmax + lo;
+      HIPCHK(launch_lb_pass(la, st));
+      if (time_main) HIPCHK(hipEventRecord(ctx->ev_lb[e++], st));
+      NNArgs b = a;
+      b.bsf = bsf;
+      b.counters = cnt;
+      b.fixed_ub = fixed_ub;
+      b.dists = dists;
+      b.list_n = la.list_n;
+      b.list_k = la.list_k;
+      b.list_mh = la.list_mh;
+      b.list_ml = la.list_ml;
+      b.list_inv = la.list_inv;
+      b.list_lbq = la.list_lbq;
+      b.list_lbmax = la.list_lbmax;
+      b.uq = lb->uq;
+      b.lq = lb->lq;
+      HIPCHK(nn_list_launcher((int)r)(b, (hi - lo + kWave - 1) / kWave, dists != nullptr,
+                                      ctx->border != 0, st));
+      if (time_main && pi + 1 < nranges) HIPCHK(hipEventRecord(ctx->ev_lb[e++], st));
+    }
   } else if (use_band(ctx, r)) {
     a.bsf = bsf;
     a.counters = cnt;
@@ -812,6 +842,17 @@ struct KnobGuard {
 
 }  // namespace
 
+// Splits a timed cascade call into bound passes and DP passes: events ev2,
+// ev_lb[0] (after the first bound pass), then with a probe range ev_lb[1]
+// (after its DP), ev_lb[2] (after the second bound pass), and ev3.
+static void lb_split_times(eapdtw_ctx *ctx) {
+  const float total = elapsed(ctx->ev2, ctx->ev3);
+  float lbt = elapsed(ctx->ev2, ctx->ev_lb[0]);
+  if (ctx->lb_probe_two) lbt += elapsed(ctx->ev_lb[1], ctx->ev_lb[2]);
+  ctx->lb_ms = lbt;
+  ctx->lb_dp_ms = total - lbt;
+}
+
 static void fill_lb_stats(eapdtw_lb_stats *ls, const unsigned long long *cnt, bool applied,
                           uint64_t K, float lb_ms) {
   if (!ls) return;
@@ -872,11 +913,11 @@ static int nn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const 
     return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
   *out_offset = best_offset(best) == 0xffffffffu ? -1 : (int64_t)best_offset(best);
   *out_dist = (double)best_dist(best);
+  if (lb_on && timed) lb_split_times(ctx);
   if (stats)
     fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
-               elapsed(ctx->ev0, ctx->ev1),
-               lb_on ? elapsed(ctx->ev4, ctx->ev3) : elapsed(ctx->ev2, ctx->ev3));
-  fill_lb_stats(lbstats, hc, lb_on, (uint64_t)K, lb_on ? elapsed(ctx->ev2, ctx->ev4) : 0.f);
+               elapsed(ctx->ev0, ctx->ev1), lb_on ? ctx->lb_dp_ms : elapsed(ctx->ev2, ctx->ev3));
+  fill_lb_stats(lbstats, hc, lb_on, (uint64_t)K, ctx->lb_ms);
   return EAPDTW_OK;
 }
 
@@ -934,10 +975,10 @@ static int nn_dists_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const f
     rc = readback(ctx, o_cnt, kCntBytes);
     if (rc) return rc;
     const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned);
+    if (lb_on) lb_split_times(ctx);
     fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
-               elapsed(ctx->ev0, ctx->ev1),
-               lb_on ? elapsed(ctx->ev4, ctx->ev3) : elapsed(ctx->ev2, ctx->ev3));
-    fill_lb_stats(lbstats, hc, lb_on, (uint64_t)K, lb_on ? elapsed(ctx->ev2, ctx->ev4) : 0.f);
+               elapsed(ctx->ev0, ctx->ev1), lb_on ? ctx->lb_dp_ms : elapsed(ctx->ev2, ctx->ev3));
+    fill_lb_stats(lbstats, hc, lb_on, (uint64_t)K, ctx->lb_ms);
   }
   return EAPDTW_OK;
 }

@@ -794,9 +794,10 @@ __global__ __launch_bounds__(64, (BORDER && R <= 52) ? 4 : 1) void nn_band_kerne
   nn_band_body<R, U, DISTS, BORDER>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
-// The candidates that passed the lower bounds (list mode of the same sweep).
+// The candidates that passed the lower bounds (list mode of the same sweep);
+// its per-lane bound tightening fits four waves per SIMD up to window 40.
 template <int R, int U, bool DISTS, bool BORDER>
-__global__ __launch_bounds__(64, (BORDER && R <= 48) ? 4 : 1) void nn_list_kernel(NNArgs a) {
+__global__ __launch_bounds__(64, (BORDER && R <= 40) ? 4 : 1) void nn_list_kernel(NNArgs a) {
   nn_band_body<R, U, DISTS, BORDER, true>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 

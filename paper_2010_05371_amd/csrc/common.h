@@ -32,7 +32,7 @@ enum Counter : int {
   kCntLbKim = 4,      // candidates skipped by LB_Kim
   kCntLbEq = 5,       // ... by LB_Keogh with the query's envelope
   kCntLbEc = 6,       // ... by LB_Keogh with the candidate's envelope
-  kCntListN = 7,      // length of the survivor list (stripe 0 only: one address)
+  kCntListN = 7,      // survivor list lengths (one word per pass, in stripes 0, 1, ...)
   kCntLbRecheck = 8,  // list entries dropped when the DP pass re-checks their bound
   kCntSlots = 9
 };
@@ -89,7 +89,8 @@ struct NNArgs {
   int block_stride;                  // workgroup b covers offsets from k_begin + 64 b stride
   int bound_only;                    // record distance-only bounds (offset field all ones)
   // List mode (candidates that passed the lower bounds): lane l of workgroup b
-  // takes list entry 64 b + l of list_n entries; the entry carries the offset,
+  // takes list entry 64 b + l of list_n entries (entries from the list
+  // arrays' start, which the caller offsets); the entry carries the offset,
   // the z-normalisation constants and the lower bounds of the candidate.
   const unsigned long long *list_n;
   const uint32_t *list_k;
@@ -118,7 +119,9 @@ struct LBArgs {
   float fixed_ub;                    // mode 1
   float *dists;                      // mode 1: +inf written for skipped candidates
   float *out_kim, *out_eq, *out_ec;  // mode 2: [k - k_begin]
-  unsigned long long *counters;      // kCntWords; kCntListN of stripe 0 counts the list
+  int use_ec;                        // modes 0, 1: apply the candidate-envelope bound
+  unsigned long long *counters;      // kCntWords
+  unsigned long long *list_n;        // modes 0, 1: entries appended so far (one word)
   uint32_t *list_k;                  // modes 0, 1: survivor list
   float *list_mh, *list_ml, *list_inv, *list_lbq, *list_lbmax;
 };

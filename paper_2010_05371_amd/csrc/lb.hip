@@ -9,9 +9,9 @@
 //    envelope, then LB_Keogh of z(query) against the candidate's envelope
 //    (the series envelope z-normalised with the candidate's mean and sigma:
 //    normalisation is increasing, so it maps the max / min of the raw values to
-//    those of the normalised ones).  Each bound, lowered by kLbMargin, is
-//    compared with the bound in force; candidates that pass all three go to a
-//    list (offset, normalisation constants, bounds) in the order of their
+//    those of the normalised ones; optional in a search).  Each bound, lowered
+//    by kLbMargin, is compared with the bound in force; candidates that pass go
+//    to a list (offset, normalisation constants, bounds) in the order of their
 //    waves' arrival, for the list mode of the band kernel.
 #include "band.h"
 #include "dispatch.h"
@@ -124,11 +124,12 @@ __global__ __launch_bounds__(64) void lb_pass_kernel(LBArgs a) {
 
   // One LDS-staged sweep over the candidate's m positions per bound: the
   // 64 + rows - 1 series values of the wave and the rows' per-position
-  // values (envelope or query) are copied once per stretch of kStageRows.
+  // values (envelope or query) are copied once per stretch of kStageRows;
+  // the per-position values are read four at a time (one ds_read_b128).
   __shared__ float s0[kWave + kStageRows - 1];
   __shared__ float s1[kWave + kStageRows - 1];
-  __shared__ float s2[kStageRows];
-  __shared__ float s3[kStageRows];
+  __shared__ __attribute__((aligned(16))) float s2[kStageRows];
+  __shared__ __attribute__((aligned(16))) float s3[kStageRows];
 
   // LB_Keogh of z(c) against the query envelope
   float eq = 0.0f;
@@ -142,10 +143,25 @@ __global__ __launch_bounds__(64) void lb_pass_kernel(LBArgs a) {
     __syncthreads();
     for (int i = 0; i < rows && run; i += kLbBlock) {
       const int nr = rows - i < kLbBlock ? rows - i : kLbBlock;
-      for (int t = 0; t < nr; ++t) {
-        const float z = znorm_value(s0[lane + i + t], mu_hi, mu_lo, inv);
-        const float d = z - __builtin_amdgcn_fmed3f(z, s3[i + t], s2[i + t]);
-        eq = __builtin_fmaf(d, d, eq);
+      if (nr == kLbBlock) {
+#pragma unroll
+        for (int t = 0; t < kLbBlock; t += 4) {
+          const float4 u4 = *reinterpret_cast<const float4 *>(&s2[i + t]);
+          const float4 l4 = *reinterpret_cast<const float4 *>(&s3[i + t]);
+          const float uv[4] = {u4.x, u4.y, u4.z, u4.w}, lv[4] = {l4.x, l4.y, l4.z, l4.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float z = znorm_value(s0[lane + i + t + j], mu_hi, mu_lo, inv);
+            const float d = z - __builtin_amdgcn_fmed3f(z, lv[j], uv[j]);
+            eq = __builtin_fmaf(d, d, eq);
+          }
+        }
+      } else {
+        for (int t = 0; t < nr; ++t) {
+          const float z = znorm_value(s0[lane + i + t], mu_hi, mu_lo, inv);
+          const float d = z - __builtin_amdgcn_fmed3f(z, s3[i + t], s2[i + t]);
+          eq = __builtin_fmaf(d, d, eq);
+        }
       }
       if (MODE != 2) {
         alive = alive && passes(eq);
@@ -155,9 +171,12 @@ __global__ __launch_bounds__(64) void lb_pass_kernel(LBArgs a) {
   }
   const bool after_eq = alive;
 
-  // LB_Keogh of z(query) against the candidate's envelope
+  // LB_Keogh of z(query) against the candidate's envelope (always for the
+  // bounds-only mode, on request otherwise: a wave runs it whenever one of
+  // its 64 lanes is still alive, which costs about as much as the first
+  // LB_Keogh for the few candidates it removes)
   float ec = 0.0f;
-  run = wave_any(MODE == 2 ? active : alive);
+  run = (MODE == 2 || a.use_ec) && wave_any(MODE == 2 ? active : alive);
   for (int base = 0; base < m && run; base += kStageRows) {
     const int rows = m - base < kStageRows ? m - base : kStageRows;
     __syncthreads();
@@ -194,7 +213,7 @@ __global__ __launch_bounds__(64) void lb_pass_kernel(LBArgs a) {
   const unsigned long long mask = __builtin_amdgcn_ballot_w64(alive);
   if (mask) {
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&a.counters[kCntListN], (unsigned long long)__popcll(mask));
+    if (lane == 0) base = atomicAdd(a.list_n, (unsigned long long)__popcll(mask));
     base = __shfl(base, 0, kWave);
     if (alive) {
       const unsigned pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

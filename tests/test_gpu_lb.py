@@ -64,8 +64,9 @@ DIST_CASES = [(64, 6, 3000), (101, 13, 3000), (128, 26, 3000), (250, 52, 3000), 
               (37, 40, 1200)]
 
 
+@pytest.mark.parametrize("ec", [0, 1])
 @pytest.mark.parametrize("m,w,n", DIST_CASES)
-def test_nn_dists_lb_threshold_contract(m, w, n):
+def test_nn_dists_lb_threshold_contract(m, w, n, ec):
     """Fixed-bound distances with the cascade: the oracle's value where it is
     at most ub, +inf above; wherever the plain kernel keeps a value that the
     cascade keeps too, the bits are the same (the tightened bound never cuts a
@@ -75,7 +76,7 @@ def test_nn_dists_lb_threshold_contract(m, w, n):
     want = oracle.nn_dists(gen.as_oracle(q32), gen.as_oracle(x32), w, np.arange(n - m + 1))
     for quant in (0.005, 0.05, 0.3, 1.0):
         ub = float(np.quantile(want, quant)) if quant < 1.0 else math.inf
-        (a, st) = eap.nn_dists_lb(q, x, w, ub=ub, stats=True)
+        (a, st) = _with({"lb_ec": ec}, lambda: eap.nn_dists_lb(q, x, w, ub=ub, stats=True))
         a = _cpu(a)
         b = _cpu(eap.nn_dists(q, x, w, ub=ub))
         assert_bounded(a, want, np.float64(np.float32(ub)), what=f"lb m={m} w={w} q={quant}")
@@ -95,11 +96,28 @@ SEARCH_CASES = [(128, 13, 20_000, 1), (128, 1, 8_000, 2), (96, 30, 12_000, 3), (
                 (77, 64, 9_000, 5), (200, 26, 25_000, 6)]
 
 
+def _with(opts, fn):
+    old = {k: eap.get_option(k) for k in opts}
+    for k, v in opts.items():
+        eap.set_option(k, v)
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            eap.set_option(k, v)
+
+
+# option sets: default (one pass, no candidate-envelope bound), all three
+# bounds, a probe range of K/16 first, a probe of half the offsets
+OPTS = [{}, {"lb_ec": 1}, {"lb_probe_div": 16}, {"lb_probe_div": 2, "lb_ec": 1}]
+
+
+@pytest.mark.parametrize("opts", OPTS, ids=["default", "ec", "probe16", "probe2_ec"])
 @pytest.mark.parametrize("m,w,n,seed", SEARCH_CASES)
-def test_nn_search_lb_equals_search_and_oracle(m, w, n, seed):
+def test_nn_search_lb_equals_search_and_oracle(m, w, n, seed, opts):
     q32, x32 = _series(m, n, 900 + seed)
     q, x = torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda()
-    (k, d), st = eap.nn_search_lb(q, x, w, stats=True)
+    (k, d), st = _with(opts, lambda: eap.nn_search_lb(q, x, w, stats=True))
     kp, dp = eap.nn_search(q, x, w)
     qo, xo = gen.as_oracle(q32), gen.as_oracle(x32)
     ko, do = oracle.nn_search(qo, xo, w)
@@ -111,6 +129,8 @@ def test_nn_search_lb_equals_search_and_oracle(m, w, n, seed):
         st["pruned_recheck"] + st["dtw_candidates"] == K
     assert 1 <= st["dtw_candidates"] < K
     assert st["problems"] == K and st["lb_ms"] > 0.0
+    if not opts.get("lb_ec"):
+        assert st["pruned_keogh_ec"] == 0
 
 
 def test_nn_search_lb_planted_and_c2_windows():
