@@ -24,7 +24,9 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
   of the DTW (LB_Kim, LB_Keogh with the query's and with the candidate's
   envelope);
 * ``nn_search_lb`` -- the search with that cascade (a sequential scan; it must
-  return the brute-force answer).
+  return the brute-force answer);
+* ``knn_search`` -- the k best offsets of the search (every distance, then a
+  lexicographic sort of (distance, offset)).
 """
 from __future__ import annotations
 
@@ -93,6 +95,8 @@ def _load():
     lib.oracle_nn_lower_bounds.restype = ctypes.c_int
     lib.oracle_nn_search_lb.argtypes = [dp, i64, dp, i64, i64, ip, dp, ip]
     lib.oracle_nn_search_lb.restype = ctypes.c_int
+    lib.oracle_knn_search.argtypes = [dp, i64, dp, i64, i64, i64, ctypes.c_int, ip, dp, ip]
+    lib.oracle_knn_search.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -270,3 +274,18 @@ def nn_search_lb(query, series, window: int):
     if rc != 0:
         raise ValueError(f"oracle_nn_search_lb failed ({rc})")
     return int(bk[0]), float(bd[0]), tuple(int(c) for c in counts)
+
+
+def knn_search(query, series, window: int, k: int, nthreads: int | None = None):
+    """The k smallest (offset, distance) pairs of the search, ordered by
+    (distance, offset); all offsets when there are fewer than k."""
+    q, x = _f64(query), _f64(series)
+    ok = np.empty(max(k, 1), dtype=np.int64)
+    od = np.empty(max(k, 1))
+    cnt = np.empty(1, dtype=np.int64)
+    rc = _load().oracle_knn_search(_ptr(q), q.size, _ptr(x), x.size, int(window), int(k),
+                                   nthreads or default_threads(), _ptr(ok), _ptr(od), _ptr(cnt))
+    if rc != 0:
+        raise ValueError(f"oracle_knn_search failed ({rc})")
+    c = int(cnt[0])
+    return [(int(ok[t]), float(od[t])) for t in range(c)]

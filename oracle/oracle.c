@@ -620,3 +620,47 @@ done:
   free(kim); free(eq); free(ec); free(zq); free(zc); free(offs); free(w.M);
   return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* k nearest neighbours of the search (the k-NN use named with NN1 in        */
+/* Section 2.2): the k smallest (d_k, k) pairs in lexicographic order, i.e.  */
+/* the k best offsets with ties going to the smaller offset, over every       */
+/* offset (no exclusion of overlapping offsets).  Plain definition: every     */
+/* distance, then a sort.  Fewer than k offsets: all of them.                 */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double d;
+  int64_t k;
+} knn_item;
+
+static int knn_cmp(const void *a, const void *b) {
+  const knn_item *x = (const knn_item *)a, *y = (const knn_item *)b;
+  if (x->d < y->d) return -1;
+  if (x->d > y->d) return 1;
+  return (x->k > y->k) - (x->k < y->k);
+}
+
+int oracle_knn_search(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                      int64_t kk, int nthreads, int64_t *out_k, double *out_d, int64_t *out_cnt) {
+  if (m <= 0 || n < m || kk < 1) return -2;
+  const int64_t K = n - m + 1;
+  int64_t *offs = malloc((size_t)K * sizeof(int64_t));
+  double *d = malloc((size_t)K * sizeof(double));
+  knn_item *it = malloc((size_t)K * sizeof(knn_item));
+  int rc = -1;
+  if (!offs || !d || !it) goto done;
+  for (int64_t t = 0; t < K; ++t) offs[t] = t;
+  if ((rc = oracle_nn_dists(q, m, x, n, r, offs, K, nthreads, d)) != 0) goto done;
+  for (int64_t t = 0; t < K; ++t) it[t] = (knn_item){d[t], t};
+  qsort(it, (size_t)K, sizeof(knn_item), knn_cmp);
+  const int64_t c = kk < K ? kk : K;
+  for (int64_t t = 0; t < c; ++t) {
+    out_k[t] = it[t].k;
+    out_d[t] = it[t].d;
+  }
+  *out_cnt = c;
+  rc = 0;
+done:
+  free(offs); free(d); free(it);
+  return rc;
+}
