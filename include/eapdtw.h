@@ -360,6 +360,25 @@ int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const
                            int64_t n, int64_t window, float *out_kim, float *out_eq,
                            float *out_ec);
 
+/* ---------------------------------------------------------------------------
+ * k nearest neighbours of the search (Section 2.2 names NN search and NN1
+ * classification; k > 1 keeps an upper bound of the k-th best distance as
+ * the early-abandoning bound).  The k smallest (distance, offset) pairs in
+ * lexicographic order over every offset k in [0, n-m] (overlapping offsets are
+ * not excluded), under eapdtw_nn_search's normalisation and window.
+ *   k           : 1..64.
+ *   out_offsets : HOST [k], ascending by (distance, offset); -1 past the
+ *                 n-m+1 available offsets.
+ *   out_dists   : HOST [k], the distances (float32 values widened); +inf past
+ *                 the available offsets.
+ * Each wave appends its kept candidates to a device buffer and, when it kept
+ * at least k, min-s its k-th smallest distance into the bound; a filter and a
+ * one-workgroup LDS sort then select the k best.  Band windows only (window
+ * after clamping to m-1 at most 64): EINVAL otherwise.  Synchronous. */
+int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                      int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
+                      double *out_dists, eapdtw_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,7 @@ __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_d
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
-           "nn_lower_bounds", "LbStats"]
+           "nn_lower_bounds", "LbStats", "knn_search"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -260,6 +260,24 @@ def nn_dists_lb(query, series, window: int, ub: float = math.inf, stats: bool = 
                                           ctypes.byref(st) if stats else None,
                                           ctypes.byref(ls) if stats else None))
     return (out, {**st.as_dict(), **ls.as_dict()}) if stats else out
+
+
+def knn_search(query, series, window: int, k: int, stats: bool = False):
+    """The k nearest candidate offsets: a list of (offset, distance) in
+    (distance, offset) order (offset -1 / distance inf past the available
+    offsets)."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    kk = int(k)
+    offs = (ctypes.c_int64 * max(kk, 1))()
+    dists = (ctypes.c_double * max(kk, 1))()
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_knn_search(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                         int(window), kk, offs, dists,
+                                         ctypes.byref(st) if stats else None))
+    res = [(offs[i], dists[i]) for i in range(kk)]
+    return (res, st.as_dict()) if stats else res
 
 
 def nn_lower_bounds(query, series, window: int):

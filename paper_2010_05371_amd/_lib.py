@@ -105,6 +105,8 @@ def load():
                                  ctypes.POINTER(f64), sp, lp], i32),
         "eapdtw_nn_dists_lb": ([vp, vp, i64, vp, i64, i64, f32, vp, sp, lp], i32),
         "eapdtw_nn_lower_bounds": ([vp, vp, i64, vp, i64, i64, vp, vp, vp], i32),
+        "eapdtw_knn_search": ([vp, vp, i64, vp, i64, i64, i64, ctypes.POINTER(i64),
+                               ctypes.POINTER(f64), sp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

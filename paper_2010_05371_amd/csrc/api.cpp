@@ -622,6 +622,13 @@ static LbBufs lb_bind(eapdtw_ctx *ctx, const size_t *offs) {
                 at<float>(ctx, offs[9])};
 }
 
+// Device buffers of the k-nearest-neighbour search: the kept candidates and
+// their count (a counter word, cleared by the set-up kernel).
+struct KnnBufs {
+  int k;
+  unsigned long long *buf, *n;
+};
+
 // The cascade serves band windows from 1 on (at window 0 LB_Keogh is the
 // squared Euclidean distance itself, which the window-0 kernel computes).
 static bool lb_applies(const eapdtw_ctx *ctx, int64_t r) { return r >= 1 && use_band(ctx, r); }
@@ -629,7 +636,8 @@ static bool lb_applies(const eapdtw_ctx *ctx, int64_t r) { return r >= 1 && use_
 static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                         int64_t n, int64_t r, float *qpad, unsigned long long *bsf,
                         unsigned long long *cnt, float *dists, float fixed_ub, float *bnd,
-                        int64_t bnd_waves, bool time_main, const LbBufs *lb = nullptr) {
+                        int64_t bnd_waves, bool time_main, const LbBufs *lb = nullptr,
+                        const KnnBufs *kb = nullptr) {
   hipStream_t st = ctx->stream;
   const int64_t K = n - m + 1;
   const int64_t nblk = (K + kWave - 1) / kWave;
@@ -673,6 +681,14 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     s.center = bsf + 1;
     s.bsf_init = bsf + 1;
     s.bound_only = 1;
+    if (kb) {
+      // k nearest neighbours: the window-0 pass only locates the seeding
+      // workgroup (its minimum bounds the best, not the k-th best); the
+      // workgroup publishes the k-th best of its 64 distances and appends
+      // nothing (its distances are under a narrower window)
+      s.bsf_init = nullptr;
+      s.knn = kb->k;
+    }
     hipStream_t ss = st;
     if (use_band(ctx, r)) {
       if (!ctx->seed_stream) {
@@ -683,9 +699,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       HIPCHK(hipEventRecord(ctx->ev_fork, st));
       HIPCHK(hipStreamWaitEvent(ctx->seed_stream, ctx->ev_fork, 0));
       ss = ctx->seed_stream;
-      a.bsf_init = bsf + 1;  // the search's waves start from the window-0 bound
+      if (!kb) a.bsf_init = bsf + 1;  // the search's waves start from the window-0 bound
     }
-    if (rs == 0 && ctx->ed)
+    if (rs == 0 && ctx->ed && !kb)  // (the window-0 kernel publishes only the best)
       HIPCHK(launch_ed_search(s, 1, false, ss));
     else
       HIPCHK(nn_band_launcher((int)rs)(s, 1, pick_rows(ctx, (int)rs), false, false, ss));
@@ -764,7 +780,12 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     a.counters = cnt;
     a.fixed_ub = fixed_ub;
     a.dists = dists;
-    if (r == 0 && ctx->ed)
+    if (kb) {
+      a.knn = kb->k;
+      a.knn_buf = kb->buf;
+      a.knn_n = kb->n;
+      HIPCHK(nn_band_launcher((int)r)(a, nblk, 4, false, ctx->border != 0, st));
+    } else if (r == 0 && ctx->ed)
       HIPCHK(launch_ed_search(a, nblk, dists != nullptr, st));
     else if (!dists && ctx->lanes && lane_search_supported((int)r, (int)m))
       HIPCHK(launch_lane_search((int)r, a, st));
@@ -1043,6 +1064,63 @@ int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const
   if (*reinterpret_cast<const unsigned *>(reinterpret_cast<unsigned long long *>(ctx->pinned) +
                                           kCntWords) == ctx->epoch)
     return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
+  return EAPDTW_OK;
+}
+
+int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                      int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
+                      double *out_dists, eapdtw_stats *stats) {
+  CHECK_CTX();
+  KnobGuard knobs(ctx);
+  knobs.apply_cached(m, window);
+  if (!out_offsets || !out_dists) return fail(ctx, EAPDTW_EINVAL, "NULL output");
+  if (k < 1 || k > kKnnMax) return fail(ctx, EAPDTW_EINVAL, "k must be in 1..64");
+  int rc = search_validate(ctx, query, m, series, n, window);
+  if (rc) return rc;
+  const int64_t r = window < m - 1 ? window : m - 1;
+  if (!use_band(ctx, r)) return fail(ctx, EAPDTW_EINVAL, "k nearest neighbours: window above 64");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  const int64_t K = n - m + 1;
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
+  const size_t o_res = pl.add(sizeof(unsigned long long) * kKnnMax);
+  const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  const size_t o_buf = pl.add(sizeof(unsigned long long) * K);
+  const size_t o_tmp = pl.add(sizeof(unsigned long long) * K);
+  rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  unsigned long long *bsf = at<unsigned long long>(ctx, o_bsf);
+  // the kept-candidate count and the filtered count live in counter words
+  // (stripe 0 and 1, slot kCntListN), cleared by the set-up kernel
+  const KnnBufs kb{(int)k, at<unsigned long long>(ctx, o_buf), cnt + kCntListN};
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
+                    nullptr, 0, stats != nullptr, nullptr, &kb);
+  if (rc) return rc;
+  HIPCHK(launch_knn_select(kb.buf, kb.n, bsf, at<unsigned long long>(ctx, o_tmp),
+                           cnt + kCntStride + kCntListN, (int)k,
+                           at<unsigned long long>(ctx, o_res), st));
+  if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
+  // counters, the best-so-far words and the results are contiguous
+  rc = readback(ctx, o_cnt, o_res + sizeof(unsigned long long) * kKnnMax - o_cnt);
+  if (rc) return rc;
+  const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned);
+  if (*reinterpret_cast<const unsigned *>(hc + kCntWords) == ctx->epoch)
+    return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
+  const unsigned long long *res =
+      reinterpret_cast<const unsigned long long *>(ctx->pinned + (o_res - o_cnt));
+  for (int64_t i = 0; i < k; ++i) {
+    const bool have = i < K && res[i] != ~0ull;
+    out_offsets[i] = have ? (int64_t)best_offset(res[i]) : -1;
+    out_dists[i] = have ? (double)best_dist(res[i]) : INFINITY;
+  }
+  if (stats)
+    fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
   return EAPDTW_OK;
 }
 

@@ -516,6 +516,50 @@ __device__ __forceinline__ void publish_best(unsigned long long *bsf, bool keep,
   if (threadIdx.x % kWave == 0 && v != ~0ull) atomicMin(bsf, v);
 }
 
+// Ascending bitonic sort of one u64 per lane across the wave (lane l ends
+// with the l-th smallest).
+__device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long v) {
+  const int lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride >= 1; stride >>= 1) {
+      const unsigned long long o = __shfl_xor(v, stride, kWave);
+      const bool up = (lane & size) == 0;           // this block sorts ascending
+      const bool low = (lane & stride) == 0;        // this lane holds the lower slot
+      const unsigned long long lo = o < v ? o : v, hi = o < v ? v : o;
+      v = (up == low) ? lo : hi;
+    }
+  }
+  return v;
+}
+
+// k-nearest-neighbour publication of a wave: its kept candidates go to the
+// buffer, and when it kept at least k of them, its k-th smallest distance --
+// the k-th best of k actual candidates, so an upper bound of the search's
+// k-th best -- is min-ed into the bound word.
+__device__ __forceinline__ void publish_knn(const NNArgs &a, bool keep, float d, uint32_t id) {
+  const int lane = threadIdx.x % kWave;
+  const unsigned long long mask = __builtin_amdgcn_ballot_w64(keep);
+  if (!mask) return;
+  const unsigned long long v = keep ? pack_best(d, id) : ~0ull;
+  if (a.knn_buf) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.knn_n, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0, kWave);
+    if (keep) {
+      const unsigned r = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      a.knn_buf[base + r] = v;
+    }
+  }
+  if (__popcll(mask) >= a.knn) {
+    const unsigned long long s = wave_sort_u64(v);
+    const unsigned long long kth = __shfl(s, a.knn - 1, kWave);
+    if (lane == 0) atomicMin(a.bsf, pack_best(best_dist(kth), 0xffffffffu));
+  }
+}
+
 __device__ __forceinline__ float load_bsf_dist(const unsigned long long *bsf) {
   unsigned long long b = __hip_atomic_load(bsf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return best_dist(b);
@@ -772,6 +816,8 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   const bool keep = alive && !stopped && d <= ub;
   if (DISTS) {
     if (active) a.dists[k - a.k_begin] = keep ? d : kInf;
+  } else if (!LIST && a.knn > 0) {
+    publish_knn(a, keep, d, (uint32_t)k);
   } else {
     publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }

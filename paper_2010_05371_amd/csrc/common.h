@@ -98,7 +98,16 @@ struct NNArgs {
   const float *list_lbq;             // LB_Keogh with the query's envelope (full sum)
   const float *list_lbmax;           // largest of the three bounds
   const float *uq, *lq;              // envelope of z(query) [m]: tightening of the bound per row
+  // k nearest neighbours (knn > 0): bsf holds an upper bound of the k-th best
+  // distance (offset field all ones); kept candidates are appended to knn_buf
+  // (when given) as packed (distance, offset) words, knn_n counting them.
+  int knn;
+  unsigned long long *knn_buf;
+  unsigned long long *knn_n;
 };
+
+// Largest k of the k-nearest-neighbour search (one wave sorts 64 candidates).
+constexpr int kKnnMax = 64;
 
 // Relative margin by which float32 lower bounds are lowered before they are
 // compared with a distance: their sums round differently from the DP's.

@@ -34,6 +34,14 @@ hipError_t launch_envelopes(const float *x, int64_t n, const float *qz, int m, i
                             float *lx, float *uq, float *lq, hipStream_t st);
 hipError_t launch_lb_pass(const LBArgs &a, hipStream_t st);
 
+// k nearest neighbours (knn.hip): from the n_buf words of buf, the k <= kKnnMax
+// smallest at or below *bound's distance, ascending, into out[k] (all-ones
+// words past the available ones); tmp holds as many words as buf, *n_tmp = 0.
+hipError_t launch_knn_select(const unsigned long long *buf, const unsigned long long *n_buf,
+                             const unsigned long long *bound, unsigned long long *tmp,
+                             unsigned long long *n_tmp, int k, unsigned long long *out,
+                             hipStream_t st);
+
 // Wide-window kernels (wide_inst.hip): kind is a WideKind, rows the tile height
 // (16, 32 or 64), grid the number of persistent single-wave workgroups.
 struct WideArgs;

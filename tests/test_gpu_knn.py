@@ -1,0 +1,92 @@
+"""GPU parity of the k-nearest-neighbour search against the FP64 oracle's
+plain definition (every distance, then a lexicographic sort)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2010_05371_amd as eap
+from parity import close
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(res, q32, x32, w, k):
+    qo, xo = gen.as_oracle(q32), gen.as_oracle(x32)
+    want = oracle.knn_search(qo, xo, w, k)
+    K = x32.size - q32.size + 1
+    assert len(res) == k
+    got = [(o, d) for o, d in res if o >= 0]
+    assert len(got) == min(k, K)
+    assert all(o == -1 and math.isinf(d) for o, d in res[len(got):])
+    offs = [o for o, _ in got]
+    assert len(set(offs)) == len(offs)
+    # ascending (distance, offset) order
+    assert all((got[i][1], got[i][0]) < (got[i + 1][1], got[i + 1][0]) for i in range(len(got) - 1))
+    at = oracle.nn_dists(qo, xo, w, offs)
+    for i, ((o, d), (wo, wd)) in enumerate(zip(got, want)):
+        assert close(d, at[i]), (i, o, d, at[i])  # the reported distance is the offset's
+        assert close(d, wd), (i, d, wd)             # the i-th best, to the tolerance
+        if o != wo:  # a near-tie swapped places
+            assert abs(at[i] - wd) <= 1e-5 * wd + 1e-6, (i, o, wo, at[i], wd)
+
+
+# (m, window, n, k): window 0, narrow and bordered windows, k = 1 and 64,
+# ragged row groups
+CASES = [(64, 0, 3000, 5), (128, 13, 20_000, 10), (96, 30, 8000, 64), (37, 6, 5000, 1),
+         (200, 52, 12_000, 16), (150, 64, 6000, 33)]
+
+
+@pytest.mark.parametrize("m,w,n,k", CASES)
+def test_knn_vs_oracle(m, w, n, k):
+    g = gen.rng(4400, m * 100 + w)
+    q32, x32 = gen.as_f32(gen.random_walk(m, g)), gen.as_f32(gen.random_walk(n, g))
+    res, st = eap.knn_search(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), w, k,
+                             stats=True)
+    _check(res, q32, x32, w, k)
+    assert st["problems"] == n - m + 1
+
+
+def test_knn_one_is_nn_search():
+    q32, x32, _ = gen.c2(n=80_000)
+    q, x = torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda()
+    for w in (0, 13, 26):
+        (res,) = eap.knn_search(q, x, w, 1)
+        assert res == eap.nn_search(q, x, w)
+
+
+def test_knn_periodic_ties_and_planted():
+    """Exactly repeated windows tie bit for bit: the smaller offsets come first.
+    Planted copies come before everything else."""
+    pattern = gen.random_walk(40, gen.rng(4401))
+    x32 = gen.as_f32(np.tile(pattern, 50))
+    q32 = gen.as_f32(np.asarray(x32[7:7 + 32], dtype=np.float64) + 0.01 * gen.rng(4402).standard_normal(32))
+    res = eap.knn_search(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), 4, 8)
+    assert [o for o, _ in res] == [7 + 40 * j for j in range(8)]
+    assert len({d for _, d in res}) == 1
+    _check(res, q32, x32, 4, 8)
+    g = gen.rng(4403)
+    q = gen.random_walk(64, g)
+    x = gen.random_walk(30_000, g)
+    x32 = gen.plant(gen.plant(x, q, 12_000, a=3.0, b=1.0), q, 25_000, a=0.5, b=-2.0)
+    q32 = gen.as_f32(q)
+    res = eap.knn_search(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), 6, 5)
+    assert [o for o, _ in res[:2]] == [12_000, 25_000] and res[1][1] <= 1e-5
+    _check(res, q32, x32, 6, 5)
+
+
+def test_knn_fewer_offsets_than_k_and_errors():
+    g = gen.rng(4404)
+    q32, x32 = gen.as_f32(gen.random_walk(10, g)), gen.as_f32(gen.random_walk(14, g))
+    res = eap.knn_search(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), 2, 8)
+    _check(res, q32, x32, 2, 8)
+    q32, x32 = gen.as_f32(gen.random_walk(300, g)), gen.as_f32(gen.random_walk(2000, g))
+    q, x = torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda()
+    for bad_k in (0, 65):
+        with pytest.raises(eap.EapdtwError):
+            eap.knn_search(q, x, 10, bad_k)
+    with pytest.raises(eap.EapdtwError):  # window above 64
+        eap.knn_search(q, x, 100, 4)
