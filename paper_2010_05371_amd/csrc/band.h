@@ -534,10 +534,18 @@ __device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long v
   return v;
 }
 
-// k-nearest-neighbour publication of a wave: its kept candidates go to the
-// buffer, and when it kept at least k of them, its k-th smallest distance --
-// the k-th best of k actual candidates, so an upper bound of the search's
-// k-th best -- is min-ed into the bound word.
+// k-nearest-neighbour publication of a wave.  Its kept candidates go to the
+// buffer.  Two upper bounds of the search's k-th best distance are min-ed
+// into the bound word:
+//  * when the wave kept at least k candidates, its k-th smallest distance
+//    (the k-th best of k actual candidates);
+//  * k slots (with counters): candidate `id` lowers slot id mod k to its
+//    distance, so the k slots hold distances of k distinct candidates once
+//    all are filled, and their largest bounds the k-th best.  Neighbouring
+//    offsets of a good match fill different slots, so this bound follows the
+//    search's progress rather than waiting for one wave with k survivors.
+//    Slots store 2^32 - 1 - (distance bits), 0 meaning empty, and take
+//    atomicMax.
 __device__ __forceinline__ void publish_knn(const NNArgs &a, bool keep, float d, uint32_t id) {
   const int lane = threadIdx.x % kWave;
   const unsigned long long mask = __builtin_amdgcn_ballot_w64(keep);
@@ -557,6 +565,24 @@ __device__ __forceinline__ void publish_knn(const NNArgs &a, bool keep, float d,
     const unsigned long long s = wave_sort_u64(v);
     const unsigned long long kth = __shfl(s, a.knn - 1, kWave);
     if (lane == 0) atomicMin(a.bsf, pack_best(best_dist(kth), 0xffffffffu));
+  }
+  if (a.counters) {
+    unsigned long long *slots = a.counters + kCntKnnSlot;
+    if (keep)
+      atomicMax(&slots[(id % (uint32_t)a.knn) * kCntStride],
+                (unsigned long long)(0xffffffffu - __builtin_bit_cast(uint32_t, d)));
+    unsigned long long sv = 1;  // lanes past k: no constraint
+    if (lane < a.knn)
+      sv = __hip_atomic_load(&slots[lane * kCntStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!wave_any(sv == 0)) {
+      uint32_t bits = lane < a.knn ? 0xffffffffu - (uint32_t)sv : 0u;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t t = __shfl_xor(bits, o, kWave);
+        bits = t > bits ? t : bits;
+      }
+      if (lane == 0) atomicMin(a.bsf, pack_best(__builtin_bit_cast(float, bits), 0xffffffffu));
+    }
   }
 }
 

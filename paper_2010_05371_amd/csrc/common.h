@@ -34,7 +34,10 @@ enum Counter : int {
   kCntLbEc = 6,       // ... by LB_Keogh with the candidate's envelope
   kCntListN = 7,      // survivor list lengths (one word per pass, in stripes 0, 1, ...)
   kCntLbRecheck = 8,  // list entries dropped when the DP pass re-checks their bound
-  kCntSlots = 9
+  kCntSlots = 9,
+  // not a counter: word j of the k-nearest-neighbour slots sits at slot
+  // kCntKnnSlot of stripe j (own 128-byte line each; cleared with the counters)
+  kCntKnnSlot = 15
 };
 constexpr int kCntStripes = 64;
 constexpr int kCntStride = 16;
