@@ -26,7 +26,9 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
 * ``nn_search_lb`` -- the search with that cascade (a sequential scan; it must
   return the brute-force answer);
 * ``knn_search`` -- the k best offsets of the search (every distance, then a
-  lexicographic sort of (distance, offset)).
+  lexicographic sort of (distance, offset));
+* ``nn1`` -- leave-one-out nearest neighbour of every series of a set (every
+  pair, then row minima).
 """
 from __future__ import annotations
 
@@ -97,6 +99,8 @@ def _load():
     lib.oracle_nn_search_lb.restype = ctypes.c_int
     lib.oracle_knn_search.argtypes = [dp, i64, dp, i64, i64, i64, ctypes.c_int, ip, dp, ip]
     lib.oracle_knn_search.restype = ctypes.c_int
+    lib.oracle_nn1.argtypes = [dp, i64, i64, i64, ctypes.c_int, ip, dp]
+    lib.oracle_nn1.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -289,3 +293,17 @@ def knn_search(query, series, window: int, k: int, nthreads: int | None = None):
         raise ValueError(f"oracle_knn_search failed ({rc})")
     c = int(cnt[0])
     return [(int(ok[t]), float(od[t])) for t in range(c)]
+
+
+def nn1(X, window: int, nthreads: int | None = None):
+    """(index, distance) arrays: for each row i of X [N][L], the row j != i with
+    the smallest DTW (smaller j on ties)."""
+    X = _f64(X)
+    N, L = X.shape
+    oj = np.empty(N, dtype=np.int64)
+    od = np.empty(N)
+    rc = _load().oracle_nn1(_ptr(X), N, L, int(window), nthreads or default_threads(), _ptr(oj),
+                            _ptr(od))
+    if rc != 0:
+        raise ValueError(f"oracle_nn1 failed ({rc})")
+    return oj, od

@@ -664,3 +664,48 @@ done:
   free(offs); free(d); free(it);
   return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Leave-one-out nearest neighbour over one set of series (the NN1            */
+/* classification use of Section 2.2): for each series i, the series j != i  */
+/* with the smallest DTW under window r, the smaller index among equal        */
+/* distances.  Plain definition: every pair i < j through oracle_dtw_pairs,   */
+/* then the minimum of each row and column.  N >= 2.                          */
+/* ------------------------------------------------------------------------- */
+int oracle_nn1(const double *X, int64_t N, int64_t L, int64_t r, int nthreads, int64_t *out_j,
+               double *out_d) {
+  if (N < 2 || L < 1) return -2;
+  const int64_t P = N * (N - 1) / 2;
+  int64_t *ia = malloc((size_t)P * sizeof(int64_t)), *ib = malloc((size_t)P * sizeof(int64_t));
+  double *D = malloc((size_t)P * sizeof(double));
+  int rc = -1;
+  if (!ia || !ib || !D) goto done;
+  int64_t p = 0;
+  for (int64_t i = 0; i < N; ++i)
+    for (int64_t j = i + 1; j < N; ++j) {
+      ia[p] = i;
+      ib[p] = j;
+      ++p;
+    }
+  if ((rc = oracle_dtw_pairs(X, X, L, r, ia, ib, P, nthreads, D)) != 0) goto done;
+  for (int64_t i = 0; i < N; ++i) {
+    out_j[i] = -1;
+    out_d[i] = INFINITY;
+  }
+  for (p = 0; p < P; ++p) {
+    const int64_t i = ia[p], j = ib[p];
+    /* j > i: for row i, j is visited in increasing order; for row j, i too */
+    if (out_j[i] < 0 || D[p] < out_d[i] || (D[p] == out_d[i] && j < out_j[i])) {
+      out_d[i] = D[p];
+      out_j[i] = j;
+    }
+    if (out_j[j] < 0 || D[p] < out_d[j] || (D[p] == out_d[j] && i < out_j[j])) {
+      out_d[j] = D[p];
+      out_j[j] = i;
+    }
+  }
+  rc = 0;
+done:
+  free(ia); free(ib); free(D);
+  return rc;
+}

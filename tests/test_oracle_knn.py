@@ -61,3 +61,33 @@ def test_knn_more_than_offsets():
     q, x = gen.random_walk(10, g), gen.random_walk(14, g)
     res = oracle.knn_search(q, x, 2, 20)
     assert len(res) == 5 and res == _brute(q, x, 2, 20)
+
+
+def _nn1_brute(X, w):
+    N = X.shape[0]
+    out = []
+    for i in range(N):
+        best = None
+        for j in range(N):
+            if j != i:
+                d = oracle.dtw(X[i], X[j], w)
+                if best is None or d < best[1]:
+                    best = (j, d)
+        out.append(best)
+    return out
+
+
+@pytest.mark.parametrize("w", [0, 3, 20])
+def test_nn1_brute_force(w):
+    X = gen.rng(605, w).standard_normal((30, 20))
+    X[17] = X[4]  # an exact duplicate: each is the other's neighbour at 0
+    X[25] = X[4]  # three copies: ties go to the smaller index
+    oj, od = oracle.nn1(X, w)
+    assert [(int(j), float(d)) for j, d in zip(oj, od)] == _nn1_brute(X, w)
+    assert oj[4] == 17 and oj[17] == 4 and oj[25] == 4 and od[4] == 0.0
+
+
+def test_nn1_two_series():
+    X = gen.rng(606).standard_normal((2, 9))
+    oj, od = oracle.nn1(X, 2)
+    assert oj.tolist() == [1, 0] and od[0] == od[1] == oracle.dtw(X[0], X[1], 2)
