@@ -379,6 +379,20 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
                       int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
                       double *out_dists, eapdtw_stats *stats);
 
+/* ---------------------------------------------------------------------------
+ * Leave-one-out nearest neighbour of every series of a set (the NN1
+ * classification use of Section 2.2): for each series i, the series j != i with
+ * the smallest DTW under the window, the smaller j among equal distances.
+ * Every unordered pair is computed once, early-abandoned above the larger of
+ * its two series' best distances so far (and pruned with the squared
+ * Euclidean distance as in eapdtw_pairwise); a kept distance lowers both
+ * series' best.
+ *   X [N][len]  : DEVICE float32 row-major, used as given (not normalised).
+ *   out_index   : HOST [N] int64, out_dist : HOST [N] (float32 values widened).
+ * N < 2 or len < 1: EINVAL.  Synchronous. */
+int eapdtw_nn1(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t window,
+               int64_t *out_index, double *out_dist, eapdtw_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

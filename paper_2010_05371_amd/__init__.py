@@ -35,7 +35,7 @@ __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_d
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
-           "nn_lower_bounds", "LbStats", "knn_search"]
+           "nn_lower_bounds", "LbStats", "knn_search", "nn1"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -278,6 +278,26 @@ def knn_search(query, series, window: int, k: int, stats: bool = False):
                                          ctypes.byref(st) if stats else None))
     res = [(offs[i], dists[i]) for i in range(kk)]
     return (res, st.as_dict()) if stats else res
+
+
+def nn1(X, window: int, stats: bool = False):
+    """Leave-one-out nearest neighbour of every row of X [N][len]: (index,
+    distance) numpy arrays, the smaller index among equal distances."""
+    import numpy as np
+
+    X = _dev(X)
+    assert X.dim() == 2, "X must be [N][len]"
+    N, L = X.shape
+    ctx = context(X.device.index)
+    ctx.bind_stream()
+    idx = np.empty(N, dtype=np.int64)
+    dist = np.empty(N, dtype=np.float64)
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn1(ctx.handle, _ptr(X), N, L, int(window),
+                                  idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  dist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(st) if stats else None))
+    return ((idx, dist), st.as_dict()) if stats else (idx, dist)
 
 
 def nn_lower_bounds(query, series, window: int):

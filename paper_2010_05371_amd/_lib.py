@@ -107,6 +107,7 @@ def load():
         "eapdtw_nn_lower_bounds": ([vp, vp, i64, vp, i64, i64, vp, vp, vp], i32),
         "eapdtw_knn_search": ([vp, vp, i64, vp, i64, i64, i64, ctypes.POINTER(i64),
                                ctypes.POINTER(f64), sp], i32),
+        "eapdtw_nn1": ([vp, vp, i64, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(f64), sp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -47,6 +47,9 @@ hipError_t launch_knn_select(const unsigned long long *buf, const unsigned long 
 struct WideArgs;
 hipError_t launch_wide(int kind, int rows, const WideArgs &a, int grid, hipStream_t st);
 int wide_rows_for(int r, int lrow, int lcol);
+// NN1 seeding: every pair's squared Euclidean distance min-ed into both series'
+// nearest-neighbour words (pairwise geometry of WideArgs).
+hipError_t launch_nn1_seed(const WideArgs &a, int grid, hipStream_t st);
 
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);

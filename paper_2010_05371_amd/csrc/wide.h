@@ -54,6 +54,7 @@ struct WideArgs {
   int64_t N, ld;
   int64_t nblk_j;                    // pairwise: column blocks per row series
   int ub_mode;                       // pairs: 0 none, 1 array, 2 ED; pairwise: ED
+  unsigned long long *nn1;           // pairwise: per-series nearest neighbour words (NN1 mode)
   const float *ub;
   float ub_scalar;
   float *out;
@@ -77,6 +78,8 @@ struct WideProblem {
   float ub;
   bool active;
   float ed;
+  // pairwise NN1: the two series' nearest-neighbour words (row uniform)
+  const unsigned long long *nn_i, *nn_j;
 };
 
 template <int KIND>
@@ -398,6 +401,9 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
     if (KIND == kWideSearch && !a.dists_mode && ++since >= a.check_interval) {
       since = 0;
       ub = fminf(ub, load_bsf_dist(a.bsf));
+    } else if (KIND == kWidePairwise && a.nn1 && ++since >= a.check_interval) {
+      since = 0;
+      ub = fminf(ub, fmaxf(load_bsf_dist(p.nn_i), load_bsf_dist(p.nn_j)));
     }
   }
   return (alive && !stopped && ans <= ub) ? ans : kInf;
@@ -454,8 +460,24 @@ __global__ __launch_bounds__(64) void wide_kernel(WideArgs a) {
       }
       p.ed = acc;
       p.ub = acc;
+      if (a.nn1) {
+        // NN1: the pair only matters if it beats the best of row i or of row j
+        // so far, so it is abandoned above the larger of the two (re-read
+        // during the sweep; never more than the squared ED, an admissible
+        // path's cost)
+        p.nn_i = a.nn1 + i;
+        p.nn_j = a.nn1 + jc;
+        p.ub = fminf(acc, fmaxf(load_bsf_dist(p.nn_i), load_bsf_dist(p.nn_j)));
+      }
       const float d = wide_problem<H, KIND, BANDED>(a, p, Bw, lane, evaluated, computed);
-      if (p.active) a.out[i * a.N - i * (i + 1) / 2 + (j - i - 1)] = d < kInf ? d : p.ed;
+      if (a.nn1) {
+        // both rows learn the pair: (distance, other index) packed, min-ed
+        const bool keep = p.active && d < kInf;
+        publish_best(a.nn1 + i, keep, d, (uint32_t)j);
+        if (keep) atomicMin(a.nn1 + j, pack_best(d, (uint32_t)i));
+      } else if (p.active) {
+        a.out[i * a.N - i * (i + 1) / 2 + (j - i - 1)] = d < kInf ? d : p.ed;
+      }
       abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
     } else {
       const int64_t pp = task * kWave + lane;

@@ -20,6 +20,37 @@ static hipError_t launch_wide_h(int kind, const WideArgs &a, int grid, hipStream
   return hipGetLastError();
 }
 
+// NN1 seeding: for every pair i < j the squared Euclidean distance, with the
+// operations of the pairwise kernel's (so it is never below the pair's DTW),
+// lowers both series' words to (ED, other index): each word then starts
+// from an admissible path's cost to an actual neighbour.  Task t = (i, block
+// of 64 j); one wave per workgroup.
+__global__ __launch_bounds__(64) void nn1_seed_kernel(WideArgs a) {
+  const int lane = threadIdx.x;
+  for (int64_t task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+    const int64_t i = task / a.nblk_j, jb = task % a.nblk_j;
+    if (jb * kWave + kWave - 1 <= i) continue;
+    const int64_t j = jb * kWave + lane;
+    const bool active = j > i && j < a.N;
+    const int64_t jc = active ? j : a.N - 1;
+    const float *rowp = a.X + i * a.lrow;
+    const float *colp = a.XT + jc;
+    float acc = 0.0f;
+    for (int t = 0; t < a.lrow; ++t) {
+      const float diff = colp[(int64_t)t * a.ld] - rowp[t];
+      acc = __builtin_fmaf(diff, diff, acc);
+    }
+    publish_best(a.nn1 + i, active, acc, (uint32_t)j);
+    if (active) atomicMin(a.nn1 + j, pack_best(acc, (uint32_t)i));
+  }
+}
+
+hipError_t launch_nn1_seed(const WideArgs &a, int grid, hipStream_t st) {
+  if (grid <= 0 || a.ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nn1_seed_kernel, dim3(grid), dim3(kWave), 0, st, a);
+  return hipGetLastError();
+}
+
 int wide_rows_for(int r, int lrow, int lcol) {
   const int lmax = lrow > lcol ? lrow : lcol;
   if (r >= lmax - 1) return kWideFullRows;

@@ -1,0 +1,66 @@
+"""GPU parity of the leave-one-out nearest neighbour (NN1) over a set of
+series: against the FP64 oracle on small sets, and at the all-pairs
+workload's full size against the minima of the GPU's own all-pairs matrix
+(same kernel arithmetic: the same bits) plus sampled oracle rows."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2010_05371_amd as eap
+from parity import close
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(idx, dist, X32, w, rows=None):
+    Xo = gen.as_oracle(X32)
+    N = X32.shape[0]
+    rows = range(N) if rows is None else rows
+    if len(rows) == N:
+        oj, od = oracle.nn1(Xo, w)
+    for i in rows:
+        others = np.array([j for j in range(N) if j != i])
+        if len(rows) == N:
+            ref_j, ref_d = int(oj[i]), float(od[i])
+        else:
+            ds = oracle.dtw_pairs(Xo, Xo, w, np.full(others.size, i), others)
+            ref_j, ref_d = int(others[np.argmin(ds)]), float(ds.min())
+        assert close(dist[i], ref_d), (i, dist[i], ref_d)
+        if idx[i] != ref_j:  # a near-tie: the reported neighbour's distance is the minimum
+            at = oracle.dtw_pairs(Xo, Xo, w, [i], [int(idx[i])])[0]
+            assert abs(at - ref_d) <= 1e-5 * ref_d + 1e-6, (i, idx[i], ref_j, at, ref_d)
+
+
+# (N, len, window): sets that span several 64-series blocks with a ragged
+# last one, band and whole-series windows
+@pytest.mark.parametrize("N,L,w", [(150, 48, 5), (130, 64, 63), (70, 100, 20), (200, 32, 0)])
+def test_nn1_vs_oracle(N, L, w):
+    X = np.stack([gen.standardise(gen.random_walk(L, gen.rng(4500, N * 10 + i))) for i in range(N)])
+    X32 = gen.as_f32(X)
+    X32[N // 2] = X32[3]  # a duplicate: each other's neighbour at distance 0
+    idx, dist = eap.nn1(torch.from_numpy(X32).cuda(), w)
+    assert idx[3] == N // 2 and idx[N // 2] == 3 and dist[3] == 0.0
+    _check(idx, dist, X32, w)
+
+
+def test_nn1_full_size_against_all_pairs():
+    """2,000 standardised random walks of 512, whole-series window: NN1 equals
+    the row/column minima of the all-pairs matrix bit for bit, and a sample of
+    rows equals the oracle's; far fewer cells than all pairs."""
+    X, w = gen.c3()
+    Xt = torch.from_numpy(X).cuda()
+    (idx, dist), st = eap.nn1(Xt, w, stats=True)
+    D, sp = eap.pairwise(Xt, w, stats=True)
+    D = D.cpu().numpy()
+    N = X.shape[0]
+    M = np.full((N, N), np.inf, dtype=np.float32)
+    iu = np.triu_indices(N, 1)
+    M[iu] = D
+    M.T[iu] = D
+    ref_j = np.argmin(M, axis=1)  # first index among equal minima
+    assert np.array_equal(dist.astype(np.float32), M[np.arange(N), ref_j])
+    assert np.array_equal(idx, ref_j)
+    _check(idx, dist, X, w, rows=[0, 777, 1999])
+    assert st["cells_evaluated"] < 0.5 * sp["cells_evaluated"]
