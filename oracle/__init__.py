@@ -28,7 +28,11 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
 * ``knn_search`` -- the k best offsets of the search (every distance, then a
   lexicographic sort of (distance, offset));
 * ``nn1`` -- leave-one-out nearest neighbour of every series of a set (every
-  pair, then row minima).
+  pair, then row minima);
+* ``wdtw``, ``wdtw_weights``, ``nn_dists_w``, ``nn_search_w`` -- weighted DTW
+  (DTW's recurrence, cost w(|i-j|) (a-b)^2 with the modified logistic weight),
+  one of the elastic distances with DTW's structure that the paper's outlook
+  names, and its search.
 """
 from __future__ import annotations
 
@@ -101,6 +105,13 @@ def _load():
     lib.oracle_knn_search.restype = ctypes.c_int
     lib.oracle_nn1.argtypes = [dp, i64, i64, i64, ctypes.c_int, ip, dp]
     lib.oracle_nn1.restype = ctypes.c_int
+    lib.oracle_wdtw_weights.argtypes = [i64, ctypes.c_double, dp]
+    lib.oracle_wdtw_weights.restype = None
+    lib.oracle_wdtw.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double]
+    lib.oracle_wdtw.restype = ctypes.c_double
+    lib.oracle_nn_dists_w.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double, ip, i64, ctypes.c_int,
+                                      dp]
+    lib.oracle_nn_dists_w.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -307,3 +318,37 @@ def nn1(X, window: int, nthreads: int | None = None):
     if rc != 0:
         raise ValueError(f"oracle_nn1 failed ({rc})")
     return oj, od
+
+
+def wdtw_weights(length: int, g: float) -> np.ndarray:
+    """w(k) = 1 / (1 + exp(-g (k - length/2))) for k = 0..length-1."""
+    wt = np.empty(max(int(length), 1))
+    _load().oracle_wdtw_weights(int(length), float(g), _ptr(wt))
+    return wt[:int(length)]
+
+
+def wdtw(S, T, window: int | None, g: float) -> float:
+    S, T = _f64(S), _f64(T)
+    r = max(S.size, T.size) if window is None else int(window)
+    return float(_load().oracle_wdtw(_ptr(S), S.size, _ptr(T), T.size, r, float(g)))
+
+
+def nn_dists_w(query, series, window: int, g: float, offsets,
+               nthreads: int | None = None) -> np.ndarray:
+    q, x = _f64(query), _f64(series)
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    out = np.empty(offs.size)
+    rc = _load().oracle_nn_dists_w(_ptr(q), q.size, _ptr(x), x.size, int(window), float(g),
+                                   _ptr(offs), offs.size, nthreads or default_threads(), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_nn_dists_w failed ({rc})")
+    return out
+
+
+def nn_search_w(query, series, window: int, g: float):
+    """(best offset, best weighted-DTW distance) over every offset (the first
+    offset among equal minima)."""
+    q = _f64(query)
+    d = nn_dists_w(query, series, window, g, np.arange(_f64(series).size - q.size + 1))
+    k = int(np.argmin(d))
+    return k, float(d[k])

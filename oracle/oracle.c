@@ -109,6 +109,52 @@ static double dtw_matrix(dtw_ws *w, const double *S, int64_t lS, const double *T
   return M[lS * W + lT];
 }
 
+/* Weighted DTW (an elastic distance with DTW's recurrence and another cost,
+ * the paper's closing outlook): cell (i, j) costs wt[|i-j|] (S_i - T_j)^2.
+ * wt has at least max(lS, lT) entries. */
+static double wdtw_matrix(dtw_ws *w, const double *S, int64_t lS, const double *T, int64_t lT,
+                          int64_t r, const double *wt) {
+  const int64_t W = lT + 1;
+  if (ws_reserve(w, (lS + 1) * W) != 0) return NAN;
+  double *M = w->M;
+  for (int64_t c = 0; c < (lS + 1) * W; ++c) M[c] = ORACLE_INF;
+  M[0] = 0.0;
+  for (int64_t i = 1; i <= lS; ++i) {
+    int64_t jlo = i - r, jhi = i + r;
+    if (jlo < 1) jlo = 1;
+    if (jhi > lT) jhi = lT;
+    for (int64_t j = jlo; j <= jhi; ++j) {
+      double d = S[i - 1] - T[j - 1];
+      double cost = wt[i > j ? i - j : j - i] * d * d;
+      M[i * W + j] = cost + min3d(M[(i - 1) * W + j], M[i * W + j - 1], M[(i - 1) * W + j - 1]);
+    }
+  }
+  return M[lS * W + lT];
+}
+
+/* The modified logistic weight of weighted DTW (Jeong, Jeong & Omitaomu,
+ * Pattern Recognition 2011): w(k) = 1 / (1 + exp(-g (k - mc))) for a phase
+ * difference k = |i - j|, with mc half the series length (the longer one for
+ * unequal lengths) and the maximum weight 1.  Fills wt[0..len). */
+void oracle_wdtw_weights(int64_t len, double g, double *wt) {
+  const double mc = (double)len / 2.0;
+  for (int64_t k = 0; k < len; ++k) wt[k] = 1.0 / (1.0 + exp(-g * ((double)k - mc)));
+}
+
+double oracle_wdtw(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r,
+                   double g) {
+  const int64_t L = lS > lT ? lS : lT;
+  double *wt = malloc((size_t)(L > 0 ? L : 1) * sizeof(double));
+  dtw_ws w = {0, 0};
+  if (!wt) return NAN;
+  oracle_wdtw_weights(L, g, wt);
+  double v = (lS == 0 && lT == 0) ? 0.0 : (lS == 0 || lT == 0) ? ORACLE_INF
+                                                                : wdtw_matrix(&w, S, lS, T, lT, r, wt);
+  free(w.M);
+  free(wt);
+  return v;
+}
+
 double oracle_dtw(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r) {
   if (lS == 0 && lT == 0) return 0.0;          /* Eq. 2 */
   if (lS == 0 || lT == 0) return ORACLE_INF;   /* Eq. 3-4 */
@@ -219,6 +265,7 @@ typedef struct {
   int64_t lo, hi;         /* slice [lo,hi) of offsets[] */
   double *out;            /* per-offset distances (indexed like offsets[]) */
   int err;
+  const double *wt;       /* weighted DTW: weights by |i-j| (NULL: DTW) */
 } nn_job;
 
 static void *nn_worker(void *arg) {
@@ -231,7 +278,8 @@ static void *nn_worker(void *arg) {
   for (int64_t t = jb->lo; t < jb->hi; ++t) {
     int64_t k = jb->offsets[t];
     oracle_znorm(jb->x + k, jb->m, zc);
-    double v = dtw_matrix(&w, zq, jb->m, zc, jb->m, jb->r);
+    double v = jb->wt ? wdtw_matrix(&w, zq, jb->m, zc, jb->m, jb->r, jb->wt)
+                      : dtw_matrix(&w, zq, jb->m, zc, jb->m, jb->r);
     if (!w.M) { jb->err = -1; goto done; }
     jb->out[t] = v;
   }
@@ -245,8 +293,32 @@ done:
 /* Distances d_k = DTW(z(query), z(x[k..k+m)), window r) for the listed
  * offsets (Section 2.2's candidates T_1..T_m, Section 5's subsequence search).
  * Returns 0 on success. */
+static int nn_dists_impl(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                         const int64_t *offsets, int64_t noff, int nthreads, double *out,
+                         const double *wt);
+
 int oracle_nn_dists(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
                     const int64_t *offsets, int64_t noff, int nthreads, double *out) {
+  return nn_dists_impl(q, m, x, n, r, offsets, noff, nthreads, out, NULL);
+}
+
+/* Weighted-DTW distances of the listed candidates (weights of
+ * oracle_wdtw_weights for length m and parameter g). */
+int oracle_nn_dists_w(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                      double g, const int64_t *offsets, int64_t noff, int nthreads,
+                      double *out) {
+  if (m <= 0) return -2;
+  double *wt = malloc((size_t)m * sizeof(double));
+  if (!wt) return -1;
+  oracle_wdtw_weights(m, g, wt);
+  int rc = nn_dists_impl(q, m, x, n, r, offsets, noff, nthreads, out, wt);
+  free(wt);
+  return rc;
+}
+
+static int nn_dists_impl(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                         const int64_t *offsets, int64_t noff, int nthreads, double *out,
+                         const double *wt) {
   for (int64_t t = 0; t < noff; ++t)
     if (offsets[t] < 0 || offsets[t] + m > n) return -2;
   if (nthreads < 1) nthreads = 1;
@@ -259,7 +331,7 @@ int oracle_nn_dists(const double *q, int64_t m, const double *x, int64_t n, int6
     int64_t lo = (int64_t)t * per, hi = lo + per;
     if (lo > noff) lo = noff;
     if (hi > noff) hi = noff;
-    jobs[t] = (nn_job){q, m, x, r, offsets, lo, hi, out, 0};
+    jobs[t] = (nn_job){q, m, x, r, offsets, lo, hi, out, 0, wt};
     live[t] = pthread_create(&th[t], NULL, nn_worker, &jobs[t]) == 0;
     if (!live[t]) nn_worker(&jobs[t]);
   }
