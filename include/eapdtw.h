@@ -393,6 +393,25 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
 int eapdtw_nn1(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t window,
                int64_t *out_index, double *out_dist, eapdtw_stats *stats);
 
+/* ---------------------------------------------------------------------------
+ * Weighted DTW search, an elastic distance with DTW's recurrence and another
+ * cost (the paper's outlook, Section 6: EAPrunedDTW carries over to such
+ * distances unchanged, since costs stay non-negative): cell (i, j) costs
+ * w(|i-j|) (q_i - c_j)^2 with the modified logistic weight of weighted DTW
+ * (Jeong, Jeong & Omitaomu, 2011), w(k) = 1 / (1 + exp(-g (k - m/2))), maximum
+ * weight 1, m the query length; weights are computed in double and rounded to
+ * float32.  Otherwise as eapdtw_nn_search / eapdtw_nn_dists (z-normalisation,
+ * early abandoning, pruning, ties, errors).  g must be finite; windows above
+ * 64 (after clamping to m-1): EINVAL.
+ * eapdtw_nn_search_w: synchronous.  eapdtw_nn_dists_w: asynchronous unless
+ * stats are requested. */
+int eapdtw_nn_search_w(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                       int64_t n, int64_t window, float g, int64_t *out_offset, double *out_dist,
+                       eapdtw_stats *stats);
+int eapdtw_nn_dists_w(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                      int64_t n, int64_t window, float g, float ub, float *out,
+                      eapdtw_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

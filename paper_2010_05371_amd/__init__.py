@@ -35,7 +35,7 @@ __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_d
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
-           "nn_lower_bounds", "LbStats", "knn_search", "nn1"]
+           "nn_lower_bounds", "LbStats", "knn_search", "nn1", "nn_search_w", "nn_dists_w"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -278,6 +278,35 @@ def knn_search(query, series, window: int, k: int, stats: bool = False):
                                          ctypes.byref(st) if stats else None))
     res = [(offs[i], dists[i]) for i in range(kk)]
     return (res, st.as_dict()) if stats else res
+
+
+def nn_search_w(query, series, window: int, g: float, stats: bool = False):
+    """nn_search under weighted DTW (cost w(|i-j|) (a-b)^2, modified logistic
+    weight with parameter g)."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    off = ctypes.c_int64()
+    dist = ctypes.c_double()
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn_search_w(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                          int(window), float(g), ctypes.byref(off),
+                                          ctypes.byref(dist), ctypes.byref(st) if stats else None))
+    res = (off.value, dist.value)
+    return (res, st.as_dict()) if stats else res
+
+
+def nn_dists_w(query, series, window: int, g: float, ub: float = math.inf, stats: bool = False):
+    """nn_dists under weighted DTW."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    out = torch.empty(x.numel() - q.numel() + 1, device=x.device, dtype=torch.float32)
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn_dists_w(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                         int(window), float(g), float(ub), _ptr(out),
+                                         ctypes.byref(st) if stats else None))
+    return (out, st.as_dict()) if stats else out
 
 
 def nn1(X, window: int, stats: bool = False):

@@ -637,7 +637,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
                         int64_t n, int64_t r, float *qpad, unsigned long long *bsf,
                         unsigned long long *cnt, float *dists, float fixed_ub, float *bnd,
                         int64_t bnd_waves, bool time_main, const LbBufs *lb = nullptr,
-                        const KnnBufs *kb = nullptr) {
+                        const KnnBufs *kb = nullptr, const float *wgt = nullptr) {
   hipStream_t st = ctx->stream;
   const int64_t K = n - m + 1;
   const int64_t nblk = (K + kWave - 1) / kWave;
@@ -654,6 +654,10 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
   a.k_end = K;
   a.check_interval = (int)ctx->check_interval;
   a.block_stride = 1;
+  // weighted DTW: the weights of phase differences 0..r (the unweighted
+  // window-0 seeding pass stays valid: every weight is at most 1, so the
+  // squared Euclidean distance bounds the weighted diagonal path's cost)
+  if (wgt) std::memcpy(a.wgt, wgt, sizeof(float) * (size_t)(r + 1));
   bool joined = true;
   if (!dists && ctx->seed) {
     // Bound seeding.  A candidate's DTW under a narrower window is never below
@@ -701,7 +705,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       ss = ctx->seed_stream;
       if (!kb) a.bsf_init = bsf + 1;  // the search's waves start from the window-0 bound
     }
-    if (rs == 0 && ctx->ed && !kb)  // (the window-0 kernel publishes only the best)
+    if (wgt)
+      HIPCHK(nn_wband_launcher((int)rs)(s, 1, false, false, ss));
+    else if (rs == 0 && ctx->ed && !kb)  // (the window-0 kernel publishes only the best)
       HIPCHK(launch_ed_search(s, 1, false, ss));
     else
       HIPCHK(nn_band_launcher((int)rs)(s, 1, pick_rows(ctx, (int)rs), false, false, ss));
@@ -780,7 +786,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     a.counters = cnt;
     a.fixed_ub = fixed_ub;
     a.dists = dists;
-    if (kb) {
+    if (wgt) {
+      HIPCHK(nn_wband_launcher((int)r)(a, nblk, dists != nullptr, ctx->border != 0, st));
+    } else if (kb) {
       a.knn = kb->k;
       a.knn_buf = kb->buf;
       a.knn_n = kb->n;
@@ -892,7 +900,8 @@ static void fill_lb_stats(eapdtw_lb_stats *ls, const unsigned long long *cnt, bo
 
 static int nn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                           int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
-                          eapdtw_stats *stats, bool use_lb, eapdtw_lb_stats *lbstats) {
+                          eapdtw_stats *stats, bool use_lb, eapdtw_lb_stats *lbstats,
+                          const float *wgt = nullptr) {
   CHECK_CTX();
   KnobGuard knobs(ctx);
   knobs.apply_cached(m, window);
@@ -922,7 +931,8 @@ static int nn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const 
   if (lb_on) lbb = lb_bind(ctx, o_lb);
   if (timed) HIPCHK(hipEventRecord(ctx->ev0, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
-                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr);
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr,
+                    nullptr, wgt);
   if (rc) return rc;
   if (timed) HIPCHK(hipEventRecord(ctx->ev1, st));
   // counters and the two best-so-far words are contiguous
@@ -958,7 +968,7 @@ int eapdtw_nn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
 
 static int nn_dists_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                          int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats,
-                         bool use_lb, eapdtw_lb_stats *lbstats) {
+                         bool use_lb, eapdtw_lb_stats *lbstats, const float *wgt = nullptr) {
   CHECK_CTX();
   KnobGuard knobs(ctx);
   knobs.apply_cached(m, window);
@@ -989,7 +999,8 @@ static int nn_dists_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const f
   if (timed) HIPCHK(hipEventRecord(ctx->ev0, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q),
                     at<unsigned long long>(ctx, o_bsf), cnt, out, ub,
-                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr);
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr,
+                    nullptr, wgt);
   if (rc) return rc;
   if (timed) {
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -1013,6 +1024,40 @@ int eapdtw_nn_dists_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const flo
                        int64_t n, int64_t window, float ub, float *out, eapdtw_stats *stats,
                        eapdtw_lb_stats *lbstats) {
   return nn_dists_impl(ctx, query, m, series, n, window, ub, out, stats, true, lbstats);
+}
+
+// Weights of weighted DTW for phase differences 0..r of a query of length m
+// (modified logistic weight, maximum 1, midpoint m / 2).  Fails for windows
+// the band kernels do not serve.
+static int wdtw_prepare(eapdtw_ctx *ctx, int64_t m, int64_t window, float g, float *wt) {
+  if (!std::isfinite(g)) return fail(ctx, EAPDTW_EINVAL, "weighted DTW: g must be finite");
+  if (m <= 0 || window < 0) return EAPDTW_OK;  // left to the search's own checks
+  const int64_t r = window < m - 1 ? window : m - 1;
+  if (!use_band(ctx, r)) return fail(ctx, EAPDTW_EINVAL, "weighted DTW: window above 64");
+  for (int64_t k = 0; k <= r; ++k)
+    wt[k] = (float)(1.0 / (1.0 + std::exp(-(double)g * ((double)k - (double)m / 2.0))));
+  return EAPDTW_OK;
+}
+
+int eapdtw_nn_search_w(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                       int64_t n, int64_t window, float g, int64_t *out_offset, double *out_dist,
+                       eapdtw_stats *stats) {
+  CHECK_CTX();
+  float wt[kBandRMax + 1] = {};
+  int rc = wdtw_prepare(ctx, m, window, g, wt);
+  if (rc) return rc;
+  return nn_search_impl(ctx, query, m, series, n, window, out_offset, out_dist, stats, false,
+                        nullptr, wt);
+}
+
+int eapdtw_nn_dists_w(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                      int64_t n, int64_t window, float g, float ub, float *out,
+                      eapdtw_stats *stats) {
+  CHECK_CTX();
+  float wt[kBandRMax + 1] = {};
+  int rc = wdtw_prepare(ctx, m, window, g, wt);
+  if (rc) return rc;
+  return nn_dists_impl(ctx, query, m, series, n, window, ub, out, stats, false, nullptr, wt);
 }
 
 int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,

@@ -174,10 +174,12 @@ constexpr int kColChunk = 16;
 // next_base set, the last chunk's step loads the next group's first chunk
 // (whose base is next_base) into first[], so no group starts by waiting for
 // its column values.
-template <int R, int U, class Ptr>
+// WT: weighted DTW, cell cost wt[|d - R|] (column - row value)^2 (wt holds
+// the weights of the band's phase differences 0..R).
+template <int R, int U, bool WT = false, class Ptr>
 __device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (&rv)[U],
                                             Cols<Ptr> cs, float (&first)[kColChunk],
-                                            Ptr next_base) {
+                                            Ptr next_base, const float *wt = nullptr) {
   constexpr int W = 2 * R + 1;
   constexpr int NS = W + U - 1;
   constexpr int CH = kColChunk;
@@ -213,7 +215,8 @@ __device__ __forceinline__ void sweep_group(float (&v)[2 * R + 1], const float (
         const float left = (d > 0) ? v[d > 0 ? d - 1 : 0] : kInf;
         const float top = (d < W - 1) ? v[d < W - 1 ? d + 1 : 0] : kInf;
         const float diff = cv - rv[u];
-        v[d] = __builtin_fmaf(diff, diff, fmin3(left, top, v[d]));
+        const float dw = WT ? diff * wt[d < R ? R - d : d - R] : diff;
+        v[d] = __builtin_fmaf(dw, diff, fmin3(left, top, v[d]));
       }
     }
     // Pin this chunk's results before the next chunk's loads are issued:
@@ -335,11 +338,12 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
 // qn / qn_unit: column values of unit qn_unit of this group, loaded during the
 // previous group; on return, those of unit b.lo of the next group (whose
 // columns start next_base), loaded while this group is swept.
-template <int R, int U, class Ptr>
+template <int R, int U, bool WT = false, class Ptr>
 __device__ __forceinline__ int sweep_group_border(float (&v)[2 * R + 1], const float (&rv)[U],
                                                   Cols<Ptr> cs, const Border &b, uint32_t ubits,
                                                   uint64_t amask, float (&qn)[kColChunk],
-                                                  int &qn_unit, Ptr next_base) {
+                                                  int &qn_unit, Ptr next_base,
+                                                  const float *wt = nullptr) {
   static_assert(kBorderChunk <= kColChunk, "look-ahead buffer too small");
   constexpr int W = 2 * R + 1;
   constexpr int NS = W + U - 1;
@@ -396,7 +400,8 @@ __device__ __forceinline__ int sweep_group_border(float (&v)[2 * R + 1], const f
         const float left = (d > 0) ? v[d > 0 ? d - 1 : 0] : kInf;
         const float top = (d < W - 1) ? v[d < W - 1 ? d + 1 : 0] : kInf;
         const float diff = cvl - rv[u];
-        v[d] = __builtin_fmaf(diff, diff, fmin3(left, top, v[d]));
+        const float dw = WT ? diff * wt[d < R ? R - d : d - R] : diff;
+        v[d] = __builtin_fmaf(dw, diff, fmin3(left, top, v[d]));
       }
     }
     // volatile asm keeps its order, so the next unit's loads cannot be
@@ -598,7 +603,7 @@ __device__ __forceinline__ float load_bsf_dist(const unsigned long long *bsf) {
 // value per column, read through the scalar cache).
 // DISTS = true writes every candidate's early-abandoned distance against the
 // fixed bound instead of updating the shared best-so-far.
-template <int R, int U, bool DISTS, bool BORDER = false, bool LIST = false>
+template <int R, int U, bool DISTS, bool BORDER = false, bool LIST = false, bool WT = false>
 __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   constexpr int W = 2 * R + 1;
   const int lane = threadIdx.x;
@@ -764,12 +769,13 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
     for (int u = 0; u < G; ++u) rvl[u] = rvg[u];
     int slast = W + G - 2;
     if constexpr (BORDER) {
-      slast = sweep_group_border<R, G>(v, rvl, cols, bd, cell_bits(thr),
-                                       __builtin_amdgcn_ballot_w64(alive), qfirst, qfirst_unit,
-                                       as_const(a.qpad + kColPad + i + G - R));
+      slast = sweep_group_border<R, G, WT>(v, rvl, cols, bd, cell_bits(thr),
+                                           __builtin_amdgcn_ballot_w64(alive), qfirst,
+                                           qfirst_unit, as_const(a.qpad + kColPad + i + G - R),
+                                           a.wgt);
       swept_cells<G>(i, kBorderChunk * bd.lo - 1, slast, m, R, band, mat);
     } else {
-      sweep_group<R, G>(v, rvl, cols, qfirst, as_const(a.qpad + kColPad + i + G - R));
+      sweep_group<R, G, WT>(v, rvl, cols, qfirst, as_const(a.qpad + kColPad + i + G - R), a.wgt);
       band = G * W;
       mat = rows_cells<G>(i, m, R);
     }
@@ -864,6 +870,13 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
 template <int R, int U, bool DISTS, bool BORDER>
 __global__ __launch_bounds__(64, (BORDER && R <= 52) ? 4 : 1) void nn_band_kernel(NNArgs a) {
   nn_band_body<R, U, DISTS, BORDER>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Weighted DTW (cost w(|i-j|) (a-b)^2, weights in NNArgs::wgt): the same
+// search with one more multiply per cell.
+template <int R, int U, bool DISTS, bool BORDER>
+__global__ __launch_bounds__(64, (BORDER && R <= 52) ? 4 : 1) void nn_wband_kernel(NNArgs a) {
+  nn_band_body<R, U, DISTS, BORDER, false, true>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // The candidates that passed the lower bounds (list mode of the same sweep);
@@ -981,6 +994,9 @@ hipError_t launch_nn_band(const NNArgs &a, int64_t nblocks, int rows_per_group, 
 template <int R>
 hipError_t launch_nn_list(const NNArgs &a, int64_t nblocks, bool dists, bool border,
                           hipStream_t st);
+template <int R>
+hipError_t launch_nn_wband(const NNArgs &a, int64_t nblocks, bool dists, bool border,
+                           hipStream_t st);
 template <int R>
 hipError_t launch_pair_band(const PairArgs &a, int64_t nblocks, int rows_per_group,
                             hipStream_t st);

@@ -53,6 +53,25 @@ hipError_t launch_nn_list(const NNArgs &a, int64_t nblocks, bool dists, bool bor
 }
 
 template <int R>
+hipError_t launch_nn_wband(const NNArgs &a, int64_t nblocks, bool dists, bool border,
+                           hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks), block(kWave);
+  constexpr bool kB = R >= kBorderMinR;
+  if (kB && border) {
+    if (dists)
+      hipLaunchKernelGGL((nn_wband_kernel<R, 4, true, kB>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((nn_wband_kernel<R, 4, false, kB>), grid, block, 0, st, a);
+  } else if (dists) {
+    hipLaunchKernelGGL((nn_wband_kernel<R, 4, true, false>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((nn_wband_kernel<R, 4, false, false>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int R>
 hipError_t launch_pair_band(const PairArgs &a, int64_t nblocks, int rows_per_group,
                             hipStream_t st) {
   (void)rows_per_group;
@@ -64,6 +83,7 @@ hipError_t launch_pair_band(const PairArgs &a, int64_t nblocks, int rows_per_gro
 #define EAPDTW_INST(R)                                                                       \
   template hipError_t launch_nn_band<R>(const NNArgs &, int64_t, int, bool, bool, hipStream_t); \
   template hipError_t launch_nn_list<R>(const NNArgs &, int64_t, bool, bool, hipStream_t);     \
+  template hipError_t launch_nn_wband<R>(const NNArgs &, int64_t, bool, bool, hipStream_t);    \
   template hipError_t launch_pair_band<R>(const PairArgs &, int64_t, int, hipStream_t);
 
 #if EAPDTW_R_LO <= 0 && 0 <= EAPDTW_R_HI

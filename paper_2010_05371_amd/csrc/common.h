@@ -107,6 +107,8 @@ struct NNArgs {
   int knn;
   unsigned long long *knn_buf;
   unsigned long long *knn_n;
+  // weighted DTW kernels: the weight of phase difference |i - j| = 0..kBandRMax
+  float wgt[kBandRMax + 1];
 };
 
 // Largest k of the k-nearest-neighbour search (one wave sorts 64 candidates).

@@ -26,6 +26,8 @@ hipError_t launch_ed_search(const NNArgs &a, int64_t nblocks, bool dists, hipStr
 // Band-in-registers kernels for windows 0..kBandRMax (nullptr otherwise).
 NNLaunchFn nn_band_launcher(int r);
 NNListLaunchFn nn_list_launcher(int r);
+// Weighted-DTW band search (same signature as the list launcher).
+NNListLaunchFn nn_wband_launcher(int r);
 PairLaunchFn pair_band_launcher(int r);
 
 // Lower bounds (lb.hip): envelopes of the series and of z(query) under window
