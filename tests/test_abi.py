@@ -22,7 +22,9 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("eapdtw_dtw", "eapdtw_nn_search", "eapdtw_nn_search_batch", "eapdtw_dtw_pairs",
                  "eapdtw_pairwise", "eapdtw_dtw_fwd", "eapdtw_dtw_bwd", "eapdtw_create",
-                 "eapdtw_destroy", "eapdtw_last_error"):
+                 "eapdtw_destroy", "eapdtw_last_error", "eapdtw_nn_search_lb", "eapdtw_nn_dists_lb",
+                 "eapdtw_nn_lower_bounds", "eapdtw_knn_search", "eapdtw_nn1", "eapdtw_nn_search_w",
+                 "eapdtw_nn_dists_w"):
         assert must in names
 
 
@@ -46,6 +48,10 @@ def test_null_context_is_einval():
     assert lib.eapdtw_dtw(None, None, 0, None, 0, 0, 0.0, ctypes.byref(out), None) == _lib.EAPDTW_EINVAL
     assert lib.eapdtw_set_option(None, b"seed", 1) == _lib.EAPDTW_EINVAL
     assert lib.eapdtw_nn_search(None, None, 1, None, 1, 0, None, None, None) == _lib.EAPDTW_EINVAL
+    assert lib.eapdtw_nn_search_lb(None, None, 1, None, 1, 0, None, None, None, None) == _lib.EAPDTW_EINVAL
+    assert lib.eapdtw_knn_search(None, None, 1, None, 1, 0, 1, None, None, None) == _lib.EAPDTW_EINVAL
+    assert lib.eapdtw_nn1(None, None, 2, 4, 0, None, None, None) == _lib.EAPDTW_EINVAL
+    assert lib.eapdtw_nn_search_w(None, None, 1, None, 1, 0, 0.1, None, None, None) == _lib.EAPDTW_EINVAL
 
 
 def test_create_rejects_null_out():
