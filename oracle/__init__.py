@@ -28,7 +28,8 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
 * ``knn_search`` -- the k best offsets of the search (every distance, then a
   lexicographic sort of (distance, offset));
 * ``nn1`` -- leave-one-out nearest neighbour of every series of a set (every
-  pair, then row minima);
+  pair, then row minima); ``nn1_ref`` -- nearest neighbour of every test
+  series in a separate reference set;
 * ``wdtw``, ``wdtw_weights``, ``nn_dists_w``, ``nn_search_w`` -- weighted DTW
   (DTW's recurrence, cost w(|i-j|) (a-b)^2 with the modified logistic weight),
   one of the elastic distances with DTW's structure that the paper's outlook
@@ -105,6 +106,8 @@ def _load():
     lib.oracle_knn_search.restype = ctypes.c_int
     lib.oracle_nn1.argtypes = [dp, i64, i64, i64, ctypes.c_int, ip, dp]
     lib.oracle_nn1.restype = ctypes.c_int
+    lib.oracle_nn1_ref.argtypes = [dp, i64, dp, i64, i64, i64, ctypes.c_int, ip, dp]
+    lib.oracle_nn1_ref.restype = ctypes.c_int
     lib.oracle_wdtw_weights.argtypes = [i64, ctypes.c_double, dp]
     lib.oracle_wdtw_weights.restype = None
     lib.oracle_wdtw.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double]
@@ -352,3 +355,17 @@ def nn_search_w(query, series, window: int, g: float):
     d = nn_dists_w(query, series, window, g, np.arange(_f64(series).size - q.size + 1))
     k = int(np.argmin(d))
     return k, float(d[k])
+
+
+def nn1_ref(Q, R, window: int, nthreads: int | None = None):
+    """(index, distance) arrays: for each row i of Q [nq][L], the row j of R
+    [nr][L] with the smallest DTW (smaller j on ties)."""
+    Q, R = _f64(Q), _f64(R)
+    nq, L = Q.shape
+    oj = np.empty(nq, dtype=np.int64)
+    od = np.empty(nq)
+    rc = _load().oracle_nn1_ref(_ptr(Q), nq, _ptr(R), R.shape[0], L, int(window),
+                                nthreads or default_threads(), _ptr(oj), _ptr(od))
+    if rc != 0:
+        raise ValueError(f"oracle_nn1_ref failed ({rc})")
+    return oj, od

@@ -781,3 +781,36 @@ done:
   free(ia); free(ib); free(D);
   return rc;
 }
+
+/* Nearest neighbour of every series of a test set Q [nq][L] among a separate
+ * reference set R [nr][L] (NN1 classification): for each i, the j with the
+ * smallest DTW(Q_i, R_j) under window r, the smaller j among equal distances.
+ * Plain definition: every (i, j) through oracle_dtw_pairs, then row minima. */
+int oracle_nn1_ref(const double *Q, int64_t nq, const double *R, int64_t nr, int64_t L,
+                   int64_t r, int nthreads, int64_t *out_j, double *out_d) {
+  if (nq < 1 || nr < 1 || L < 1) return -2;
+  const int64_t P = nq * nr;
+  int64_t *ia = malloc((size_t)P * sizeof(int64_t)), *ib = malloc((size_t)P * sizeof(int64_t));
+  double *D = malloc((size_t)P * sizeof(double));
+  int rc = -1;
+  if (!ia || !ib || !D) goto done;
+  for (int64_t i = 0, p = 0; i < nq; ++i)
+    for (int64_t j = 0; j < nr; ++j, ++p) {
+      ia[p] = i;
+      ib[p] = j;
+    }
+  if ((rc = oracle_dtw_pairs(Q, R, L, r, ia, ib, P, nthreads, D)) != 0) goto done;
+  for (int64_t i = 0; i < nq; ++i) {
+    out_j[i] = 0;
+    out_d[i] = D[i * nr];
+    for (int64_t j = 1; j < nr; ++j)
+      if (D[i * nr + j] < out_d[i]) {
+        out_d[i] = D[i * nr + j];
+        out_j[i] = j;
+      }
+  }
+  rc = 0;
+done:
+  free(ia); free(ib); free(D);
+  return rc;
+}

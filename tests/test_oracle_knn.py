@@ -91,3 +91,16 @@ def test_nn1_two_series():
     X = gen.rng(606).standard_normal((2, 9))
     oj, od = oracle.nn1(X, 2)
     assert oj.tolist() == [1, 0] and od[0] == od[1] == oracle.dtw(X[0], X[1], 2)
+
+
+@pytest.mark.parametrize("w", [0, 4, 30])
+def test_nn1_ref_brute_force(w):
+    g = gen.rng(607, w)
+    Q, R = g.standard_normal((12, 16)), g.standard_normal((40, 16))
+    R[9] = Q[5]    # a copy of a test series: its neighbour at 0
+    R[31] = Q[5]   # a second copy: the smaller index wins
+    oj, od = oracle.nn1_ref(Q, R, w)
+    for i in range(12):
+        ds = [oracle.dtw(Q[i], R[j], w) for j in range(40)]
+        assert (int(oj[i]), float(od[i])) == (int(np.argmin(ds)), float(min(ds)))
+    assert oj[5] == 9 and od[5] == 0.0
