@@ -393,6 +393,19 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
 int eapdtw_nn1(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t window,
                int64_t *out_index, double *out_dist, eapdtw_stats *stats);
 
+/* Nearest neighbour of every series of a test set among a separate reference
+ * set (NN1 classification): for each test series i, the reference series j with
+ * the smallest DTW(Q_i, R_j) under the window, the smaller j on ties.  Every
+ * pair is early-abandoned above its test series' best distance so far (and
+ * pruned with the squared Euclidean distance); a seeding pass starts each
+ * test series from its smallest squared Euclidean distance.
+ *   Q [nq][len], R [nr][len] : DEVICE float32 row-major, used as given.
+ *   out_index : HOST [nq] int64, out_dist : HOST [nq].
+ * Empty sets or len < 1: EINVAL.  Synchronous. */
+int eapdtw_nn1_ref(eapdtw_ctx *ctx, const float *Q, int64_t nq, const float *R, int64_t nr,
+                   int64_t len, int64_t window, int64_t *out_index, double *out_dist,
+                   eapdtw_stats *stats);
+
 /* ---------------------------------------------------------------------------
  * Weighted DTW search, an elastic distance with DTW's recurrence and another
  * cost (the paper's outlook, Section 6: EAPrunedDTW carries over to such

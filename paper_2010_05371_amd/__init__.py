@@ -35,7 +35,8 @@ __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_d
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
-           "nn_lower_bounds", "LbStats", "knn_search", "nn1", "nn_search_w", "nn_dists_w"]
+           "nn_lower_bounds", "LbStats", "knn_search", "nn1", "nn_search_w", "nn_dists_w",
+           "nn1_ref"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -326,6 +327,26 @@ def nn1(X, window: int, stats: bool = False):
                                   idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                   dist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   ctypes.byref(st) if stats else None))
+    return ((idx, dist), st.as_dict()) if stats else (idx, dist)
+
+
+def nn1_ref(Q, R, window: int, stats: bool = False):
+    """Nearest neighbour of every row of the test set Q [nq][len] among the rows
+    of the reference set R [nr][len]: (index, distance) numpy arrays."""
+    import numpy as np
+
+    Q, R = _dev(Q), _dev(R)
+    assert Q.dim() == 2 and R.dim() == 2 and Q.shape[1] == R.shape[1], "Q, R must be [n][len]"
+    nq, L = Q.shape
+    ctx = context(Q.device.index)
+    ctx.bind_stream()
+    idx = np.empty(nq, dtype=np.int64)
+    dist = np.empty(nq, dtype=np.float64)
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn1_ref(ctx.handle, _ptr(Q), nq, _ptr(R), R.shape[0], L, int(window),
+                                      idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      dist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.byref(st) if stats else None))
     return ((idx, dist), st.as_dict()) if stats else (idx, dist)
 
 

@@ -108,6 +108,8 @@ def load():
         "eapdtw_knn_search": ([vp, vp, i64, vp, i64, i64, i64, ctypes.POINTER(i64),
                                ctypes.POINTER(f64), sp], i32),
         "eapdtw_nn1": ([vp, vp, i64, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(f64), sp], i32),
+        "eapdtw_nn1_ref": ([vp, vp, i64, vp, i64, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(f64),
+                            sp], i32),
         "eapdtw_nn_search_w": ([vp, vp, i64, vp, i64, i64, f32, ctypes.POINTER(i64),
                                 ctypes.POINTER(f64), sp], i32),
         "eapdtw_nn_dists_w": ([vp, vp, i64, vp, i64, i64, f32, f32, vp, sp], i32),

@@ -1180,6 +1180,76 @@ int eapdtw_nn1(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t 
   return EAPDTW_OK;
 }
 
+int eapdtw_nn1_ref(eapdtw_ctx *ctx, const float *Q, int64_t nq, const float *R, int64_t nr,
+                   int64_t len, int64_t window, int64_t *out_index, double *out_dist,
+                   eapdtw_stats *stats) {
+  CHECK_CTX();
+  if (nq < 1 || nr < 1 || len < 1) return fail(ctx, EAPDTW_EINVAL, "empty test or reference set");
+  if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
+  if (!Q || !R || !out_index || !out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
+  if (len > INT_MAX / 2 || nr > (int64_t)0xfffffffe || nq > ((int64_t)1 << 40))
+    return fail(ctx, EAPDTW_EINVAL, "too large");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int64_t npairs = nq * nr;
+  const int64_t r = window < len - 1 ? window : len - 1;
+  const int64_t ldN = (nr + kWave - 1) / kWave * kWave;
+  const int64_t nblk_j = ldN / kWave;
+  const int64_t ntasks = nq * nblk_j;
+  const int64_t grid = wide_grid(ntasks);
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_nn = pl.add(sizeof(unsigned long long) * nq);
+  const size_t o_xt = pl.add(sizeof(float) * len * ldN);
+  const size_t o_bnd = pl.add(sizeof(float) * grid * (len + 1) * kWave);
+  int rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  unsigned long long *nn = at<unsigned long long>(ctx, o_nn);
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
+  HIPCHK(launch_fill_u64(nn, pack_best(INFINITY, 0xffffffffu), nq, st));
+  HIPCHK(launch_transpose_pad(R, nr, (int)len, ldN, 0, 0.0f, at<float>(ctx, o_xt), st));
+  WideArgs w{};
+  w.lrow = (int)len;
+  w.lcol = (int)len;
+  w.r = (int)r;
+  w.X = Q;
+  w.XT = at<float>(ctx, o_xt);
+  w.N = nr;
+  w.nq = nq;
+  w.ld = ldN;
+  w.nblk_j = nblk_j;
+  w.ub_mode = 2;
+  w.nn1 = nn;
+  w.ntasks = ntasks;
+  w.bnd = at<float>(ctx, o_bnd);
+  w.bnd_stride = (len + 1) * kWave;
+  w.counters = cnt;
+  w.check_interval = 1;
+  HIPCHK(launch_nn1_seed(w, (int)grid, st));
+  if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
+  HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
+  if (stats) {
+    HIPCHK(hipEventRecord(ctx->ev3, st));
+    HIPCHK(hipEventRecord(ctx->ev1, st));
+  }
+  rc = readback(ctx, o_cnt, o_nn + sizeof(unsigned long long) * nq - o_cnt);
+  if (rc) return rc;
+  const unsigned long long *words =
+      reinterpret_cast<const unsigned long long *>(ctx->pinned + (o_nn - o_cnt));
+  for (int64_t i = 0; i < nq; ++i) {
+    out_index[i] = best_offset(words[i]) == 0xffffffffu ? -1 : (int64_t)best_offset(words[i]);
+    out_dist[i] = (double)best_dist(words[i]);
+  }
+  if (stats)
+    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned),
+               (uint64_t)(band_cells_total(len, len, r) * npairs), (uint64_t)npairs,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+  return EAPDTW_OK;
+}
+
 int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                       int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
                       double *out_dists, eapdtw_stats *stats) {

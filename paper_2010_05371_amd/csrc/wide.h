@@ -55,6 +55,9 @@ struct WideArgs {
   int64_t nblk_j;                    // pairwise: column blocks per row series
   int ub_mode;                       // pairs: 0 none, 1 array, 2 ED; pairwise: ED
   unsigned long long *nn1;           // pairwise: per-series nearest neighbour words (NN1 mode)
+  int64_t nq;                        // pairwise: > 0 = rows are the nq series of X, columns the
+                                     // N series of XT, every (row, column) pair (NN1 of a test
+                                     // set against a reference set); 0 = i < j within one set
   const float *ub;
   float ub_scalar;
   float *out;
@@ -446,9 +449,10 @@ __global__ __launch_bounds__(64) void wide_kernel(WideArgs a) {
       wide_search_task<H, BANDED>(a, task, Bw, lane, evaluated, computed, abandoned);
     } else if (KIND == kWidePairwise) {
       const int64_t i = task / a.nblk_j, jb = task % a.nblk_j;
-      if (jb * kWave + kWave - 1 <= i) continue;  // block entirely on or below the diagonal
+      const bool cross = a.nq > 0;
+      if (!cross && jb * kWave + kWave - 1 <= i) continue;  // block on or below the diagonal
       const int64_t j = jb * kWave + lane;
-      p.active = j > i && j < a.N;
+      p.active = (cross || j > i) && j < a.N;
       const int64_t jc = p.active ? j : a.N - 1;
       p.rowp = a.X + i * a.lrow;
       p.colp = a.XT + jc;
@@ -465,16 +469,18 @@ __global__ __launch_bounds__(64) void wide_kernel(WideArgs a) {
         // so far, so it is abandoned above the larger of the two (re-read
         // during the sweep; never more than the squared ED, an admissible
         // path's cost)
+        // (a reference-set column has no word: only row i's best counts)
         p.nn_i = a.nn1 + i;
-        p.nn_j = a.nn1 + jc;
+        p.nn_j = cross ? p.nn_i : a.nn1 + jc;
         p.ub = fminf(acc, fmaxf(load_bsf_dist(p.nn_i), load_bsf_dist(p.nn_j)));
       }
       const float d = wide_problem<H, KIND, BANDED>(a, p, Bw, lane, evaluated, computed);
       if (a.nn1) {
-        // both rows learn the pair: (distance, other index) packed, min-ed
+        // the row learns the pair, and within one set so does the column:
+        // (distance, other index) packed, min-ed
         const bool keep = p.active && d < kInf;
         publish_best(a.nn1 + i, keep, d, (uint32_t)j);
-        if (keep) atomicMin(a.nn1 + j, pack_best(d, (uint32_t)i));
+        if (!cross && keep) atomicMin(a.nn1 + j, pack_best(d, (uint32_t)i));
       } else if (p.active) {
         a.out[i * a.N - i * (i + 1) / 2 + (j - i - 1)] = d < kInf ? d : p.ed;
       }

@@ -29,9 +29,10 @@ __global__ __launch_bounds__(64) void nn1_seed_kernel(WideArgs a) {
   const int lane = threadIdx.x;
   for (int64_t task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
     const int64_t i = task / a.nblk_j, jb = task % a.nblk_j;
-    if (jb * kWave + kWave - 1 <= i) continue;
+    const bool cross = a.nq > 0;  // test set against a reference set: every pair
+    if (!cross && jb * kWave + kWave - 1 <= i) continue;
     const int64_t j = jb * kWave + lane;
-    const bool active = j > i && j < a.N;
+    const bool active = (cross || j > i) && j < a.N;
     const int64_t jc = active ? j : a.N - 1;
     const float *rowp = a.X + i * a.lrow;
     const float *colp = a.XT + jc;
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(64) void nn1_seed_kernel(WideArgs a) {
       acc = __builtin_fmaf(diff, diff, acc);
     }
     publish_best(a.nn1 + i, active, acc, (uint32_t)j);
-    if (active) atomicMin(a.nn1 + j, pack_best(acc, (uint32_t)i));
+    if (!cross && active) atomicMin(a.nn1 + j, pack_best(acc, (uint32_t)i));
   }
 }
 

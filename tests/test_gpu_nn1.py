@@ -64,3 +64,37 @@ def test_nn1_full_size_against_all_pairs():
     assert np.array_equal(idx, ref_j)
     _check(idx, dist, X, w, rows=[0, 777, 1999])
     assert st["cells_evaluated"] < 0.5 * sp["cells_evaluated"]
+
+
+@pytest.mark.parametrize("nq,nr,L,w", [(40, 150, 48, 5), (70, 65, 64, 63), (3, 200, 100, 20),
+                                       (64, 64, 32, 0)])
+def test_nn1_ref_vs_oracle(nq, nr, L, w):
+    g = gen.rng(4501, nq + nr + w)
+    Q = gen.as_f32(np.stack([gen.standardise(gen.random_walk(L, g)) for _ in range(nq)]))
+    R = gen.as_f32(np.stack([gen.standardise(gen.random_walk(L, g)) for _ in range(nr)]))
+    R[nr // 2] = Q[1]  # a copy of a test series: its neighbour at distance 0
+    idx, dist = eap.nn1_ref(torch.from_numpy(Q).cuda(), torch.from_numpy(R).cuda(), w)
+    assert idx[1] == nr // 2 and dist[1] == 0.0
+    oj, od = oracle.nn1_ref(gen.as_oracle(Q), gen.as_oracle(R), w)
+    for i in range(nq):
+        assert close(dist[i], od[i]), (i, dist[i], od[i])
+        if idx[i] != oj[i]:
+            at = oracle.dtw_pairs(gen.as_oracle(Q), gen.as_oracle(R), w, [i], [int(idx[i])])[0]
+            assert abs(at - od[i]) <= 1e-5 * od[i] + 1e-6, (i, idx[i], oj[i])
+
+
+def test_nn1_ref_matches_leave_one_out_split():
+    """The C3 set split into 1,500 reference and 500 test series: every test
+    series' neighbour equals the minimum of the GPU's own all-pairs distances
+    between the two parts (same kernel arithmetic: the same bits)."""
+    X, w = gen.c3()
+    Xt = torch.from_numpy(X).cuda()
+    (idx, dist), st = eap.nn1_ref(Xt[1500:], Xt[:1500], w, stats=True)
+    D = eap.pairwise(Xt, w).cpu().numpy()
+    N = X.shape[0]
+    for t in (0, 123, 499):
+        i = 1500 + t
+        ds = np.array([D[eap.pairwise_index(N, j, i)] for j in range(1500)])
+        j = int(np.argmin(ds))
+        assert idx[t] == j and np.float32(dist[t]) == ds[j], (t, idx[t], j, dist[t], ds[j])
+    assert st["problems"] == 500 * 1500
