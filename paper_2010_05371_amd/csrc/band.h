@@ -447,8 +447,8 @@ __device__ __forceinline__ uint32_t chunk_min_bits(const float (&v)[2 * R + 1]) 
 }
 
 // Borders of the last swept row.  Registers outside the swept range hold
-// values above the bound, so every chunk can be tested without a range
-// check.  Returns whether this lane still has a live cell; hi < 0 when no
+// values above the bound (or +inf, see clear_outside), so every chunk can be
+// tested without a range check.  Returns whether this lane still has a live cell; hi < 0 when no
 // lane has one.
 template <int R>
 __device__ __forceinline__ bool border_update(const float (&v)[2 * R + 1], Border &b,
@@ -465,6 +465,28 @@ __device__ __forceinline__ bool border_update(const float (&v)[2 * R + 1], Borde
   b.lo = all ? __builtin_ctz(all) : -1;
   b.hi = all ? 31 - __builtin_clz(all) : -1;
   return mask != 0u;
+}
+
+// Sets every register of the chunks outside [b.lo, b.hi] to +inf.  The
+// bordered sweep leaves those registers holding values of older rows, which
+// is harmless while the bound can only fall (they were above it when their
+// chunk was dropped); a bound that can rise from row to row (the list mode's
+// tightening) must not see them again.  Cells outside the borders lie on no
+// path that ends at or below the bound, so +inf stands in for them.
+template <int R>
+__device__ __forceinline__ void clear_outside(float (&v)[2 * R + 1], const Border &b) {
+  constexpr int W = 2 * R + 1;
+  constexpr int NCD = (W + kBorderChunk - 1) / kBorderChunk;
+  static_for<NCD>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if (c < b.lo || c > b.hi) {
+#pragma unroll
+      for (int t = 0; t < kBorderChunk; ++t) {
+        const int d = c * kBorderChunk + t;
+        if (d < W) v[d < W ? d : 0] = kInf;
+      }
+    }
+  });
 }
 
 // Cells of rows [i0, i0 + U) swept over group columns [s0, s1]: in the band,
@@ -795,6 +817,9 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
     if constexpr (BORDER) {
       alive = border_update<R>(v, bd, cell_bits(thr), alive);
       if (bd.hi < 0) stopped = true;
+      if constexpr (LIST) {
+        if (!stopped) clear_outside<R>(v, bd);
+      }
     } else {
       alive = alive && band_min<R>(v) <= thr;
       if (!wave_any(alive)) stopped = true;

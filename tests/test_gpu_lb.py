@@ -170,3 +170,23 @@ def test_nn_search_lb_nonfinite_and_errors():
     q32, x32 = _series(300, 2000, 98)
     with pytest.raises(eap.EapdtwError):  # window 100 > 64 after clamping to m - 1
         eap.nn_lower_bounds(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), 100)
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("w", [24, 40, 52, 64])
+def test_nn_dists_lb_bordered_regression(w, seed):
+    """Bordered list sweeps whose per-row bound rises from row to row: a chunk
+    dropped from the borders must not re-enter with the values of an older row
+    (they are below its cells' true values).  Tight bounds, both bound sets."""
+    m, n = 250, 3000
+    g = gen.rng(4320, seed * 100 + w)
+    x32 = gen.as_f32(gen.random_walk(n, g))
+    q32 = gen.as_f32(gen.random_walk(m, g))
+    q, x = torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda()
+    want = oracle.nn_dists(gen.as_oracle(q32), gen.as_oracle(x32), w, np.arange(n - m + 1))
+    for quant in (0.02, 0.05, 0.1):
+        ub = float(np.quantile(want, quant))
+        for ec in (0, 1):
+            a = _cpu(_with({"lb_ec": ec}, lambda: eap.nn_dists_lb(q, x, w, ub=ub)))
+            assert_bounded(a, want, np.float64(np.float32(ub)),
+                           what=f"lb regression w={w} seed={seed} q={quant} ec={ec}")
