@@ -629,6 +629,15 @@ struct KnnBufs {
   unsigned long long *buf, *n;
 };
 
+// The second stream (and its fork/join events) of the concurrent seeding.
+static hipError_t ensure_seed_stream(eapdtw_ctx *ctx) {
+  if (ctx->seed_stream) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&ctx->seed_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+  return e;
+}
+
 // The cascade serves band windows from 1 on (at window 0 LB_Keogh is the
 // squared Euclidean distance itself, which the window-0 kernel computes).
 static bool lb_applies(const eapdtw_ctx *ctx, int64_t r) { return r >= 1 && use_band(ctx, r); }
@@ -671,6 +680,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     // The band search starts from the window-0 bound and the seeding
     // workgroup runs beside it on a second stream: its bound reaches the
     // search's waves through their periodic reads of the best-so-far.
+    // (Running this pass beside the search too, so that the search's waves
+    // start at once from +inf, was slower on C2: 2.24-2.31 against 2.11-2.32
+    // ms per step.)
     const int64_t sstr = seed_stride_for(ctx->seed_stride, nblk);
     NNArgs e = a;
     e.bsf = bsf + 1;
@@ -695,11 +707,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     }
     hipStream_t ss = st;
     if (use_band(ctx, r)) {
-      if (!ctx->seed_stream) {
-        HIPCHK(hipStreamCreateWithFlags(&ctx->seed_stream, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
-      }
+      HIPCHK(ensure_seed_stream(ctx));
       HIPCHK(hipEventRecord(ctx->ev_fork, st));
       HIPCHK(hipStreamWaitEvent(ctx->seed_stream, ctx->ev_fork, 0));
       ss = ctx->seed_stream;
