@@ -371,10 +371,11 @@ int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const
  *                 n-m+1 available offsets.
  *   out_dists   : HOST [k], the distances (float32 values widened); +inf past
  *                 the available offsets.
- * Each wave appends its kept candidates to a device buffer and, when it kept
- * at least k, min-s its k-th smallest distance into the bound; a filter and a
- * one-workgroup LDS sort then select the k best.  Band windows only (window
- * after clamping to m-1 at most 64): EINVAL otherwise.  Synchronous. */
+ * Each wave appends its kept candidates to a device buffer and lowers the
+ * bound (its own k-th smallest distance when it kept at least k; the largest
+ * of k slot words that hold distances of k distinct candidates); a filter and
+ * a one-workgroup LDS sort then select the k best.  Every window (band kernels
+ * up to 64, the tiled kernel beyond).  Synchronous. */
 int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                       int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
                       double *out_dists, eapdtw_stats *stats);

@@ -827,6 +827,11 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     w.bnd_stride = (m + 1) * kWave;
     w.counters = cnt;
     w.check_interval = (int)ctx->check_interval;
+    if (kb) {
+      w.knn = kb->k;
+      w.knn_buf = kb->buf;
+      w.knn_n = kb->n;
+    }
     HIPCHK(launch_wide(kWideSearch, (int)ctx->wide_rows, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev3, st));
@@ -1269,9 +1274,9 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
   int rc = search_validate(ctx, query, m, series, n, window);
   if (rc) return rc;
   const int64_t r = window < m - 1 ? window : m - 1;
-  if (!use_band(ctx, r)) return fail(ctx, EAPDTW_EINVAL, "k nearest neighbours: window above 64");
   if (stats) std::memset(stats, 0, sizeof *stats);
   const int64_t K = n - m + 1;
+  const int64_t grid = use_band(ctx, r) ? 0 : wide_grid((K + kWave - 1) / kWave);
   Plan pl;
   const size_t o_cnt = pl.add(kCntBytes);
   const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
@@ -1279,6 +1284,7 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
   const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
   const size_t o_buf = pl.add(sizeof(unsigned long long) * K);
   const size_t o_tmp = pl.add(sizeof(unsigned long long) * K);
+  const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
@@ -1290,7 +1296,7 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
   const KnnBufs kb{(int)k, at<unsigned long long>(ctx, o_buf), cnt + kCntListN};
   if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
-                    nullptr, 0, stats != nullptr, nullptr, &kb);
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr, nullptr, &kb);
   if (rc) return rc;
   HIPCHK(launch_knn_select(kb.buf, kb.n, bsf, at<unsigned long long>(ctx, o_tmp),
                            cnt + kCntStride + kCntListN, (int)k,

@@ -573,42 +573,42 @@ __device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long v
 //    search's progress rather than waiting for one wave with k survivors.
 //    Slots store 2^32 - 1 - (distance bits), 0 meaning empty, and take
 //    atomicMax.
-__device__ __forceinline__ void publish_knn(const NNArgs &a, bool keep, float d, uint32_t id) {
+__device__ __forceinline__ void publish_knn(const KnnOut &a, bool keep, float d, uint32_t id) {
   const int lane = threadIdx.x % kWave;
   const unsigned long long mask = __builtin_amdgcn_ballot_w64(keep);
   if (!mask) return;
   const unsigned long long v = keep ? pack_best(d, id) : ~0ull;
-  if (a.knn_buf) {
+  if (a.buf) {
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(a.knn_n, (unsigned long long)__popcll(mask));
+    if (lane == 0) base = atomicAdd(a.n, (unsigned long long)__popcll(mask));
     base = __shfl(base, 0, kWave);
     if (keep) {
       const unsigned r = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      a.knn_buf[base + r] = v;
+      a.buf[base + r] = v;
     }
   }
-  if (__popcll(mask) >= a.knn) {
+  if (__popcll(mask) >= a.k) {
     const unsigned long long s = wave_sort_u64(v);
-    const unsigned long long kth = __shfl(s, a.knn - 1, kWave);
-    if (lane == 0) atomicMin(a.bsf, pack_best(best_dist(kth), 0xffffffffu));
+    const unsigned long long kth = __shfl(s, a.k - 1, kWave);
+    if (lane == 0) atomicMin(a.bound, pack_best(best_dist(kth), 0xffffffffu));
   }
   if (a.counters) {
     unsigned long long *slots = a.counters + kCntKnnSlot;
     if (keep)
-      atomicMax(&slots[(id % (uint32_t)a.knn) * kCntStride],
+      atomicMax(&slots[(id % (uint32_t)a.k) * kCntStride],
                 (unsigned long long)(0xffffffffu - __builtin_bit_cast(uint32_t, d)));
     unsigned long long sv = 1;  // lanes past k: no constraint
-    if (lane < a.knn)
+    if (lane < a.k)
       sv = __hip_atomic_load(&slots[lane * kCntStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!wave_any(sv == 0)) {
-      uint32_t bits = lane < a.knn ? 0xffffffffu - (uint32_t)sv : 0u;
+      uint32_t bits = lane < a.k ? 0xffffffffu - (uint32_t)sv : 0u;
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) {
         const uint32_t t = __shfl_xor(bits, o, kWave);
         bits = t > bits ? t : bits;
       }
-      if (lane == 0) atomicMin(a.bsf, pack_best(__builtin_bit_cast(float, bits), 0xffffffffu));
+      if (lane == 0) atomicMin(a.bound, pack_best(__builtin_bit_cast(float, bits), 0xffffffffu));
     }
   }
 }
@@ -874,7 +874,7 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   if (DISTS) {
     if (active) a.dists[k - a.k_begin] = keep ? d : kInf;
   } else if (!LIST && a.knn > 0) {
-    publish_knn(a, keep, d, (uint32_t)k);
+    publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters}, keep, d, (uint32_t)k);
   } else {
     publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }

@@ -114,6 +114,15 @@ struct NNArgs {
 // Largest k of the k-nearest-neighbour search (one wave sorts 64 candidates).
 constexpr int kKnnMax = 64;
 
+// Where a k-nearest-neighbour search publishes (see publish_knn).
+struct KnnOut {
+  unsigned long long *bound;      // upper bound of the k-th best distance (packed)
+  int k;
+  unsigned long long *buf;        // kept candidates (nullable)
+  unsigned long long *n;          // their count
+  unsigned long long *counters;   // counter array holding the k slot words (nullable)
+};
+
 // Relative margin by which float32 lower bounds are lowered before they are
 // compared with a distance: their sums round differently from the DP's.
 constexpr float kLbMargin = 1.0f / 262144.0f;  // 2^-18

@@ -55,6 +55,8 @@ struct WideArgs {
   int64_t nblk_j;                    // pairwise: column blocks per row series
   int ub_mode;                       // pairs: 0 none, 1 array, 2 ED; pairwise: ED
   unsigned long long *nn1;           // pairwise: per-series nearest neighbour words (NN1 mode)
+  int knn;                           // search: k nearest neighbours (bsf bounds the k-th best)
+  unsigned long long *knn_buf, *knn_n;
   int64_t nq;                        // pairwise: > 0 = rows are the nq series of X, columns the
                                      // N series of XT, every (row, column) pair (NN1 of a test
                                      // set against a reference set); 0 = i < j within one set
@@ -432,6 +434,8 @@ __device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task
   const bool keep = p.active && d <= p.ub && d < kInf;
   if (a.dists_mode) {
     if (p.active) a.dists[k - a.k_begin] = d;
+  } else if (a.knn > 0) {
+    publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters}, keep, d, (uint32_t)k);
   } else {
     publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }

@@ -34,10 +34,11 @@ def _check(res, q32, x32, w, k):
             assert abs(at[i] - wd) <= 1e-5 * wd + 1e-6, (i, o, wo, at[i], wd)
 
 
-# (m, window, n, k): window 0, narrow and bordered windows, k = 1 and 64,
-# ragged row groups
+# (m, window, n, k): window 0, narrow and bordered windows, windows past 64
+# (tiled kernel, banded and whole-query), k = 1 and 64, ragged row groups
 CASES = [(64, 0, 3000, 5), (128, 13, 20_000, 10), (96, 30, 8000, 64), (37, 6, 5000, 1),
-         (200, 52, 12_000, 16), (150, 64, 6000, 33)]
+         (200, 52, 12_000, 16), (150, 64, 6000, 33), (150, 100, 6000, 12), (90, 89, 4000, 64),
+         (300, 65, 5000, 7)]
 
 
 @pytest.mark.parametrize("m,w,n,k", CASES)
@@ -88,5 +89,3 @@ def test_knn_fewer_offsets_than_k_and_errors():
     for bad_k in (0, 65):
         with pytest.raises(eap.EapdtwError):
             eap.knn_search(q, x, 10, bad_k)
-    with pytest.raises(eap.EapdtwError):  # window above 64
-        eap.knn_search(q, x, 100, 4)
