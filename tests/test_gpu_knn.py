@@ -89,3 +89,23 @@ def test_knn_fewer_offsets_than_k_and_errors():
     for bad_k in (0, 65):
         with pytest.raises(eap.EapdtwError):
             eap.knn_search(q, x, 10, bad_k)
+
+
+def test_knn_many_ties_multi_tile_selection():
+    """A long periodic series: 6,000 windows per phase tie bit for bit, so
+    the words at or below the final bound span several 4,096-word sort tiles
+    and the k best must be carried from tile to tile (smaller offsets first
+    among the equal distances)."""
+    pattern = gen.random_walk(20, gen.rng(4405))
+    x32 = gen.as_f32(np.tile(pattern, 6000))
+    q32 = gen.as_f32(np.asarray(x32[3:3 + 40], dtype=np.float64)
+                     + 0.05 * gen.rng(4406).standard_normal(40))
+    for w, k in ((0, 64), (4, 17), (6, 1)):
+        res = eap.knn_search(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), w, k)
+        offs = [o for o, _ in res]
+        ds = [d for _, d in res]
+        # the best phase repeats every 20 points: offsets 3, 23, 43, ... all at one distance
+        assert offs == [3 + 20 * j for j in range(k)], (w, offs[:5])
+        assert len(set(ds)) == 1
+        qo, xo = gen.as_oracle(q32), gen.as_oracle(x32)
+        assert close(ds[0], oracle.nn_dists(qo, xo, w, [3])[0])
