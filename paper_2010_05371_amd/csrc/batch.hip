@@ -119,7 +119,9 @@ __global__ __launch_bounds__(64) void batch_main_kernel(BatchArgs a) {
       w.k_end = bq.K;
       w.check_interval = a.check_interval;
       const int64_t task = unit - bq.unit_begin;
-      if (2 * w.r + 2 >= kWideBandRows)
+      if (2 * w.r + 2 >= kWideBandRowsTall)
+        wide_search_task<kWideBandRowsTall, true>(w, task, Bw, lane, evaluated, computed, abandoned);
+      else if (2 * w.r + 2 >= kWideBandRows)
         wide_search_task<kWideBandRows, true>(w, task, Bw, lane, evaluated, computed, abandoned);
       else if (2 * w.r + 2 >= 4)
         wide_search_task<4, true>(w, task, Bw, lane, evaluated, computed, abandoned);

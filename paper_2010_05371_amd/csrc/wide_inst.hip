@@ -57,6 +57,7 @@ int wide_rows_for(int r, int lrow, int lcol) {
   if (r >= lmax - 1) return kWideFullRows;
   // a banded tile of H rows needs 2r + 2 >= H (its entering and exiting
   // triangles must not overlap)
+  if (2 * r + 2 >= kWideBandRowsTall) return kWideBandRowsTall;
   if (2 * r + 2 >= kWideBandRows) return kWideBandRows;
   if (2 * r + 2 >= 4) return 4;
   return 2;
@@ -71,6 +72,7 @@ hipError_t launch_wide(int kind, int rows, const WideArgs &a, int grid, hipStrea
       // whole-matrix windows: 32- or 64-row tiles (rows option, default 64)
       if (rows == 32) return launch_wide_h<32, false>(kind, a, grid, st);
       return launch_wide_h<64, false>(kind, a, grid, st);
+    case kWideBandRowsTall: return launch_wide_h<kWideBandRowsTall, true>(kind, a, grid, st);
     case kWideBandRows: return launch_wide_h<kWideBandRows, true>(kind, a, grid, st);
     case 4: return launch_wide_h<4, true>(kind, a, grid, st);
     default: return launch_wide_h<2, true>(kind, a, grid, st);
