@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "NN-search candidates/s + effective DTW GCUPS (1 MI355X); fwd+bwd pairs/s"
+PEAK_HBM = 8.0e12  # bytes/s, MI355X HBM3E
 PEAK_FP32_VALU = 157.3e12        # FLOP/s, MI355X vector FP32 (256 CUs x 2.4 GHz x 256)
 OPS_PER_CELL = 5                 # sub, mul, add, two 2-input mins
 BORDER_MIN_WINDOW = 24           # windows served by the bordered band kernel
@@ -214,7 +215,11 @@ def main():
                      "ops_per_cell": OPS_PER_CELL,
                      "cells_computed_per_launch": dw["cells_computed"],
                      "cells_per_launch": dw["cells_evaluated"],
-                     "launch_ms": dw["main_kernel_ms"]},
+                     "launch_ms": dw["main_kernel_ms"],
+                     # HBM bandwidth of the same launch (measured bytes / event time)
+                     # against the 8 TB/s peak: the path is not bandwidth-bound
+                     "hbm_gbs": (traffic / (dw["main_kernel_ms"] / 1e3) / 1e9) if traffic else None,
+                     "hbm_frac": (traffic / (dw["main_kernel_ms"] / 1e3) / PEAK_HBM) if traffic else None},
     }
     if args.lb_steps > 0:
         line["lb_cascade"] = lb_cascade(eap, q, x, windows, K, args.lb_steps, rec)
