@@ -221,9 +221,13 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
  *   border         : bordered band sweep on/off (windows >= 24)
  *   check_interval : row groups between best-so-far reads (0 = automatic)
  *   wide_rows      : tile height of the whole-window tiled kernel (0, 32, 64)
+ *   lanes          : band windows: 0 = 64 candidates per wave in lockstep row
+ *                    groups, 1 = each lane streams its own candidates (option
+ *                    "lanes"; single searches only, the batch ignores it)
  *   ms             : measured time of the sample search with these choices */
 typedef struct {
   int64_t rows_per_group, border, check_interval, wide_rows;
+  int64_t lanes;
   float ms;
 } eapdtw_tune;
 

@@ -52,7 +52,7 @@ class Result(ctypes.Structure):
 class Tune(ctypes.Structure):
     _fields_ = [("rows_per_group", ctypes.c_int64), ("border", ctypes.c_int64),
                 ("check_interval", ctypes.c_int64), ("wide_rows", ctypes.c_int64),
-                ("ms", ctypes.c_float)]
+                ("lanes", ctypes.c_int64), ("ms", ctypes.c_float)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -859,15 +859,16 @@ namespace {
 // the previous ones afterwards.
 struct KnobGuard {
   eapdtw_ctx *ctx;
-  int64_t rows, border, ci, wide;
+  int64_t rows, border, ci, wide, lanes;
   explicit KnobGuard(eapdtw_ctx *c)
       : ctx(c), rows(c->rows_per_group), border(c->border), ci(c->check_interval),
-        wide(c->wide_rows) {}
+        wide(c->wide_rows), lanes(c->lanes) {}
   void apply(const eapdtw_tune &t) {
     ctx->rows_per_group = t.rows_per_group;
     ctx->border = t.border;
     ctx->check_interval = t.check_interval;
     ctx->wide_rows = t.wide_rows;
+    ctx->lanes = t.lanes;
   }
   void apply_cached(int64_t m, int64_t window) {
     if (!ctx->autotune) return;
@@ -879,6 +880,7 @@ struct KnobGuard {
     ctx->border = border;
     ctx->check_interval = ci;
     ctx->wide_rows = wide;
+    ctx->lanes = lanes;
   }
 };
 
@@ -1460,7 +1462,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   // per-query choices for the band launches: the tuned ones of the query's
   // bucket when autotuning, else the context's
   std::vector<eapdtw_tune> knob(nq, eapdtw_tune{ctx->rows_per_group, ctx->border,
-                                                ctx->check_interval, ctx->wide_rows, 0.f});
+                                                ctx->check_interval, ctx->wide_rows, 0, 0.f});
   if (ctx->autotune) {
     for (int64_t i = 0; i < nq; ++i) {
       auto it = ctx->tune.find(eapdtw_tune_bucket(qs[order[i]].m, qs[order[i]].window));
@@ -1576,18 +1578,20 @@ int eapdtw_autotune(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
   if (use_band(ctx, r)) {
     for (int64_t ci : cis) {
       if (r >= kBorderMinR) {
-        for (int64_t b : {1, 0}) cand.push_back({0, b, ci, 0, 0.f});
+        for (int64_t b : {1, 0}) cand.push_back({0, b, ci, 0, 0, 0.f});
       } else {
-        for (int64_t u : {4, 2, 8}) cand.push_back({u, 1, ci, 0, 0.f});
+        for (int64_t u : {4, 2, 8}) cand.push_back({u, 1, ci, 0, 0, 0.f});
       }
+      // the other mapping of lanes to candidates: each lane streams its own
+      if (lane_search_supported((int)r, (int)m)) cand.push_back({0, 1, ci, 0, 1, 0.f});
     }
   } else {
     const bool full = m > 1 && r >= m - 1;
     for (int64_t ci : cis) {
       if (full) {
-        for (int64_t h : {64, 32}) cand.push_back({0, 1, ci, h, 0.f});
+        for (int64_t h : {64, 32}) cand.push_back({0, 1, ci, h, 0, 0.f});
       } else {
-        cand.push_back({0, 1, ci, 0, 0.f});
+        cand.push_back({0, 1, ci, 0, 0, 0.f});
       }
     }
   }
@@ -1635,10 +1639,10 @@ int eapdtw_tune_save(const eapdtw_ctx *ctx, const char *path) {
     const eapdtw_tune &t = kv.second;
     std::fprintf(f,
                  "%s\n  {\"bucket\": %lld, \"rows_per_group\": %lld, \"border\": %lld, "
-                 "\"check_interval\": %lld, \"wide_rows\": %lld, \"ms\": %.6g}",
+                 "\"check_interval\": %lld, \"wide_rows\": %lld, \"lanes\": %lld, \"ms\": %.6g}",
                  first ? "" : ",", (long long)kv.first, (long long)t.rows_per_group,
                  (long long)t.border, (long long)t.check_interval, (long long)t.wide_rows,
-                 (double)t.ms);
+                 (long long)t.lanes, (double)t.ms);
     first = false;
   }
   std::fprintf(f, "\n]}\n");
@@ -1661,17 +1665,23 @@ int eapdtw_tune_load(eapdtw_ctx *ctx, const char *path) {
   std::map<int64_t, eapdtw_tune> add;
   size_t pos = 0;
   while ((pos = text.find("{\"bucket\"", pos)) != std::string::npos) {
-    long long b, u, bo, ci, w;
+    long long b, u, bo, ci, w, ln = 0;
     double ms;
+    // entries written before the lanes choice existed have no "lanes" field
     if (std::sscanf(text.c_str() + pos,
+                    "{\"bucket\": %lld, \"rows_per_group\": %lld, \"border\": %lld, "
+                    "\"check_interval\": %lld, \"wide_rows\": %lld, \"lanes\": %lld, \"ms\": %lf}",
+                    &b, &u, &bo, &ci, &w, &ln, &ms) != 7 &&
+        std::sscanf(text.c_str() + pos,
                     "{\"bucket\": %lld, \"rows_per_group\": %lld, \"border\": %lld, "
                     "\"check_interval\": %lld, \"wide_rows\": %lld, \"ms\": %lf}",
                     &b, &u, &bo, &ci, &w, &ms) != 6)
       return fail(ctx, EAPDTW_EINVAL, "malformed tuning entry");
     const bool ok = b >= 0 && (u == 0 || u == 2 || u == 4 || u == 8) && (bo == 0 || bo == 1) &&
-                    ci >= 0 && ci <= (1 << 20) && (w == 0 || w == 32 || w == 64);
+                    ci >= 0 && ci <= (1 << 20) && (w == 0 || w == 32 || w == 64) &&
+                    (ln == 0 || ln == 1);
     if (!ok) return fail(ctx, EAPDTW_EINVAL, "tuning entry out of range");
-    add[b] = eapdtw_tune{u, bo, ci, w, (float)ms};
+    add[b] = eapdtw_tune{u, bo, ci, w, ln, (float)ms};
     ++pos;
   }
   for (const auto &kv : add) ctx->tune[kv.first] = kv.second;

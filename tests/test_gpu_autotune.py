@@ -31,6 +31,7 @@ def test_autotune_choice_and_same_results(m, w, autotune_on):
     t = eap.autotune(q, x, w, sample_n=30_000)
     assert t["ms"] > 0 and t["rows_per_group"] in (0, 2, 4, 8) and t["border"] in (0, 1)
     assert t["check_interval"] in (0, 1, 4) and t["wide_rows"] in (0, 32, 64)
+    assert t["lanes"] in (0, 1) and (t["lanes"] == 0 or (m % 4 == 0 and 1 <= min(w, m - 1) <= 64))
     assert eap.tune_get(m, w) == t
     eap.set_option("autotune", 1)
     assert eap.nn_search(q, x, w) == plain
@@ -69,6 +70,11 @@ def test_tune_save_load_round_trip(tmp_path, autotune_on):
     assert any(e["bucket"] == eap.tune_bucket(100, 10) for e in d["entries"])
     eap.tune_load(p)
     assert eap.tune_get(100, 10) == pytest.approx(t)
+    # an entry written without the lanes field still loads (lanes 0)
+    old = tmp_path / "old.json"
+    old.write_text('{"arch": "gfx950", "entries": [\n  {"bucket": 7, "rows_per_group": 4, '
+                   '"border": 1, "check_interval": 0, "wide_rows": 0, "ms": 1.5}\n]}\n')
+    eap.tune_load(old)
     bad = tmp_path / "bad.json"
     bad.write_text('{"arch": "gfx942", "entries": []}')
     with pytest.raises(eap.EapdtwError):
