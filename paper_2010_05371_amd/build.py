@@ -28,16 +28,23 @@ BAND_RANGES = [(0, 7), (8, 13), (14, 18), (19, 23), (24, 27), (28, 31), (32, 35)
                (40, 43), (44, 47), (48, 51), (52, 55), (56, 58), (59, 61), (62, 64)]
 
 
+# translation units that compile longest, started first so that the pool of
+# compilers does not end waiting on one of them
+SLOW_FIRST = ("wide_inst.hip", "batch.hip", "lanes.hip", "bwd.hip")
+
+
 def _units():
-    units = []
-    for lo, hi in BAND_RANGES:
+    others = [src for src in sorted(os.listdir(CSRC))
+              if src != "band_inst.hip" and (src.endswith(".hip") or src.endswith(".cpp"))]
+    others.sort(key=lambda src: (src not in SLOW_FIRST,
+                                 SLOW_FIRST.index(src) if src in SLOW_FIRST else 0))
+    units = [(src, os.path.splitext(src)[0] + ".o", []) for src in others
+             if src in SLOW_FIRST]
+    for lo, hi in BAND_RANGES[::-1]:  # the widest windows compile longest
         units.append(("band_inst.hip", f"band_r{lo:02d}_{hi:02d}.o",
                       [f"-DEAPDTW_R_LO={lo}", f"-DEAPDTW_R_HI={hi}"]))
-    for src in sorted(os.listdir(CSRC)):
-        if src == "band_inst.hip":
-            continue
-        if src.endswith(".hip") or src.endswith(".cpp"):
-            units.append((src, os.path.splitext(src)[0] + ".o", []))
+    units += [(src, os.path.splitext(src)[0] + ".o", []) for src in others
+              if src not in SLOW_FIRST]
     return units
 
 
