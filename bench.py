@@ -114,6 +114,27 @@ def lb_cascade(eap, q, x, windows, K, steps, plain_rec):
             "per_window": out}
 
 
+def batched(eap, q, x, windows, K, steps, plain_rec):
+    """The same four searches as one batched call (reported beside the plain
+    search, outside its timed steps): the band-window launches run on
+    concurrent streams, so one launch's late waves overlap the next ones."""
+    import time as _t
+
+    import torch
+
+    qs = [(q, w) for w in windows]
+    res = eap.nn_search_batch(qs, x)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(steps):
+        res = eap.nn_search_batch(qs, x)
+    torch.cuda.synchronize()
+    ms = (_t.perf_counter() - t0) * 1e3 / steps
+    same = all(tuple(r) == (plain_rec[w][-1][0], plain_rec[w][-1][1]) for r, w in zip(res, windows))
+    return {"candidates_per_s": K * len(windows) / (ms / 1e3), "ms_per_step": round(ms, 4),
+            "same_as_plain": same, "streams": eap.get_option("batch_branches")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +146,9 @@ def main():
     ap.add_argument("--lb-steps", type=int, default=5,
                     help="repetitions of the lower-bound cascade searches reported beside "
                          "the plain ones (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="repetitions of the four searches as one batched call reported "
+                         "beside the plain ones (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-mebibyte buffer once (a plain copy of known size "
                          "that calibrates HBM byte counters in a profiler run)")
@@ -223,6 +247,8 @@ def main():
     }
     if args.lb_steps > 0:
         line["lb_cascade"] = lb_cascade(eap, q, x, windows, K, args.lb_steps, rec)
+    if args.batch_steps > 0:
+        line["batched"] = batched(eap, q, x, windows, K, args.batch_steps, rec)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(q32, x32, windows, args.cpu_budget)
     else:

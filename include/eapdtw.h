@@ -111,6 +111,9 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *   "batch_grid"     : persistent workgroups of the batched search
  *   "batch_chunk"    : work units taken per queue access in the batched search
  *   "batch_seed_stride": seed_stride of the batched search
+ *   "batch_branches" : streams over which the batched search spreads its
+ *                      band-window launches, which then run concurrently
+ *                      (1-8, default 4; 1 = one after the other)
  *   "wide_rows"      : rows per tile of the whole-matrix-window kernel (32, 64; 0=auto)
  *   "graph"          : 1 = replay batched searches from a captured hipGraph
  *   "force_wide"     : 1 = use the wide-window kernel even for narrow windows

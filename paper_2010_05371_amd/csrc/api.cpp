@@ -54,6 +54,7 @@ struct eapdtw_ctx {
   int64_t batch_grid = 2048;
   int64_t batch_chunk = 4;
   int64_t batch_seed_stride = 0;
+  int64_t batch_branches = 4;  // streams the batched search's band launches spread over
   // batched search: dedicated device buffer and the captured graph
   char *batch_buf = nullptr;
   size_t batch_cap = 0;
@@ -63,6 +64,12 @@ struct eapdtw_ctx {
   // second stream on which the seeding workgroup runs beside the search
   hipStream_t seed_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // side streams of the batched search's concurrent band launches, with the
+  // fork event and one join event each
+  static constexpr int kMaxBranches = 8;
+  hipStream_t branch[kMaxBranches] = {};
+  hipEvent_t ev_bfork = nullptr;
+  hipEvent_t ev_bjoin[kMaxBranches] = {};
 };
 
 static thread_local std::string g_create_error;
@@ -286,6 +293,14 @@ void eapdtw_destroy(eapdtw_ctx *ctx) {
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  for (int b = 0; b < eapdtw_ctx::kMaxBranches; ++b) {
+    if (ctx->branch[b]) {
+      if (!ctx->poisoned) (void)hipStreamSynchronize(ctx->branch[b]);
+      (void)hipStreamDestroy(ctx->branch[b]);
+    }
+    if (ctx->ev_bjoin[b]) (void)hipEventDestroy(ctx->ev_bjoin[b]);
+  }
+  if (ctx->ev_bfork) (void)hipEventDestroy(ctx->ev_bfork);
   delete ctx;
 }
 
@@ -316,6 +331,7 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "batch_grid")) return &ctx->batch_grid;
   if (!strcmp(key, "batch_chunk")) return &ctx->batch_chunk;
   if (!strcmp(key, "batch_seed_stride")) return &ctx->batch_seed_stride;
+  if (!strcmp(key, "batch_branches")) return &ctx->batch_branches;
   if (!strcmp(key, "border")) return &ctx->border;
   if (!strcmp(key, "ed")) return &ctx->ed;
   if (!strcmp(key, "autotune")) return &ctx->autotune;
@@ -343,6 +359,7 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   else if (!strcmp(key, "batch_grid")) ok = value >= 64 && value <= 65536;
   else if (!strcmp(key, "batch_chunk")) ok = value >= 1 && value <= 1024;
   else if (!strcmp(key, "batch_seed_stride")) ok = value >= 0 && value <= (1 << 20);
+  else if (!strcmp(key, "batch_branches")) ok = value >= 1 && value <= eapdtw_ctx::kMaxBranches;
   if (!ok) return fail(ctx, EAPDTW_EINVAL, std::string("bad value for option ") + key);
   *slot = value;
   return EAPDTW_OK;
@@ -1329,8 +1346,9 @@ static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
   return h;
 }
 
-// Queues the whole batched search on the context stream (used directly, or
-// once under stream capture to build the graph).
+// Queues the whole batched search on stream st, forking side streams from it
+// and joining them back (used directly, or once under stream capture to build
+// the graph).
 // Queries with band windows (the descriptors from nband_first on) each get
 // one launch of their band (or window-0) kernel after the batched seeding;
 // the others share the persistent tiled launch.
@@ -1341,7 +1359,36 @@ static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid,
   HIPCHK(launch_batch_prep(ba, st));
   HIPCHK(launch_check_finite(ba.x, ba.n, ba.counters, st));
   if (ctx->seed) HIPCHK(launch_batch_seed(ba, st));
+  // Band-window queries are independent searches (own best-so-far word; the
+  // shared counters are atomics): they go round-robin, most expensive first,
+  // onto up to batch_branches streams forked from st, so that one launch's
+  // tail of late waves overlaps the next launches.  st itself takes the
+  // persistent tiled launch, or the first branch when there is none.
+  const int64_t nband = (int64_t)desc.size() - nband_first;
+  const bool own_main = ba.total_units > 0;
+  // band-launch branches on side streams (st takes one more when it has no
+  // tiled launch of its own)
+  const int nside = (int)std::max<int64_t>(
+      0, own_main ? std::min<int64_t>(ctx->batch_branches - 1, nband)
+                  : std::min<int64_t>(ctx->batch_branches, nband) - 1);
+  if (nside > 0) {
+    if (!ctx->ev_bfork) HIPCHK(hipEventCreateWithFlags(&ctx->ev_bfork, hipEventDisableTiming));
+    for (int b = 0; b < nside; ++b) {
+      if (!ctx->branch[b]) HIPCHK(hipStreamCreateWithFlags(&ctx->branch[b], hipStreamNonBlocking));
+      if (!ctx->ev_bjoin[b]) HIPCHK(hipEventCreateWithFlags(&ctx->ev_bjoin[b], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(ctx->ev_bfork, st));
+    for (int b = 0; b < nside; ++b) HIPCHK(hipStreamWaitEvent(ctx->branch[b], ctx->ev_bfork, 0));
+  }
+  // branch j of the band launches: side stream j (or j - 1 after st's own
+  // first branch when there is no tiled launch)
+  auto branch_stream = [&](int64_t j) -> hipStream_t {
+    if (own_main) return ctx->branch[j % nside];
+    const int64_t b = j % (nside + 1);
+    return b == 0 ? st : ctx->branch[b - 1];
+  };
   for (int64_t i = nband_first; i < (int64_t)desc.size(); ++i) {
+    const hipStream_t bs = nside > 0 ? branch_stream(i - nband_first) : st;
     const BatchQuery &d = desc[i];
     NNArgs a{};
     a.x = ba.x;
@@ -1359,11 +1406,15 @@ static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid,
     a.check_interval = (int)t.check_interval;
     const int rows = t.rows_per_group ? (int)t.rows_per_group : pick_rows(ctx, d.r);
     if (d.r == 0 && ctx->ed)
-      HIPCHK(launch_ed_search(a, nblk, false, st));
+      HIPCHK(launch_ed_search(a, nblk, false, bs));
     else
-      HIPCHK(nn_band_launcher(d.r)(a, nblk, rows, false, t.border != 0, st));
+      HIPCHK(nn_band_launcher(d.r)(a, nblk, rows, false, t.border != 0, bs));
   }
   if (ba.total_units > 0) HIPCHK(launch_batch_main(ba, grid, st));
+  for (int b = 0; b < nside; ++b) {
+    HIPCHK(hipEventRecord(ctx->ev_bjoin[b], ctx->branch[b]));
+    HIPCHK(hipStreamWaitEvent(st, ctx->ev_bjoin[b], 0));
+  }
   return EAPDTW_OK;
 }
 
@@ -1496,6 +1547,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   key = fnv1a(key, &ctx->ed, sizeof ctx->ed);
   key = fnv1a(key, &ctx->rows_per_group, sizeof ctx->rows_per_group);
   key = fnv1a(key, &ctx->force_wide, sizeof ctx->force_wide);
+  key = fnv1a(key, &ctx->batch_branches, sizeof ctx->batch_branches);
   for (const eapdtw_tune &t : knob) {
     const int64_t f[4] = {t.rows_per_group, t.border, t.check_interval, t.wide_rows};
     key = fnv1a(key, f, sizeof f);

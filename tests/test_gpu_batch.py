@@ -80,13 +80,44 @@ def test_batch_knobs_do_not_change_results():
     qt = [(torch.from_numpy(q).cuda(), w) for q, w in qs]
     base = eap.nn_search_batch(qt, xt)
     for key, val in (("batch_chunk", 1), ("batch_grid", 64), ("check_interval", 7), ("seed", 0),
-                     ("batch_seed_stride", 1)):
+                     ("batch_seed_stride", 1), ("batch_branches", 1), ("batch_branches", 8)):
         old = eap.get_option(key)
         eap.set_option(key, val)
         try:
             assert eap.nn_search_batch(qt, xt) == base, key
         finally:
             eap.set_option(key, old)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_band_launch_branches(graph):
+    """Band-window queries spread over 1-8 concurrent streams, with and
+    without tiled-window queries beside them, in a graph or eagerly: the same
+    answers as one search per query."""
+    g = gen.rng(1006)
+    x32 = gen.as_f32(gen.random_walk(60_000, g))
+    q = gen.as_f32(gen.random_walk(128, g))
+    wide = gen.as_f32(gen.random_walk(300, g))
+    xt = torch.from_numpy(x32).cuda()
+    qt = torch.from_numpy(q).cuda()
+    band_only = [(qt, w) for w in (0, 13, 26, 52, 5)]
+    mixed = band_only + [(torch.from_numpy(wide).cuda(), 120)]
+    want = {id(b): [eap.nn_search(t, xt, w) for t, w in b] for b in (band_only, mixed)}
+    old_g, old_b = eap.get_option("graph"), eap.get_option("batch_branches")
+    eap.set_option("graph", graph)
+    try:
+        for nb in (1, 2, 3, 4, 8):
+            eap.set_option("batch_branches", nb)
+            for b in (band_only, mixed):
+                for _ in range(2):
+                    assert eap.nn_search_batch(b, xt) == want[id(b)], (nb, len(b))
+    finally:
+        eap.set_option("graph", old_g)
+        eap.set_option("batch_branches", old_b)
+    with pytest.raises(eap.EapdtwError):
+        eap.set_option("batch_branches", 0)
+    with pytest.raises(eap.EapdtwError):
+        eap.set_option("batch_branches", 9)
 
 
 def test_batch_stats_and_validation():
