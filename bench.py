@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="repetitions of the four searches as one batched call reported "
                          "beside the plain ones (0 = skip)")
+    ap.add_argument("--batch-streams", type=int, default=0,
+                    help="streams of the batched call's band launches (0 = the library's "
+                         "default)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-mebibyte buffer once (a plain copy of known size "
                          "that calibrates HBM byte counters in a profiler run)")
@@ -248,6 +251,8 @@ def main():
     if args.lb_steps > 0:
         line["lb_cascade"] = lb_cascade(eap, q, x, windows, K, args.lb_steps, rec)
     if args.batch_steps > 0:
+        if args.batch_streams > 0:
+            eap.set_option("batch_branches", args.batch_streams)
         line["batched"] = batched(eap, q, x, windows, K, args.batch_steps, rec)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(q32, x32, windows, args.cpu_budget)

@@ -1361,8 +1361,9 @@ static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid,
   if (ctx->seed) HIPCHK(launch_batch_seed(ba, st));
   // Band-window queries are independent searches (own best-so-far word; the
   // shared counters are atomics): they go round-robin, most expensive first,
-  // onto up to batch_branches streams forked from st, so that one launch's
-  // tail of late waves overlaps the next launches.  st itself takes the
+  // onto up to batch_branches streams forked from st.  The launches then run
+  // side by side, and the CUs that one launch's late waves (the candidates
+  // abandoned last) leave idle take the others' waves.  st itself takes the
   // persistent tiled launch, or the first branch when there is none.
   const int64_t nband = (int64_t)desc.size() - nband_first;
   const bool own_main = ba.total_units > 0;
