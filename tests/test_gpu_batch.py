@@ -114,6 +114,13 @@ def test_band_launch_branches(graph):
     finally:
         eap.set_option("graph", old_g)
         eap.set_option("batch_branches", old_b)
+    # on a caller's stream other than the default one (forked from and joined
+    # back to it); the answers are read after that stream alone is synchronised
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for b in (band_only, mixed):
+            assert eap.nn_search_batch(b, xt) == want[id(b)], len(b)
+    side.synchronize()
     with pytest.raises(eap.EapdtwError):
         eap.set_option("batch_branches", 0)
     with pytest.raises(eap.EapdtwError):
