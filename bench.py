@@ -10,7 +10,9 @@ best-so-far.  Inputs are resident in HBM before the timed region.
 Prints ONE JSON line (rank 0): candidates/s over the step, effective and
 nominal cells/s, pruned fraction, the VALU roofline of the dominant kernel
 (5 float32 operations per evaluated cell against the 157.3 TFLOP/s vector
-peak) and the FP64 CPU oracle timed on a bounded sample on this host.
+peak) and the FP64 CPU oracle timed on a bounded sample on this host; beside
+the timed steps, the same searches with the lower-bound cascade
+(`lb_cascade`) and as one batched call (`batched`).
 """
 from __future__ import annotations
 
@@ -116,8 +118,9 @@ def lb_cascade(eap, q, x, windows, K, steps, plain_rec):
 
 def batched(eap, q, x, windows, K, steps, plain_rec):
     """The same four searches as one batched call (reported beside the plain
-    search, outside its timed steps): the band-window launches run on
-    concurrent streams, so one launch's late waves overlap the next ones."""
+    search, outside its timed steps): the band-window launches run side by
+    side on concurrent streams, and the CUs one launch's late waves leave idle
+    take the others' waves."""
     import time as _t
 
     import torch
