@@ -273,9 +273,119 @@ def test_path_is_valid_and_optimal():
             assert (i0 - i1, j0 - j1) in ((1, 1), (1, 0), (0, 1))
             assert abs(i1 - j1) <= r
         assert _path_cost(S, T, path) == pytest.approx(d, rel=1e-13)
-    # tie-break order on the worked example: every step prefers diagonal, then top
-    _, _, _, path, _ = oracle.dtw_grad(S_EX, T_EX, None)
-    assert _path_cost(S_EX, T_EX, path) == GOLD["dtw"]
+
+
+# Path ties (Section 2: several optimal warping paths may exist).  The oracle
+# takes, at every backtrack step, the diagonal predecessor, then (i-1, j), then
+# (i, j-1) among those holding the minimum.  Among all optimal paths this is
+# the one whose step sequence, read from (lS, lT) backwards with the order
+# diagonal < top < left, is lexicographically smallest -- a definition the
+# tests below evaluate by enumerating every warping path, without the DP
+# matrix.
+
+_STEP = {(1, 1): 0, (1, 0): 1, (0, 1): 2}  # diagonal, top (i-1, j), left (i, j-1)
+
+
+def _all_paths(l1, l2, r):
+    out = []
+
+    def rec(i, j, acc):
+        if abs(i - j) > r:
+            return
+        acc.append((i, j))
+        if (i, j) == (l1, l2):
+            out.append(list(acc))
+        else:
+            if i < l1 and j < l2:
+                rec(i + 1, j + 1, acc)
+            if i < l1:
+                rec(i + 1, j, acc)
+            if j < l2:
+                rec(i, j + 1, acc)
+        acc.pop()
+
+    rec(1, 1, [])
+    return out
+
+
+def _backward_steps(path_from_start):
+    rev = path_from_start[::-1]
+    return [_STEP[(a[0] - b[0], a[1] - b[1])] for a, b in zip(rev, rev[1:])]
+
+
+def _enumerated_choice(S, T, r, rank=(0, 1, 2)):
+    """The optimal path (from the end back to (1,1)) that a backtrack preferring
+    the steps in `rank` order takes, found by enumeration (exact: integer data)."""
+    paths = _all_paths(len(S), len(T), r)
+    cost = [sum((S[i - 1] - T[j - 1]) ** 2 for i, j in p) for p in paths]
+    best = min(cost)
+    opt = [p for p, c in zip(paths, cost) if c == best]
+    pick = min(opt, key=lambda p: [rank[c] for c in _backward_steps(p)])
+    return pick[::-1], best, len(opt)
+
+
+def _grad_of_path(S, T, path):
+    dS, dT = np.zeros(len(S)), np.zeros(len(T))
+    for i, j in path:
+        dS[i - 1] += 2 * (S[i - 1] - T[j - 1])
+        dT[j - 1] -= 2 * (S[i - 1] - T[j - 1])
+    return dS, dT
+
+
+def test_worked_example_path_and_gradient():
+    """The worked example's optimal path has a diagonal/left tie at (6,6); the
+    path and gradient were derived by hand from the printed matrix."""
+    d, dS, dT, path, _ = oracle.dtw_grad(S_EX, T_EX, None)
+    assert d == GOLD["dtw"]
+    assert path == [tuple(c) for c in GOLD["path_diag_top_left"]]
+    assert dS.tolist() == GOLD["grad_S"] and dT.tolist() == GOLD["grad_T"]
+
+
+def test_hand_worked_tie_case():
+    case = GOLD["tie_case"]
+    S, T = np.array(case["S"], float), np.array(case["T"], float)
+    M = oracle.dtw_matrix(S, T)
+    assert M[1:, 1:].tolist() == case["matrix"]
+    d, dS, dT, path, gap = oracle.dtw_grad(S, T, None)
+    assert d == case["dtw"] and gap == 0.0
+    assert path == [tuple(c) for c in case["path_diag_top_left"]]
+    assert dS.tolist() == case["grad_S"] and dT.tolist() == case["grad_T"]
+
+
+def test_tie_order_against_enumeration():
+    """On small integer cases the oracle's path is the enumerated choice, and the
+    cases include every kind of tie on the chosen path where another order
+    would choose a different path, so a changed tie order fails here."""
+    g = np.random.default_rng(2010)
+    seen = set()
+    other_orders = [(2, 1, 0), (1, 0, 2), (0, 2, 1), (2, 0, 1), (1, 2, 0)]
+    decisive = {o: 0 for o in other_orders}
+    for _ in range(700):
+        L1, L2 = int(g.integers(1, 6)), int(g.integers(1, 6))
+        r = int(g.integers(abs(L1 - L2), max(L1, L2) + 1))
+        S = g.integers(0, 4, L1).astype(float)
+        T = g.integers(0, 4, L2).astype(float)
+        want, best, nopt = _enumerated_choice(S, T, r)
+        d, dS, dT, path, _ = oracle.dtw_grad(S, T, r)
+        assert d == best
+        assert path == want, (S, T, r)
+        wS, wT = _grad_of_path(S, T, want)
+        assert dS.tolist() == wS.tolist() and dT.tolist() == wT.tolist()
+        if nopt < 2:
+            continue
+        M = oracle.dtw_matrix(S, T, r)
+        for i, j in want[:-1]:
+            pred = (M[i - 1, j - 1], M[i - 1, j], M[i, j - 1])
+            tie = tuple(v == min(pred) for v in pred)
+            if sum(tie) > 1:
+                seen.add(tie)
+        for o in other_orders:
+            if _enumerated_choice(S, T, r, o)[0] != want:
+                decisive[o] += 1
+    # diagonal/top, diagonal/left, top/left and three-way ties all occur
+    assert {(True, True, False), (True, False, True), (False, True, True),
+            (True, True, True)} <= seen, seen
+    assert all(v > 0 for v in decisive.values()), decisive
 
 
 def test_grad_central_finite_differences():
