@@ -653,12 +653,15 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   } else {
     int64_t kbeg = a.k_begin, kend = a.k_end;
     if (a.center) {
-      // seed launch: 64 offsets centred on the best offset of an earlier pass
+      // seed launch: the 64 offsets of the block holding the best offset of an
+      // earlier pass
       const unsigned long long c = *a.center;
       int64_t ck = (int64_t)best_offset(c);
       if (ck > kend - 1) ck = kend - 1;
-      int64_t lo = ck - 32;
-      if (lo < kbeg) lo = kbeg;
+      // the 64-offset block of the search that holds ck: its window statistics
+      // (pivot, summation order) and so its z-values are the search's bit for bit
+      if (ck < kbeg) ck = kbeg;
+      const int64_t lo = kbeg + ((ck - kbeg) & ~(int64_t)(kWave - 1));
       if (lo + 64 < kend) kend = lo + 64;
       kbeg = lo;
       if (a.bsf_init && lane == 0) atomicMin(a.bsf, pack_best(best_dist(*a.bsf_init), 0xffffffffu));

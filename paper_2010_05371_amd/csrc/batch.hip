@@ -64,7 +64,7 @@ __global__ __launch_bounds__(64) void batch_seed0_kernel(BatchArgs a) {
   nn_band_body<0, 8, false>(n, blockIdx.x - bq.seed_begin);
 }
 
-// One workgroup per query: 64 offsets around the window-0 best, window
+// One workgroup per query: the 64-offset block holding the window-0 best, window
 // min(r, seed_window); records a distance-only bound.
 template <int RS>
 __device__ __forceinline__ void batch_seed_rs(const NNArgs &n) {

@@ -87,7 +87,7 @@ struct NNArgs {
   const float *qpad;                 // z(query) with kColPad +inf on each side
   unsigned long long *bsf;           // shared best-so-far (packed)
   int64_t k_begin, k_end;            // candidate offsets [k_begin, k_end)
-  const unsigned long long *center;  // optional: restrict to 64 offsets around center's offset
+  const unsigned long long *center;  // optional: restrict to the 64-offset block holding center's offset
   const unsigned long long *bsf_init;// optional: start from this word's distance as the bound
                                      // (with center: also min it into bsf first)
   float fixed_ub;                    // per-candidate-distance mode: fixed bound

@@ -24,8 +24,10 @@ __global__ __launch_bounds__(64) void ed_search_kernel(NNArgs a) {
     const unsigned long long c = *a.center;
     int64_t ck = (int64_t)best_offset(c);
     if (ck > kend - 1) ck = kend - 1;
-    int64_t lo = ck - 32;
-    if (lo < kbeg) lo = kbeg;
+    // the 64-offset block of the search that holds ck: its window statistics
+    // (pivot, summation order) and so its z-values are the search's bit for bit
+    if (ck < kbeg) ck = kbeg;
+    const int64_t lo = kbeg + ((ck - kbeg) & ~(int64_t)(kWave - 1));
     if (lo + 64 < kend) kend = lo + 64;
     kbeg = lo;
     if (a.bsf_init && lane == 0) atomicMin(a.bsf, pack_best(best_dist(*a.bsf_init), 0xffffffffu));

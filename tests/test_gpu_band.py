@@ -222,3 +222,29 @@ def test_nn_search_rejects_bad_input():
     with pytest.raises(eap.EapdtwError) as e:
         eap.nn_search(torch.arange(10, dtype=torch.float32), bad, 2)
     assert "ENONFINITE" in str(e.value)
+
+
+def test_seeded_search_keeps_the_true_minimum():
+    """The seeding workgroup normalises its candidates with the search's own
+    64-offset block statistics, so its bound never falls below the search's
+    own distance of the best candidate: with seeding on, every search returns
+    a valid offset and the same answer, bit for bit, as without seeding (small
+    windows, where the seeding window equals the search window)."""
+    g = np.random.default_rng(2024)
+    cases = []
+    for _ in range(60):
+        m = int(g.integers(8, 80))
+        n = int(g.integers(m + 1, 3000))
+        w = int(g.integers(0, 9))
+        x32 = gen.as_f32(np.cumsum(g.standard_normal(n)) * float(g.uniform(0.1, 100)))
+        q32 = gen.as_f32(np.cumsum(g.standard_normal(m)))
+        cases.append((torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), w))
+    try:
+        eap.set_option("seed", 0)
+        plain = [eap.nn_search(q, x, w) for q, x, w in cases]
+        eap.set_option("seed", 1)
+        seeded = [eap.nn_search(q, x, w) for q, x, w in cases]
+    finally:
+        eap.set_option("seed", 1)
+    for (q, x, w), p, s in zip(cases, plain, seeded):
+        assert s[0] >= 0 and s == p, (q.numel(), x.numel(), w, p, s)
