@@ -256,29 +256,111 @@ int eapdtw_tune_save(const eapdtw_ctx *ctx, const char *path);
 int eapdtw_tune_load(eapdtw_ctx *ctx, const char *path);
 
 /* ---------------------------------------------------------------------------
- * Forward of the differentiable batch (Section 2: DTW value; the gradient
- * follows the optimal warping path).  Plain DTW (no bound) of pairs
- * (S[p], T[p]) of equal length, storing the band state every few rows into
- * `ckpt` so that the backward can recompute the matrix tile by tile.
- *   S, T [npairs][len]: DEVICE float32.   out_dist [npairs]: DEVICE float32.
- *   ckpt : DEVICE scratch of eapdtw_dtw_ckpt_bytes(npairs, len, window) bytes,
- *          owned by the caller, consumed by eapdtw_dtw_bwd.
- * Asynchronous. */
+ * Differentiable batch of equal-length pairs (Section 2: DTW is the cost of an
+ * optimal warping path; its gradient is the gradient of that path's cost,
+ * dD/dS(i) = 2 sum_j (S(i)-T(j)), dD/dT(j) = -2 sum_i (S(i)-T(j)) over the
+ * path cells).  Each pair is swept by 16 or 64 SIMD lanes along the
+ * anti-diagonals of its band, one matrix row per lane; no bound, plain DTW.
+ *   S, T [npairs][len] : DEVICE float32, row-major.
+ *   window             : r >= 0 (clipped to len - 1).  Supported: len <= 8191
+ *                        and min(window + 1, len) <= 511 (rows active at
+ *                        once); otherwise EINVAL.
+ *
+ * eapdtw_dtw_ckpt_bytes: size of the direction record of such a batch: two
+ *   bits per swept cell (which predecessor gave the minimum; ties: the
+ *   diagonal, then (i-1,j), then (i,j-1)) plus a status word per pair.  The
+ *   len x len matrix is never stored.  -1 for unsupported sizes.
+ * eapdtw_dtw_fwd: out_dist [npairs] DEVICE.  ckpt: DEVICE buffer of
+ *   eapdtw_dtw_ckpt_bytes bytes that receives the direction record (consumed
+ *   by eapdtw_dtw_bwd), or NULL for the distances alone (the backward then
+ *   sweeps the forward again).  A pair with a non-finite value gets NaN.
+ *   Asynchronous.
+ * eapdtw_dtw_bwd: follows each pair's record from (len,len) back to (1,1)
+ *   (ckpt = the forward's record, or NULL: the forward is swept again with a
+ *   record in the context's scratch) and writes
+ *   grad_S[p][i] = 2 g sum over the path cells (i,j) of (S(i)-T(j)),
+ *   grad_T[p][j] = -2 g sum over the path cells (i,j) of (S(i)-T(j)),
+ *   g = grad_out[p]; a pair with a non-finite value gets NaN gradients.
+ *   grad_out [npairs], grad_S, grad_T [npairs][len]: DEVICE float32
+ *   (overwritten).  Asynchronous. */
 int64_t eapdtw_dtw_ckpt_bytes(int64_t npairs, int64_t len, int64_t window);
 int eapdtw_dtw_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
                    int64_t window, float *out_dist, void *ckpt);
-
-/* Backward: recomputes the forward from `ckpt` in tiles, backtracks the
- * optimal path (ties: diagonal, then (i-1,j), then (i,j-1)) and scatters
- * dD/dS(i) = sum_j 2(S(i)-T(j)) g and dD/dT(j) = -sum_i 2(S(i)-T(j)) g over the
- * path cells, g = grad_out[p].  A pair with infinite distance gets zero
- * gradients.
- *   grad_out [npairs], grad_S, grad_T [npairs][len]: DEVICE float32
- *   (grad_S/grad_T are overwritten).
- * Asynchronous. */
 int eapdtw_dtw_bwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
                    int64_t window, const void *ckpt, const float *grad_out, float *grad_S,
                    float *grad_T);
+
+/* The optimal warping path of each pair of an equal-length batch, as the
+ * backward follows it (Section 2; ties as above), and the distances.
+ *   out_dist [npairs] : DEVICE float32 (may be NULL).
+ *   rowrng, colrng [npairs][len] : DEVICE uint32.  rowrng[p][i] =
+ *     jlo | jhi << 16: the path cells of row i (0-based) are the columns
+ *     jlo..jhi; colrng[p][j] = ilo | ihi << 16 likewise for column j.  A path
+ *     is monotone, so these ranges describe it completely.  Pairs with a
+ *     non-finite value are left untouched.
+ * Asynchronous. */
+int eapdtw_dtw_path(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
+                    int64_t window, float *out_dist, unsigned *rowrng, unsigned *colrng);
+
+/* ---------------------------------------------------------------------------
+ * Batches of pairs of uneven length and window (Section 2, Eq. 1-5 for
+ * lS != lT; Section 2.1 window per pair).  Series live in two DEVICE pools:
+ * pair p is S[s_off .. s_off + s_len) against T[t_off .. t_off + t_len) under
+ * window r_p (clipped to max(s_len, t_len) - 1; |s_len - t_len| > r_p has no
+ * warping path: +inf).  Pairs are grouped by the lanes they need (16 or 64 per
+ * pair) and run longest first, one launch per group.  Supported: lengths up
+ * to 8191 and min(r_p + 1, s_len, t_len) <= 511; otherwise EINVAL.  Both
+ * series empty: 0; one empty: +inf (Eq. 2-4).
+ *   pairs [npairs] : HOST array (copied before the call returns). */
+typedef struct {
+  int64_t s_off, s_len;
+  int64_t t_off, t_len;
+  int64_t window;
+} eapdtw_pair;
+
+/* Distances with an optional early-abandoning bound (Section 2.2): ub [npairs]
+ * DEVICE float32 or NULL; a distance strictly above its bound is +inf, and a
+ * pair stops as soon as every cell of two consecutive anti-diagonals exceeds
+ * its bound (every warping path crosses one of them).  A pair with a
+ * non-finite value gets NaN.  out [npairs]: DEVICE.  Asynchronous unless
+ * stats are requested. */
+int eapdtw_dtw_pairs_batch(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                           int64_t t_total, const eapdtw_pair *pairs, int64_t npairs,
+                           const float *ub, float *out, eapdtw_stats *stats);
+
+/* Differentiable form (as eapdtw_dtw_fwd / eapdtw_dtw_bwd): the record size
+ * (-1 when unsupported), the forward (record may be NULL) and the backward
+ * into pool-shaped gradients grad_S [s_total], grad_T [t_total] (elements
+ * outside every pair are not written).  The backward needs pairs whose S
+ * regions do not overlap, nor their T regions (EINVAL otherwise); it must get
+ * the same pairs as the forward that wrote the record. */
+int64_t eapdtw_dtw_batch_record_bytes(const eapdtw_pair *pairs, int64_t npairs);
+int eapdtw_dtw_batch_fwd(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                         int64_t t_total, const eapdtw_pair *pairs, int64_t npairs, float *out,
+                         void *record);
+int eapdtw_dtw_batch_bwd(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                         int64_t t_total, const eapdtw_pair *pairs, int64_t npairs,
+                         const void *record, const float *grad_out, float *grad_S,
+                         float *grad_T);
+/* Path ranges of each pair, pool-shaped: rowrng [s_total], colrng [t_total]
+ * DEVICE uint32 (as eapdtw_dtw_path; disjoint pairs).  Asynchronous. */
+int eapdtw_dtw_batch_path(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                          int64_t t_total, const eapdtw_pair *pairs, int64_t npairs,
+                          unsigned *rowrng, unsigned *colrng);
+
+/* ---------------------------------------------------------------------------
+ * One DTW barycentre averaging (DBA) update (the barycentre use of the path
+ * named in Section 6's outlook; Petitjean, Ketterlin & Gancarski, 2011): with
+ * the optimal warping path of every pair (B, X[p]) under the window (Section
+ * 2; ties as above), each point i of B becomes the mean of the values X[p][j]
+ * its paths align with it.
+ *   B [lb], X [n][len] : DEVICE float32.
+ *   out_B [lb]         : DEVICE float32, sum / count (sums in float64).
+ *   out_count [lb]     : DEVICE float32 or NULL, the number of aligned values.
+ * |lb - len| beyond the window, empty inputs or unsupported sizes (as the
+ * differentiable batch): EINVAL.  Asynchronous. */
+int eapdtw_dba_step(eapdtw_ctx *ctx, const float *B, int64_t lb, const float *X, int64_t n,
+                    int64_t len, int64_t window, float *out_B, float *out_count);
 
 /* ---------------------------------------------------------------------------
  * Exposed steps of the search, for tests.

@@ -17,6 +17,12 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
   lexicographic minimum of (distance, offset);
 * ``dtw_grad``    -- optimal warping path (Section 2) and the gradient of the
   path cost with respect to both series;
+* ``path_cost``, ``path_grad``, ``is_warping_path`` -- the cost of a given
+  warping path, its gradient, and the definition of a warping path (Section 2;
+  used to check a GPU path on its own terms);
+* ``dba_step``, ``dba_of_paths`` -- one DTW barycentre averaging update (each
+  barycentre point becomes the mean of the values the optimal paths align with
+  it), the barycentre use of the path;
 * ``eap_model``   -- a model of Algorithm 3 (Section 4), kept only to check the
   threshold contract and the worked example (never a reference value);
 * ``envelope``, ``lb_kim``, ``lb_keogh``, ``nn_lower_bounds`` -- the lower
@@ -191,6 +197,65 @@ def dtw_grad(S, T, window: int | None, gout: float = 1.0):
         raise MemoryError("oracle_dtw_grad")
     path = list(zip(pi[:n].tolist(), pj[:n].tolist()))
     return float(dist[0]), dS, dT, path, float(gap[0])
+
+
+def path_cost(S, T, path) -> float:
+    """Cost of a warping path (Section 2): the sum of (S(i) - T(j))^2 over its
+    cells, path given as 1-based (i, j) pairs in any order."""
+    S, T = _f64(S), _f64(T)
+    return float(sum((S[i - 1] - T[j - 1]) ** 2 for i, j in path))
+
+
+def path_grad(S, T, path, gout: float = 1.0):
+    """Gradient of a path's cost: dS(i) = 2 g sum (S(i) - T(j)), dT(j) = -2 g
+    sum (S(i) - T(j)) over the path cells (1-based (i, j))."""
+    S, T = _f64(S), _f64(T)
+    dS, dT = np.zeros(S.size), np.zeros(T.size)
+    for i, j in path:
+        d = 2.0 * (S[i - 1] - T[j - 1]) * gout
+        dS[i - 1] += d
+        dT[j - 1] -= d
+    return dS, dT
+
+
+def is_warping_path(path, lS: int, lT: int, window: int | None) -> bool:
+    """Section 2: a warping path runs from (1,1) to (lS,lT) in steps (1,0),
+    (0,1), (1,1); with a window (Section 2.1) every cell has |i - j| <= r.
+    path: 1-based cells in order from (1,1)."""
+    r = max(lS, lT) if window is None else int(window)
+    if not path or tuple(path[0]) != (1, 1) or tuple(path[-1]) != (lS, lT):
+        return False
+    for (i0, j0), (i1, j1) in zip(path, path[1:]):
+        if (i1 - i0, j1 - j0) not in ((1, 0), (0, 1), (1, 1)):
+            return False
+    return all(abs(i - j) <= r for i, j in path)
+
+
+def dba_of_paths(lb: int, X, paths) -> np.ndarray:
+    """DBA average for given paths: point i of the barycentre becomes the mean
+    of the values X[p][j] over the cells (i, j) of path p (1-based cells)."""
+    X = [np.asarray(x, dtype=np.float64) for x in X]
+    s, c = np.zeros(lb), np.zeros(lb)
+    for x, path in zip(X, paths):
+        for i, j in path:
+            s[i - 1] += x[j - 1]
+            c[i - 1] += 1.0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return s / c
+
+
+def dba_step(B, X, window: int | None):
+    """One DTW barycentre averaging update (Petitjean et al. 2011): the optimal
+    path of every pair (B, X[p]) under the window (the backtrack of dtw_grad,
+    ties diagonal, then (i-1, j), then (i, j-1)), then dba_of_paths.  Returns
+    (new barycentre, counts)."""
+    B = _f64(B)
+    paths = [dtw_grad(B, x, window)[3] for x in X]
+    c = np.zeros(B.size)
+    for path in paths:
+        for i, _ in path:
+            c[i - 1] += 1.0
+    return dba_of_paths(B.size, X, paths), c
 
 
 def nn_dists(query, series, window: int, offsets, nthreads: int | None = None) -> np.ndarray:

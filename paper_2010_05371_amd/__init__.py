@@ -16,6 +16,11 @@ Functions (names follow the C ABI):
 * ``nn_dists(query, series, window, ub)``  -- per-candidate bounded distances
 * ``window_stats(series, m)``, ``znorm(x)`` -- exposed steps of the search
 * ``DTWFunction.apply(S, T, window)``      -- differentiable batch (autograd)
+* ``dtw_path(S, T, window)``               -- the optimal path ranges the backward follows
+* ``dtw_pairs_batch(S_list, T_list, windows, ub=None)`` -- uneven pairs in pools
+* ``DTWBatchFunction.apply(S_pool, T_pool, pairs, ...)`` -- differentiable uneven batch
+* ``dtw_batch_path(...)``                  -- path ranges of an uneven batch
+* ``dba_step(B, X, window)``               -- one DTW barycentre averaging update
 * ``window_from_ratio(ratio, m)``          -- integer window, rounded up
 * ``autotune(query, series, window)``, ``tune_get``, ``tune_save``,
   ``tune_load``                            -- the kernel-choice tuning cache
@@ -29,14 +34,15 @@ import threading
 import torch
 
 from . import _lib
-from ._lib import EapdtwError, LbStats, Query, Result, Stats, Tune
+from ._lib import EapdtwError, LbStats, Pair, Query, Result, Stats, Tune
 
 __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_dists",
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
            "nn_lower_bounds", "LbStats", "knn_search", "nn1", "nn_search_w", "nn_dists_w",
-           "nn1_ref"]
+           "nn1_ref", "dtw_path", "dtw_pairs_batch", "pack_pairs", "DTWBatchFunction",
+           "dtw_batch_path", "dba_step", "unpack_ranges"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -419,4 +425,100 @@ def znorm(x):
     return out
 
 
-from .autograd import DTWFunction  # noqa: E402
+def unpack_ranges(rng: torch.Tensor):
+    """(lo, hi) int64 tensors of packed path ranges (lo | hi << 16)."""
+    r = rng.to(torch.int64) & 0xFFFFFFFF
+    return r & 0xFFFF, r >> 16
+
+
+def dtw_path(S, T, window: int):
+    """(distances, rowrng, colrng) of equal-length pairs S, T [npairs, len]:
+    the optimal warping path the backward follows, as packed ranges per row
+    (columns jlo..jhi) and per column (rows ilo..ihi); see unpack_ranges."""
+    S, T = _dev(S), _dev(T)
+    if S.shape != T.shape or S.dim() != 2:
+        raise ValueError("S and T must both be [npairs, len]")
+    ctx = context(S.device.index)
+    ctx.bind_stream()
+    P, L = S.shape
+    dist = torch.empty(P, device=S.device, dtype=torch.float32)
+    rr = torch.zeros((P, L), device=S.device, dtype=torch.int32)
+    cr = torch.zeros((P, L), device=S.device, dtype=torch.int32)
+    ctx.check(ctx._lib.eapdtw_dtw_path(ctx.handle, _ptr(S), _ptr(T), P, L, int(window), _ptr(dist),
+                                       _ptr(rr), _ptr(cr)))
+    return dist, rr, cr
+
+
+def pack_pairs(S_list, T_list, windows, device=None):
+    """Pools and descriptors of an uneven batch: S_list / T_list are sequences
+    of 1-D series, windows an int or a sequence.  Returns (S_pool, T_pool,
+    pairs), pairs a ctypes array of Pair (host)."""
+    n = len(S_list)
+    if len(T_list) != n:
+        raise ValueError("S_list and T_list differ in length")
+    if isinstance(windows, int):
+        windows = [windows] * n
+    Ss = [_dev(x, device).reshape(-1) for x in S_list]
+    Ts = [_dev(x, device).reshape(-1) for x in T_list]
+    dev = Ss[0].device if n else torch.device("cuda", torch.cuda.current_device())
+    S_pool = torch.cat(Ss) if n else torch.empty(0, device=dev)
+    T_pool = torch.cat(Ts) if n else torch.empty(0, device=dev)
+    pairs = (Pair * max(n, 1))()
+    so = to = 0
+    for p in range(n):
+        pairs[p].s_off, pairs[p].s_len = so, Ss[p].numel()
+        pairs[p].t_off, pairs[p].t_len = to, Ts[p].numel()
+        pairs[p].window = int(windows[p])
+        so += Ss[p].numel()
+        to += Ts[p].numel()
+    return S_pool, T_pool, pairs
+
+
+def dtw_pairs_batch(S_list, T_list, windows, ub=None, stats: bool = False):
+    """DTW of pairs of uneven length and window (one launch per lane class);
+    ub: None or a per-pair bound (a distance strictly above it is +inf)."""
+    S_pool, T_pool, pairs = pack_pairs(S_list, T_list, windows)
+    n = len(S_list)
+    ctx = context(S_pool.device.index)
+    ctx.bind_stream()
+    out = torch.empty(n, device=S_pool.device, dtype=torch.float32)
+    ubt = None if ub is None else _dev(ub, S_pool.device.index)
+    if ubt is not None and ubt.numel() != n:
+        raise ValueError("ub must have one entry per pair")
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_dtw_pairs_batch(
+        ctx.handle, _ptr(S_pool), S_pool.numel(), _ptr(T_pool), T_pool.numel(), pairs, n,
+        _ptr(ubt) if ubt is not None else None, _ptr(out), ctypes.byref(st) if stats else None))
+    return (out, st.as_dict()) if stats else out
+
+
+def dtw_batch_path(S_pool, T_pool, pairs, n: int):
+    """(rowrng [len(S_pool)], colrng [len(T_pool)]) path ranges of an uneven
+    batch (disjoint pairs), pool-shaped; see unpack_ranges."""
+    S_pool, T_pool = _dev(S_pool), _dev(T_pool)
+    ctx = context(S_pool.device.index)
+    ctx.bind_stream()
+    rr = torch.zeros(S_pool.numel(), device=S_pool.device, dtype=torch.int32)
+    cr = torch.zeros(T_pool.numel(), device=S_pool.device, dtype=torch.int32)
+    ctx.check(ctx._lib.eapdtw_dtw_batch_path(ctx.handle, _ptr(S_pool), S_pool.numel(),
+                                             _ptr(T_pool), T_pool.numel(), pairs, int(n),
+                                             _ptr(rr), _ptr(cr)))
+    return rr, cr
+
+
+def dba_step(B, X, window: int, counts: bool = False):
+    """One DBA update of barycentre B [lb] against the series X [n, len]."""
+    B, X = _dev(B).reshape(-1), _dev(X)
+    if X.dim() != 2:
+        raise ValueError("X must be [n, len]")
+    ctx = context(B.device.index)
+    ctx.bind_stream()
+    out = torch.empty_like(B)
+    cnt = torch.empty_like(B) if counts else None
+    ctx.check(ctx._lib.eapdtw_dba_step(ctx.handle, _ptr(B), B.numel(), _ptr(X), X.shape[0],
+                                       X.shape[1], int(window), _ptr(out),
+                                       _ptr(cnt) if cnt is not None else None))
+    return (out, cnt) if counts else out
+
+
+from .autograd import DTWBatchFunction, DTWFunction  # noqa: E402

@@ -49,6 +49,12 @@ class Result(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_int64), ("dist", ctypes.c_double)]
 
 
+class Pair(ctypes.Structure):
+    """One pair of an uneven batch (eapdtw_pair)."""
+    _fields_ = [("s_off", ctypes.c_int64), ("s_len", ctypes.c_int64), ("t_off", ctypes.c_int64),
+                ("t_len", ctypes.c_int64), ("window", ctypes.c_int64)]
+
+
 class Tune(ctypes.Structure):
     _fields_ = [("rows_per_group", ctypes.c_int64), ("border", ctypes.c_int64),
                 ("check_interval", ctypes.c_int64), ("wide_rows", ctypes.c_int64),
@@ -93,6 +99,15 @@ def load():
         "eapdtw_dtw_ckpt_bytes": ([i64, i64, i64], i64),
         "eapdtw_dtw_fwd": ([vp, vp, vp, i64, i64, i64, vp, vp], i32),
         "eapdtw_dtw_bwd": ([vp, vp, vp, i64, i64, i64, vp, vp, vp, vp], i32),
+        "eapdtw_dtw_path": ([vp, vp, vp, i64, i64, i64, vp, vp, vp], i32),
+        "eapdtw_dtw_pairs_batch": ([vp, vp, i64, vp, i64, ctypes.POINTER(Pair), i64, vp, vp, sp],
+                                   i32),
+        "eapdtw_dtw_batch_record_bytes": ([ctypes.POINTER(Pair), i64], i64),
+        "eapdtw_dtw_batch_fwd": ([vp, vp, i64, vp, i64, ctypes.POINTER(Pair), i64, vp, vp], i32),
+        "eapdtw_dtw_batch_bwd": ([vp, vp, i64, vp, i64, ctypes.POINTER(Pair), i64, vp, vp, vp, vp],
+                                 i32),
+        "eapdtw_dtw_batch_path": ([vp, vp, i64, vp, i64, ctypes.POINTER(Pair), i64, vp, vp], i32),
+        "eapdtw_dba_step": ([vp, vp, i64, vp, i64, i64, i64, vp, vp], i32),
         "eapdtw_window_stats": ([vp, vp, i64, i64, vp, vp], i32),
         "eapdtw_znorm": ([vp, vp, i64, vp], i32),
         "eapdtw_nn_dists": ([vp, vp, i64, vp, i64, i64, f32, vp, sp], i32),

@@ -30,7 +30,7 @@ BAND_RANGES = [(0, 7), (8, 13), (14, 18), (19, 23), (24, 27), (28, 31), (32, 35)
 
 # translation units that compile longest, started first so that the pool of
 # compilers does not end waiting on one of them
-SLOW_FIRST = ("wide_inst.hip", "batch.hip", "lanes.hip", "bwd.hip")
+SLOW_FIRST = ("wide_inst.hip", "wf.hip", "batch.hip", "lanes.hip")
 
 
 def _units():

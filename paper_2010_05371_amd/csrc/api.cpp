@@ -12,7 +12,7 @@
 #include "../../include/eapdtw.h"
 #include "dispatch.h"
 #include "wide.h"
-#include "bwd.h"
+#include "wf.h"
 #include "batch.h"
 
 #include <algorithm>
@@ -690,10 +690,14 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     // its DTW under the search window (fewer admissible paths), so
     //  1. the window-0 (squared Euclidean) pass over every seed_stride-th
     //     block of candidates yields a valid distance bound and an offset;
-    //  2. one workgroup of candidates around that offset, under window
-    //     min(r, seed_window), tightens it.
+    //  2. one workgroup over the search's 64-offset block holding that
+    //     offset, under window min(r, seed_window), tightens it.
     // Both record distance-only bounds; the search itself then finds the
-    // exact minimum and its offset (the true minimum is never abandoned).
+    // exact minimum and its offset.  The true minimum is never abandoned:
+    // the seeding workgroup normalises its candidates with the search's own
+    // block statistics (the same float32 z-values), and float32 addition is
+    // monotone, so its distance for any candidate is never below the
+    // search's distance for that candidate.
     // The band search starts from the window-0 bound and the seeding
     // workgroup runs beside it on a second stream: its bound reaches the
     // search's waves through their periodic reads of the best-so-far.
@@ -1741,72 +1745,542 @@ int eapdtw_tune_load(eapdtw_ctx *ctx, const char *path) {
   return EAPDTW_OK;
 }
 
-// --------------------------------------------------------------------------- differentiable batch
+// --------------------------------------------------------------------------- wavefront pair batches
+
+// Host view of one pair of a wavefront batch (window already clipped).
+struct WfHostPair {
+  int64_t s_off, t_off, ls, lt, r;
+};
+
+static int64_t clip_window(int64_t window, int64_t ls, int64_t lt) {
+  const int64_t lmax = ls > lt ? ls : lt;
+  return lmax > 0 && window > lmax - 1 ? lmax - 1 : window;
+}
+
+// Validates a host array of eapdtw_pair against the pools and clips the
+// windows.  `disjoint`: the pairs' S regions must not overlap, nor their T
+// regions (their gradients and path ranges are written in place).
+static int wf_validate(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                       int64_t t_total, const eapdtw_pair *pairs, int64_t npairs, bool disjoint,
+                       std::vector<WfHostPair> &hp) {
+  if (npairs < 0 || s_total < 0 || t_total < 0) return fail(ctx, EAPDTW_EINVAL, "negative size");
+  if (npairs > 0 && !pairs) return fail(ctx, EAPDTW_EINVAL, "pairs is NULL");
+  if ((s_total > 0 && !S) || (t_total > 0 && !T)) return fail(ctx, EAPDTW_EINVAL, "NULL pool");
+  if (npairs > INT_MAX) return fail(ctx, EAPDTW_EINVAL, "too many pairs");
+  hp.resize((size_t)npairs);
+  for (int64_t p = 0; p < npairs; ++p) {
+    const eapdtw_pair &q = pairs[p];
+    if (q.s_len < 0 || q.t_len < 0 || q.window < 0 || q.s_off < 0 || q.t_off < 0)
+      return fail(ctx, EAPDTW_EINVAL, "pair " + std::to_string(p) + ": negative field");
+    if (q.s_len > kWfMaxLen || q.t_len > kWfMaxLen)
+      return fail(ctx, EAPDTW_EINVAL, "pair " + std::to_string(p) + ": series longer than 8191");
+    if (q.s_off > s_total - q.s_len || q.t_off > t_total - q.t_len)
+      return fail(ctx, EAPDTW_EINVAL, "pair " + std::to_string(p) + ": outside its pool");
+    const int64_t r = clip_window(q.window, q.s_len, q.t_len);
+    if (q.s_len > 0 && q.t_len > 0 && wf_class_for((int)q.s_len, (int)q.t_len, (int)r) < 0)
+      return fail(ctx, EAPDTW_EINVAL,
+                  "pair " + std::to_string(p) + ": more than 511 rows active at once");
+    hp[(size_t)p] = WfHostPair{q.s_off, q.t_off, q.s_len, q.t_len, r};
+  }
+  if (disjoint) {
+    for (int side = 0; side < 2; ++side) {
+      std::vector<std::pair<int64_t, int64_t>> iv;
+      iv.reserve(hp.size());
+      for (const auto &h : hp) {
+        const int64_t o = side ? h.t_off : h.s_off, l = side ? h.lt : h.ls;
+        if (l > 0) iv.emplace_back(o, o + l);
+      }
+      std::sort(iv.begin(), iv.end());
+      for (size_t k = 1; k < iv.size(); ++k)
+        if (iv[k].first < iv[k - 1].second)
+          return fail(ctx, EAPDTW_EINVAL, side ? "pairs overlap in T" : "pairs overlap in S");
+    }
+  }
+  return EAPDTW_OK;
+}
+
+static int wf_class_of(const WfHostPair &h) {
+  if (h.ls == 0 || h.lt == 0) return 0;
+  return wf_class_for((int)h.ls, (int)h.lt, (int)h.r);
+}
+
+// Per-pair device descriptors, record offsets and per-class launch orders
+// (most steps first) of a batch.
+struct WfBatchPlan {
+  std::vector<WfPair> desc;
+  std::vector<int32_t> order;        // pairs grouped by class
+  int64_t begin[kWfClasses + 1] = {};
+  int lds_stride[kWfClasses] = {};
+  int max_chunks[kWfClasses] = {};  // record chunks of the class's longest pair
+  int max_ranges[kWfClasses] = {};  // ls + lt of the class's longest pair
+  int64_t rec_words = 0;
+  uint64_t band_cells = 0;
+};
+
+static void wf_plan(const std::vector<WfHostPair> &hp, WfBatchPlan &pl) {
+  const int64_t n = (int64_t)hp.size();
+  pl.desc.resize((size_t)n);
+  std::vector<int> cls((size_t)n);
+  int64_t cnt[kWfClasses] = {};
+  for (int64_t p = 0; p < n; ++p) {
+    const WfHostPair &h = hp[(size_t)p];
+    const int c = wf_class_of(h);
+    cls[(size_t)p] = c;
+    ++cnt[c];
+    WfPair &d = pl.desc[(size_t)p];
+    d.s_off = h.s_off;
+    d.t_off = h.t_off;
+    d.rec_off = pl.rec_words;
+    d.ls = (int32_t)h.ls;
+    d.lt = (int32_t)h.lt;
+    d.r = (int32_t)h.r;
+    d.pad = 0;
+    pl.rec_words += wf_rec_words((int)h.ls, (int)h.lt, c);
+    const int need = (int)(h.ls + h.lt + 2 * kWfPad);
+    if (need > pl.lds_stride[c]) pl.lds_stride[c] = need;
+    const int nch = wf_chunks((int)h.ls, (int)h.lt);
+    if (nch > pl.max_chunks[c]) pl.max_chunks[c] = nch;
+    if (h.ls + h.lt > pl.max_ranges[c]) pl.max_ranges[c] = (int)(h.ls + h.lt);
+    if (h.ls > 0 && h.lt > 0 && std::llabs(h.ls - h.lt) <= h.r)
+      pl.band_cells += (uint64_t)band_cells_total(h.ls, h.lt, h.r);
+  }
+  for (int c = 0; c < kWfClasses; ++c) pl.begin[c + 1] = pl.begin[c] + cnt[c];
+  pl.order.resize((size_t)n);
+  std::vector<int64_t> fill(pl.begin, pl.begin + kWfClasses);
+  std::vector<int32_t> idx((size_t)n);
+  for (int64_t p = 0; p < n; ++p) idx[(size_t)p] = (int32_t)p;
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+    return hp[(size_t)x].ls + hp[(size_t)x].lt > hp[(size_t)y].ls + hp[(size_t)y].lt;
+  });
+  for (int32_t p : idx) pl.order[(size_t)fill[cls[(size_t)p]]++] = p;
+}
+
+// Forward launches of a planned batch: one per class present.
+static int wf_launch_batch(eapdtw_ctx *ctx, const float *S, const float *T, const WfBatchPlan &pl,
+                           const WfPair *d_desc, const int32_t *d_order, float *out,
+                           unsigned *rec, const float *ub, unsigned long long *cnt) {
+  for (int c = 0; c < kWfClasses; ++c) {
+    const int64_t n = pl.begin[c + 1] - pl.begin[c];
+    if (n == 0) continue;
+    WfArgs a{};
+    a.S = S;
+    a.T = T;
+    a.pairs = d_desc;
+    a.order = d_order + pl.begin[c];
+    a.nitems = n;
+    a.out = out;
+    a.rec = rec;
+    a.lds_stride = pl.lds_stride[c];
+    a.ub = ub;
+    a.counters = cnt;
+    HIPCHK(launch_wf_fwd(c, rec != nullptr, a, ctx->stream));
+  }
+  return EAPDTW_OK;
+}
+
+// Uploads a host array into the scratch at `off` (stream-ordered; the host
+// array may be reused once this returns).
+static int upload(eapdtw_ctx *ctx, size_t off, const void *src, size_t nbytes) {
+  if (nbytes == 0) return EAPDTW_OK;
+  HIPCHK(hipMemcpyAsync(ctx->scratch + off, src, nbytes, hipMemcpyHostToDevice, ctx->stream));
+  return EAPDTW_OK;
+}
+
+int eapdtw_dtw_pairs_batch(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                           int64_t t_total, const eapdtw_pair *pairs, int64_t npairs,
+                           const float *ub, float *out, eapdtw_stats *stats) {
+  CHECK_CTX();
+  std::vector<WfHostPair> hp;
+  int rc = wf_validate(ctx, S, s_total, T, t_total, pairs, npairs, false, hp);
+  if (rc) return rc;
+  if (npairs > 0 && !out) return fail(ctx, EAPDTW_EINVAL, "out is NULL");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (npairs == 0) return EAPDTW_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  WfBatchPlan pl;
+  wf_plan(hp, pl);
+  Plan sp;
+  const size_t o_cnt = sp.add(kCntBytes);
+  const size_t o_desc = sp.add(sizeof(WfPair) * pl.desc.size());
+  const size_t o_ord = sp.add(sizeof(int32_t) * pl.order.size());
+  rc = ensure_scratch(ctx, sp.off);
+  if (rc) return rc;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, ctx->stream));
+  if ((rc = upload(ctx, o_desc, pl.desc.data(), sizeof(WfPair) * pl.desc.size()))) return rc;
+  if ((rc = upload(ctx, o_ord, pl.order.data(), sizeof(int32_t) * pl.order.size()))) return rc;
+  if (stats) HIPCHK(hipEventRecord(ctx->ev2, ctx->stream));
+  rc = wf_launch_batch(ctx, S, T, pl, at<WfPair>(ctx, o_desc), at<int32_t>(ctx, o_ord), out,
+                       nullptr, ub, cnt);
+  if (rc) return rc;
+  if (stats) {
+    HIPCHK(hipEventRecord(ctx->ev3, ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+    rc = readback(ctx, o_cnt, kCntBytes);
+    if (rc) return rc;
+    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned), pl.band_cells,
+               (uint64_t)npairs, elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+  }
+  return EAPDTW_OK;
+}
+
+int64_t eapdtw_dtw_batch_record_bytes(const eapdtw_pair *pairs, int64_t npairs) {
+  if (npairs < 0 || (npairs > 0 && !pairs)) return -1;
+  int64_t words = 0;
+  for (int64_t p = 0; p < npairs; ++p) {
+    const eapdtw_pair &q = pairs[p];
+    if (q.s_len < 0 || q.t_len < 0 || q.window < 0 || q.s_len > kWfMaxLen || q.t_len > kWfMaxLen)
+      return -1;
+    const int64_t r = clip_window(q.window, q.s_len, q.t_len);
+    const int c = (q.s_len == 0 || q.t_len == 0)
+                      ? 0
+                      : wf_class_for((int)q.s_len, (int)q.t_len, (int)r);
+    if (c < 0) return -1;
+    words += wf_rec_words((int)q.s_len, (int)q.t_len, c);
+  }
+  return words * (int64_t)sizeof(unsigned);
+}
+
+// Backtrack of a recorded batch into path ranges, one launch per class.
+static int wf_walk_batch(eapdtw_ctx *ctx, const WfBatchPlan &pl, const WfPair *d_desc,
+                         const int32_t *d_order, const unsigned *rec, unsigned *rowrng,
+                         unsigned *colrng) {
+  (void)d_order;
+  // the walk runs per pair; each class has its own record chunk width
+  for (int c = 0; c < kWfClasses; ++c) {
+    const int64_t n = pl.begin[c + 1] - pl.begin[c];
+    if (n == 0) continue;
+    WfWalkArgs w{};
+    w.pairs = d_desc;
+    w.npairs = (int64_t)pl.desc.size();
+    w.order = d_order + pl.begin[c];
+    w.nitems = n;
+    w.rec = rec;
+    w.rowrng = rowrng;
+    w.colrng = colrng;
+    w.max_chunks = pl.max_chunks[c];
+    w.max_ranges = pl.max_ranges[c];
+    HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
+  }
+  return EAPDTW_OK;
+}
+
+// Common part of the batched forward / backward / path entry points: plan,
+// upload the descriptors and run the recording forward into `rec` (or a
+// scratch record).  Returns the scratch offsets through the plan.
+struct WfBatchRun {
+  WfBatchPlan pl;
+  WfPair *desc = nullptr;
+  int32_t *order = nullptr;
+  unsigned *rec = nullptr;
+  float *dist = nullptr;
+  unsigned *rowrng = nullptr, *colrng = nullptr;
+};
+
+static int wf_batch_prepare(eapdtw_ctx *ctx, const std::vector<WfHostPair> &hp, int64_t s_total,
+                            int64_t t_total, bool own_record, bool ranges, WfBatchRun &run) {
+  wf_plan(hp, run.pl);
+  Plan sp;
+  const size_t o_desc = sp.add(sizeof(WfPair) * run.pl.desc.size());
+  const size_t o_ord = sp.add(sizeof(int32_t) * run.pl.order.size());
+  const size_t o_rec = own_record ? sp.add(sizeof(unsigned) * (size_t)run.pl.rec_words) : 0;
+  const size_t o_dist = sp.add(sizeof(float) * run.pl.desc.size());
+  const size_t o_rr = ranges ? sp.add(sizeof(unsigned) * (size_t)s_total) : 0;
+  const size_t o_cr = ranges ? sp.add(sizeof(unsigned) * (size_t)t_total) : 0;
+  int rc = ensure_scratch(ctx, sp.off);
+  if (rc) return rc;
+  run.desc = at<WfPair>(ctx, o_desc);
+  run.order = at<int32_t>(ctx, o_ord);
+  if (own_record) run.rec = at<unsigned>(ctx, o_rec);
+  run.dist = at<float>(ctx, o_dist);
+  if (ranges) {
+    run.rowrng = at<unsigned>(ctx, o_rr);
+    run.colrng = at<unsigned>(ctx, o_cr);
+  }
+  if ((rc = upload(ctx, o_desc, run.pl.desc.data(), sizeof(WfPair) * run.pl.desc.size())))
+    return rc;
+  return upload(ctx, o_ord, run.pl.order.data(), sizeof(int32_t) * run.pl.order.size());
+}
+
+int eapdtw_dtw_batch_fwd(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                         int64_t t_total, const eapdtw_pair *pairs, int64_t npairs, float *out,
+                         void *record) {
+  CHECK_CTX();
+  std::vector<WfHostPair> hp;
+  int rc = wf_validate(ctx, S, s_total, T, t_total, pairs, npairs, false, hp);
+  if (rc) return rc;
+  if (npairs > 0 && !out) return fail(ctx, EAPDTW_EINVAL, "out is NULL");
+  if (npairs == 0) return EAPDTW_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  WfBatchRun run;
+  if ((rc = wf_batch_prepare(ctx, hp, s_total, t_total, false, false, run))) return rc;
+  return wf_launch_batch(ctx, S, T, run.pl, run.desc, run.order, out,
+                         static_cast<unsigned *>(record), nullptr, nullptr);
+}
+
+// Walk + gradient (+ the recording forward into scratch without a record).
+static int wf_batch_backward(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                             int64_t t_total, const std::vector<WfHostPair> &hp,
+                             const void *record, const float *grad_out, float *grad_S,
+                             float *grad_T, unsigned *rowrng_out, unsigned *colrng_out) {
+  WfBatchRun run;
+  const bool own = record == nullptr;
+  const bool ranges = rowrng_out == nullptr;
+  int rc = wf_batch_prepare(ctx, hp, s_total, t_total, own, ranges, run);
+  if (rc) return rc;
+  const unsigned *rec = own ? run.rec : static_cast<const unsigned *>(record);
+  if (own) {
+    rc = wf_launch_batch(ctx, S, T, run.pl, run.desc, run.order, run.dist, run.rec, nullptr,
+                         nullptr);
+    if (rc) return rc;
+  }
+  unsigned *rr = ranges ? run.rowrng : rowrng_out;
+  unsigned *cr = ranges ? run.colrng : colrng_out;
+  if ((rc = wf_walk_batch(ctx, run.pl, run.desc, run.order, rec, rr, cr))) return rc;
+  if (!grad_S) return EAPDTW_OK;
+  WfGradArgs g{};
+  g.pairs = run.desc;
+  g.npairs = (int64_t)hp.size();
+  g.rec = rec;
+  g.S = S;
+  g.T = T;
+  g.rowrng = rr;
+  g.colrng = cr;
+  g.gout = grad_out;
+  g.gS = grad_S;
+  g.gT = grad_T;
+  HIPCHK(launch_wf_grad(g, ctx->stream));
+  return EAPDTW_OK;
+}
+
+int eapdtw_dtw_batch_bwd(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                         int64_t t_total, const eapdtw_pair *pairs, int64_t npairs,
+                         const void *record, const float *grad_out, float *grad_S,
+                         float *grad_T) {
+  CHECK_CTX();
+  std::vector<WfHostPair> hp;
+  int rc = wf_validate(ctx, S, s_total, T, t_total, pairs, npairs, true, hp);
+  if (rc) return rc;
+  if (npairs == 0) return EAPDTW_OK;
+  if (!grad_out || !grad_S || !grad_T) return fail(ctx, EAPDTW_EINVAL, "NULL gradient buffer");
+  HIPCHK(hipSetDevice(ctx->device));
+  return wf_batch_backward(ctx, S, s_total, T, t_total, hp, record, grad_out, grad_S, grad_T,
+                           nullptr, nullptr);
+}
+
+int eapdtw_dtw_batch_path(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
+                          int64_t t_total, const eapdtw_pair *pairs, int64_t npairs,
+                          unsigned *rowrng, unsigned *colrng) {
+  CHECK_CTX();
+  std::vector<WfHostPair> hp;
+  int rc = wf_validate(ctx, S, s_total, T, t_total, pairs, npairs, true, hp);
+  if (rc) return rc;
+  if (npairs == 0) return EAPDTW_OK;
+  if (!rowrng || !colrng) return fail(ctx, EAPDTW_EINVAL, "NULL range buffer");
+  HIPCHK(hipSetDevice(ctx->device));
+  return wf_batch_backward(ctx, S, s_total, T, t_total, hp, nullptr, nullptr, nullptr, nullptr,
+                           rowrng, colrng);
+}
+
+// --------------------------------------------------------------------------- differentiable batch (equal lengths)
+
+static int wf_uniform_class(int64_t len, int64_t window, int64_t *r_out) {
+  const int64_t r = clip_window(window, len, len);
+  if (r_out) *r_out = r;
+  if (len == 0) return 0;
+  if (len > kWfMaxLen) return -1;
+  return wf_class_for((int)len, (int)len, (int)r);
+}
 
 int64_t eapdtw_dtw_ckpt_bytes(int64_t npairs, int64_t len, int64_t window) {
-  if (npairs < 0 || len < 0 || window < 0 || len > INT_MAX / 2) return -1;
-  const int64_t r = len > 0 ? (window < len - 1 ? window : len - 1) : 0;
-  if (r > kBandRMax) return -1;
-  const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
-  const int64_t bytes = bwd_num_ckpt(len) * (2 * r + 1) * ld * (int64_t)sizeof(float);
+  if (npairs < 0 || len < 0 || window < 0) return -1;
+  const int c = wf_uniform_class(len, window, nullptr);
+  if (c < 0) return -1;
+  const int64_t bytes = npairs * wf_rec_words((int)len, (int)len, c) * (int64_t)sizeof(unsigned);
   return bytes > 4 ? bytes : 4;
 }
 
 static int diff_validate(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
-                         int64_t len, int64_t window, const void *ckpt) {
+                         int64_t len, int64_t window) {
   if (npairs < 0 || len < 0) return fail(ctx, EAPDTW_EINVAL, "negative size");
   if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
-  if (npairs > 0 && len > 0 && (!S || !T || !ckpt)) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
-  if (eapdtw_dtw_ckpt_bytes(npairs, len, window) < 0)
-    return fail(ctx, EAPDTW_EINVAL, "the differentiable batch supports windows up to 64");
-  if (len > 65535) return fail(ctx, EAPDTW_EINVAL, "series longer than 65535");
+  if (npairs > INT_MAX) return fail(ctx, EAPDTW_EINVAL, "too many pairs");
+  if (npairs > 0 && len > 0 && (!S || !T)) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
+  if (wf_uniform_class(len, window, nullptr) < 0)
+    return fail(ctx, EAPDTW_EINVAL,
+                "the differentiable batch supports lengths up to 8191 with at most 511 rows "
+                "active at once (min(window + 1, len) <= 511)");
+  return EAPDTW_OK;
+}
+
+// Forward of uniform pairs through the wavefront kernel (record optional).
+static int wf_uniform_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
+                          int64_t len, int64_t window, float *out, unsigned *rec) {
+  int64_t r = 0;
+  const int c = wf_uniform_class(len, window, &r);
+  WfArgs a{};
+  a.S = S;
+  a.T = T;
+  a.nitems = npairs;
+  a.ls = a.lt = (int)len;
+  a.r = (int)r;
+  a.rec_words_u = wf_rec_words((int)len, (int)len, c);
+  a.out = out;
+  a.rec = rec;
+  a.lds_stride = (int)(2 * len + 2 * kWfPad);
+  HIPCHK(launch_wf_fwd(c, rec != nullptr, a, ctx->stream));
   return EAPDTW_OK;
 }
 
 int eapdtw_dtw_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
                    int64_t window, float *out_dist, void *ckpt) {
   CHECK_CTX();
-  int rc = diff_validate(ctx, S, T, npairs, len, window, ckpt);
+  int rc = diff_validate(ctx, S, T, npairs, len, window);
   if (rc) return rc;
-  if (npairs > 0 && !out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL output");
-  return pairs_common(ctx, S, T, npairs, len, window, 0, nullptr, out_dist, nullptr,
-                      static_cast<float *>(ckpt), kBwdBlock);
+  if (npairs == 0) return EAPDTW_OK;
+  if (!out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL output");
+  HIPCHK(hipSetDevice(ctx->device));
+  return wf_uniform_fwd(ctx, S, T, npairs, len, window, out_dist, static_cast<unsigned *>(ckpt));
+}
+
+// Walk + gradient of uniform pairs (recording forward into scratch when no
+// record is given); with rowrng_out the ranges go there and no gradient is made.
+static int wf_uniform_backward(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
+                               int64_t len, int64_t window, const void *record,
+                               const float *grad_out, float *grad_S, float *grad_T,
+                               unsigned *rowrng_out, unsigned *colrng_out, float *dist_out) {
+  int64_t r = 0;
+  const int c = wf_uniform_class(len, window, &r);
+  const int64_t words = wf_rec_words((int)len, (int)len, c);
+  const bool own = record == nullptr;
+  const bool ranges = rowrng_out == nullptr;
+  Plan sp;
+  const size_t o_rec = own ? sp.add(sizeof(unsigned) * (size_t)(npairs * words)) : 0;
+  const size_t o_dist = sp.add(sizeof(float) * (size_t)npairs);
+  const size_t o_rr = ranges ? sp.add(sizeof(unsigned) * (size_t)(npairs * len)) : 0;
+  const size_t o_cr = ranges ? sp.add(sizeof(unsigned) * (size_t)(npairs * len)) : 0;
+  int rc = ensure_scratch(ctx, sp.off);
+  if (rc) return rc;
+  const unsigned *rec = own ? at<unsigned>(ctx, o_rec) : static_cast<const unsigned *>(record);
+  if (own) {
+    rc = wf_uniform_fwd(ctx, S, T, npairs, len, window, dist_out ? dist_out : at<float>(ctx, o_dist),
+                        at<unsigned>(ctx, o_rec));
+    if (rc) return rc;
+  }
+  unsigned *rr = ranges ? at<unsigned>(ctx, o_rr) : rowrng_out;
+  unsigned *cr = ranges ? at<unsigned>(ctx, o_cr) : colrng_out;
+  WfWalkArgs w{};
+  w.npairs = npairs;
+  w.nitems = npairs;
+  w.ls = w.lt = (int)len;
+  w.r = (int)r;
+  w.rec_words_u = words;
+  w.rec = rec;
+  w.rowrng = rr;
+  w.colrng = cr;
+  w.max_chunks = wf_chunks((int)len, (int)len);
+  w.max_ranges = (int)(2 * len);
+  HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
+  if (!grad_S) return EAPDTW_OK;
+  WfGradArgs g{};
+  g.npairs = npairs;
+  g.ls = g.lt = (int)len;
+  g.rec_words_u = words;
+  g.rec = rec;
+  g.S = S;
+  g.T = T;
+  g.rowrng = rr;
+  g.colrng = cr;
+  g.gout = grad_out;
+  g.gS = grad_S;
+  g.gT = grad_T;
+  HIPCHK(launch_wf_grad(g, ctx->stream));
+  return EAPDTW_OK;
 }
 
 int eapdtw_dtw_bwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
                    int64_t window, const void *ckpt, const float *grad_out, float *grad_S,
                    float *grad_T) {
   CHECK_CTX();
-  int rc = diff_validate(ctx, S, T, npairs, len, window, ckpt);
+  int rc = diff_validate(ctx, S, T, npairs, len, window);
   if (rc) return rc;
   if (npairs == 0 || len == 0) return EAPDTW_OK;
   if (!grad_out || !grad_S || !grad_T) return fail(ctx, EAPDTW_EINVAL, "NULL gradient buffer");
   HIPCHK(hipSetDevice(ctx->device));
-  hipStream_t st = ctx->stream;
-  const int64_t r = window < len - 1 ? window : len - 1;
-  const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
-  Plan pl;
-  const size_t o_rows = pl.add(sizeof(float) * len * ld);
-  const size_t o_cols = pl.add(sizeof(float) * (len + 2 * kColPad) * ld);
-  const size_t o_rr = pl.add(sizeof(unsigned) * len * ld);
-  const size_t o_cr = pl.add(sizeof(unsigned) * len * ld);
-  rc = ensure_scratch(ctx, pl.off);
+  return wf_uniform_backward(ctx, S, T, npairs, len, window, ckpt, grad_out, grad_S, grad_T,
+                             nullptr, nullptr, nullptr);
+}
+
+int eapdtw_dtw_path(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs, int64_t len,
+                    int64_t window, float *out_dist, unsigned *rowrng, unsigned *colrng) {
+  CHECK_CTX();
+  int rc = diff_validate(ctx, S, T, npairs, len, window);
   if (rc) return rc;
-  HIPCHK(launch_transpose_pad(S, npairs, (int)len, ld, 0, 0.0f, at<float>(ctx, o_rows), st));
-  HIPCHK(launch_transpose_pad(T, npairs, (int)len, ld, kColPad, INFINITY, at<float>(ctx, o_cols), st));
-  BwdArgs b{};
-  b.rowsT = at<float>(ctx, o_rows);
-  b.colsT = at<float>(ctx, o_cols);
-  b.ckpt = static_cast<const float *>(ckpt);
-  b.dist = nullptr;
-  b.rowrng = at<unsigned>(ctx, o_rr);
-  b.colrng = at<unsigned>(ctx, o_cr);
-  b.npairs = npairs;
-  b.ld = ld;
-  b.len = (int)len;
-  HIPCHK(launch_dtw_bwd((int)r, b, st));
-  HIPCHK(launch_dtw_grad(S, T, npairs, (int)len, b.rowrng, b.colrng, nullptr, grad_out, grad_S,
-                         grad_T, st));
+  if (npairs == 0 || len == 0) return EAPDTW_OK;
+  if (!rowrng || !colrng) return fail(ctx, EAPDTW_EINVAL, "NULL range buffer");
+  HIPCHK(hipSetDevice(ctx->device));
+  return wf_uniform_backward(ctx, S, T, npairs, len, window, nullptr, nullptr, nullptr, nullptr,
+                             rowrng, colrng, out_dist);
+}
+
+// --------------------------------------------------------------------------- DBA
+
+int eapdtw_dba_step(eapdtw_ctx *ctx, const float *B, int64_t lb, const float *X, int64_t n,
+                    int64_t len, int64_t window, float *out_B, float *out_count) {
+  CHECK_CTX();
+  if (lb <= 0 || len <= 0 || n <= 0) return fail(ctx, EAPDTW_EINVAL, "empty barycentre or set");
+  if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
+  if (!B || !X || !out_B) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
+  if (n > INT_MAX / 2) return fail(ctx, EAPDTW_EINVAL, "too many series");
+  if (std::llabs(lb - len) > clip_window(window, lb, len))
+    return fail(ctx, EAPDTW_EINVAL, "no warping path: |lb - len| exceeds the window");
+  const int64_t r = clip_window(window, lb, len);
+  if (lb > kWfMaxLen || len > kWfMaxLen || wf_class_for((int)lb, (int)len, (int)r) < 0)
+    return fail(ctx, EAPDTW_EINVAL, "more than 511 rows active at once, or series too long");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int c = wf_class_for((int)lb, (int)len, (int)r);
+  const int64_t words = wf_rec_words((int)lb, (int)len, c);
+  const int64_t nchunk = (n + kDbaPairs - 1) / kDbaPairs;
+  Plan sp;
+  const size_t o_Bx = sp.add(sizeof(float) * (size_t)(n * lb));
+  const size_t o_rec = sp.add(sizeof(unsigned) * (size_t)(n * words));
+  const size_t o_dist = sp.add(sizeof(float) * (size_t)n);
+  const size_t o_rr = sp.add(sizeof(unsigned) * (size_t)(n * lb));
+  const size_t o_cr = sp.add(sizeof(unsigned) * (size_t)(n * len));
+  const size_t o_ps = sp.add(sizeof(double) * (size_t)(nchunk * lb));
+  const size_t o_pc = sp.add(sizeof(double) * (size_t)(nchunk * lb));
+  int rc = ensure_scratch(ctx, sp.off);
+  if (rc) return rc;
+  // the barycentre is the row series of every pair
+  HIPCHK(launch_broadcast_rows(B, lb, n, at<float>(ctx, o_Bx), ctx->stream));
+  WfArgs a{};
+  a.S = at<float>(ctx, o_Bx);
+  a.T = X;
+  a.nitems = n;
+  a.ls = (int)lb;
+  a.lt = (int)len;
+  a.r = (int)r;
+  a.rec_words_u = words;
+  a.out = at<float>(ctx, o_dist);
+  a.rec = at<unsigned>(ctx, o_rec);
+  a.lds_stride = (int)(lb + len + 2 * kWfPad);
+  HIPCHK(launch_wf_fwd(c, true, a, ctx->stream));
+  WfWalkArgs w{};
+  w.npairs = n;
+  w.nitems = n;
+  w.ls = (int)lb;
+  w.lt = (int)len;
+  w.r = (int)r;
+  w.rec_words_u = words;
+  w.rec = a.rec;
+  w.rowrng = at<unsigned>(ctx, o_rr);
+  w.colrng = at<unsigned>(ctx, o_cr);
+  w.max_chunks = wf_chunks((int)lb, (int)len);
+  w.max_ranges = (int)(lb + len);
+  HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
+  HIPCHK(launch_wf_dba(X, n, (int)len, (int)lb, w.rowrng, a.rec, words, at<double>(ctx, o_ps),
+                       at<double>(ctx, o_pc), nchunk, out_B, out_count, ctx->stream));
   return EAPDTW_OK;
 }
 

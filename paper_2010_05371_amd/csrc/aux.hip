@@ -87,6 +87,22 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// dst[p][i] = src[i] for p < n, i < len
+__global__ void broadcast_rows_kernel(const float *__restrict__ src, int64_t len, int64_t n,
+                                      float *__restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n * len) dst[k] = src[k % len];
+}
+
+hipError_t launch_broadcast_rows(const float *src, int64_t len, int64_t n, float *dst,
+                                 hipStream_t st) {
+  const int64_t total = n * len;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(broadcast_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, src, len, n, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_check_finite(const float *x, int64_t n, unsigned long long *counters,
                                hipStream_t st) {
   if (n <= 0) return hipSuccess;

@@ -68,5 +68,8 @@ hipError_t launch_window_stats(const float *x, int64_t n, int m, double *mean, d
                                hipStream_t st);
 hipError_t launch_znorm(const float *x, int m, float *out, hipStream_t st);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
+// n copies of src [len] into dst [n][len]
+hipError_t launch_broadcast_rows(const float *src, int64_t len, int64_t n, float *dst,
+                                 hipStream_t st);
 
 }  // namespace eapdtw

@@ -10,7 +10,7 @@ import torch
 import gen
 import oracle
 import paper_2010_05371_amd as eap
-from parity import close
+from parity import check_gpu_paths, close
 
 pytestmark = pytest.mark.gpu
 
@@ -47,16 +47,13 @@ def test_dtw_loss_barycentre_training():
     b = gen.as_oracle(B.detach().cpu().numpy())
     ref = float(np.mean([oracle.dtw(b, gen.as_oracle(S[p]), w) for p in range(P)]))
     assert close(final, ref), (final, ref)
-    # the per-pair gradients at the trained barycentre against the oracle's
-    # path gradient, for the pairs away from path ties
+    # the per-pair gradients at the trained barycentre, on the GPU's own
+    # paths (a trained barycentre sits near many path ties, where float32
+    # rounding picks one of several optimal paths)
     Bx = B.detach().unsqueeze(0).expand(P, L).contiguous().requires_grad_(True)
-    eap.DTWFunction.apply(Bx, St, w).mean().backward()
+    d = eap.DTWFunction.apply(Bx, St, w)
+    d.mean().backward()
     gx = Bx.grad.cpu().numpy()
-    checked = 0
-    for p in range(P):
-        _, dS, _, _, gap = oracle.dtw_grad(b, gen.as_oracle(S[p]), w, 1.0 / P)
-        if gap > 1e-4:
-            floor = 1e-5 * max(1.0 / P, float(np.abs(dS).max()))
-            assert np.all(np.abs(gx[p] - dS) <= floor + 1e-4 * np.abs(dS)), p
-            checked += 1
-    assert checked >= P // 4, checked  # a trained barycentre sits near many path ties
+    dp, rr, cr = eap.dtw_path(Bx.detach(), St, w)
+    check_gpu_paths(Bx.detach().cpu().numpy(), S, w, d.detach().cpu().numpy(), rr.cpu().numpy(),
+                    cr.cpu().numpy(), gx, None, np.full(P, 1.0 / P), grad_abs=1e-5 / P)

@@ -1,6 +1,10 @@
 """GPU parity of the differentiable batch (forward + backward through
-torch.autograd) against the FP64 oracle's path gradient and against central
-finite differences of the FP64 DTW."""
+torch.autograd).  Every pair is checked on the GPU's own path: the path the
+backward follows (exported by dtw_path) must be a valid warping path in the
+window whose float64 cost is the oracle's DTW (Section 2: several optimal paths
+may exist, and float32 rounding may pick another one of equal cost), and the
+GPU gradient must be that path's float64 gradient.  On integer data, where
+float32 is exact, the path must be the oracle's own (its tie order)."""
 import numpy as np
 import pytest
 import torch
@@ -8,52 +12,59 @@ import torch
 import gen
 import oracle
 import paper_2010_05371_amd as eap
-from parity import assert_close_array
+from parity import assert_close_array, check_gpu_paths, unpack
 
 pytestmark = pytest.mark.gpu
 
-GRAD_REL = 1e-5
-GRAD_ABS = 1e-5
 
-
-def _grad_close(got, want, scale):
-    return np.abs(got - want) <= GRAD_ABS * np.maximum(1.0, scale) + GRAD_REL * np.abs(want)
-
-
-def _run(S32, T32, w, gout=None):
+def _run(S32, T32, w, gout=None, recompute=False):
     S = torch.from_numpy(S32).cuda().requires_grad_(True)
     T = torch.from_numpy(T32).cuda().requires_grad_(True)
-    d = eap.DTWFunction.apply(S, T, w)
+    d = eap.DTWFunction.apply(S, T, w, recompute)
     g = torch.ones_like(d) if gout is None else torch.from_numpy(gout).cuda()
     d.backward(g)
     return d.detach().cpu().numpy(), S.grad.cpu().numpy(), T.grad.cpu().numpy()
 
 
-def _check_pairs(S32, T32, w, gout, allow_tie_frac=0.05):
+def _check(S32, T32, w, gout=None):
     d, gS, gT = _run(S32, T32, w, gout)
-    P = S32.shape[0]
-    want = oracle.dtw_pairs(gen.as_oracle(S32), gen.as_oracle(T32), w, np.arange(P), np.arange(P))
-    assert_close_array(d, want, what="forward")
-    mismatched = 0
-    for p in range(P):
-        od, odS, odT, _, gap = oracle.dtw_grad(gen.as_oracle(S32[p]), gen.as_oracle(T32[p]), w,
-                                               float(gout[p]))
-        scale = float(np.max(np.abs(odS)) + np.max(np.abs(odT)))
-        ok = _grad_close(gS[p], odS, scale).all() and _grad_close(gT[p], odT, scale).all()
-        if not ok:
-            # a float32 near-tie may select another optimal path: accepted only
-            # where the oracle itself sees a predecessor within tolerance
-            assert gap <= 1e-4, (p, gap)
-            mismatched += 1
-    assert mismatched <= allow_tie_frac * P + 1, mismatched
+    dp, rr, cr = eap.dtw_path(torch.from_numpy(S32), torch.from_numpy(T32), w)
+    assert np.array_equal(dp.cpu().numpy(), d), "dtw_path and the forward differ"
+    check_gpu_paths(S32, T32, w, d, rr.cpu().numpy(), cr.cpu().numpy(), gS, gT, gout)
+    return d, gS, gT
 
 
 @pytest.mark.parametrize("P,L,w", [(64, 64, 7), (130, 100, 10), (70, 37, 5), (64, 48, 0),
-                                   (5, 17, 16), (3, 2, 1), (66, 90, 64)])
-def test_forward_backward_vs_oracle_path_gradient(P, L, w):
+                                   (5, 17, 16), (3, 2, 1), (66, 90, 64), (40, 120, 119),
+                                   (17, 300, 200), (9, 700, 300)])
+def test_forward_backward_on_the_gpu_path(P, L, w):
     S32, T32, _ = gen.c5(P=P, L=L)
     gout = gen.as_f32(gen.rng(50, P).uniform(0.5, 2.0, P))
-    _check_pairs(S32, T32, w, gout)
+    _check(S32, T32, w, gout)
+
+
+def test_integer_data_follows_the_oracle_tie_order():
+    """Small integers: float32 arithmetic is exact, ties are exact, and the
+    GPU's path must be the oracle's (diagonal, then (i-1,j), then (i,j-1))."""
+    g = np.random.default_rng(31)
+    for L, w in ((9, 3), (16, 15), (33, 4), (70, 70)):
+        S32 = g.integers(0, 3, (64, L)).astype(np.float32)
+        T32 = g.integers(0, 3, (64, L)).astype(np.float32)
+        d, rr, cr = eap.dtw_path(torch.from_numpy(S32), torch.from_numpy(T32), w)
+        lo, hi = unpack(rr.cpu().numpy())
+        for p in range(64):
+            od, _, _, opath, _ = oracle.dtw_grad(S32[p].astype(float), T32[p].astype(float), w)
+            mine = sorted((i + 1, j + 1) for i in range(L) for j in range(lo[p, i], hi[p, i] + 1))
+            assert mine == sorted(opath), (L, w, p)
+            assert float(d[p]) == od
+
+
+def test_recompute_equals_record():
+    S32, T32, _ = gen.c5(P=100, L=80)
+    a = _run(S32, T32, 9, recompute=False)
+    b = _run(S32, T32, 9, recompute=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
 
 
 def test_single_cell():
@@ -75,19 +86,36 @@ def test_identical_series_zero_gradient():
     assert not d.any() and not gS.any() and not gT.any()
 
 
+def test_non_finite_pair_gives_nan_and_leaves_the_others():
+    S32, T32, _ = gen.c5(P=20, L=30)
+    S32[3, 7] = np.nan
+    T32[11, 0] = np.inf
+    d, gS, gT = _run(S32, T32, 4)
+    for p in (3, 11):
+        assert np.isnan(d[p]) and np.isnan(gS[p]).all() and np.isnan(gT[p]).all()
+    ok = [p for p in range(20) if p not in (3, 11)]
+    want = oracle.dtw_pairs(gen.as_oracle(S32[ok]), gen.as_oracle(T32[ok]), 4, np.arange(18),
+                            np.arange(18))
+    assert_close_array(d[ok], want, what="finite pairs")
+    assert np.isfinite(gS[ok]).all() and np.isfinite(gT[ok]).all()
+
+
 def test_central_finite_differences():
     """FP64 central differences of the oracle DTW are exact for a fixed path;
     compare the GPU gradient to them on coordinates whose perturbation keeps
-    the oracle's optimal path."""
+    the oracle's optimal path (where the oracle's path is the GPU's)."""
     S32, T32, _ = gen.c5(P=8, L=40)
     w = 4
     d, gS, gT = _run(S32, T32, w)
+    _, rr, _ = eap.dtw_path(torch.from_numpy(S32), torch.from_numpy(T32), w)
+    lo, hi = unpack(rr.cpu().numpy())
     h = 1e-4
     checked = 0
     for p in range(8):
         S, T = gen.as_oracle(S32[p]), gen.as_oracle(T32[p])
-        _, _, _, path, gap = oracle.dtw_grad(S, T, w)
-        if gap <= 1e-4:
+        _, _, _, path, _ = oracle.dtw_grad(S, T, w)
+        mine = sorted((i + 1, j + 1) for i in range(40) for j in range(lo[p, i], hi[p, i] + 1))
+        if mine != sorted(path):
             continue
         for which, base, grad in (("S", S, gS[p]), ("T", T, gT[p])):
             for k in range(0, 40, 3):
@@ -109,24 +137,17 @@ def test_central_finite_differences():
 
 
 def test_ckpt_bytes():
-    assert eap._lib.load().eapdtw_dtw_ckpt_bytes(4096, 256, 26) == 15 * 53 * 4096 * 4
-    assert eap._lib.load().eapdtw_dtw_ckpt_bytes(10, 256, 100) == -1
+    lib = eap._lib.load()
+    # 64 status words + one word per lane-slot (32 for window 26) and 16 steps
+    assert lib.eapdtw_dtw_ckpt_bytes(4096, 256, 26) == 4096 * (64 + 32 * 32) * 4
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 256, 100) == 10 * (64 + 32 * 128) * 4
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 600, 599) == -1   # 600 rows active at once
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 9000, 3) == -1    # longer than 8191
 
 
 def test_c5_full_size():
-    """4,096 warped pairs of length 256, window 26: every forward distance
-    against the oracle, gradients on a sample of pairs."""
+    """4,096 warped pairs of length 256, window 26: every pair's distance,
+    path and gradient."""
     S32, T32, w = gen.c5()
-    d, gS, gT = _run(S32, T32, w)
-    P = S32.shape[0]
-    want = oracle.dtw_pairs(gen.as_oracle(S32), gen.as_oracle(T32), w, np.arange(P), np.arange(P))
-    assert_close_array(d, want, what="c5 forward")
-    idx = np.linspace(0, P - 1, 48).astype(int)
-    bad = 0
-    for p in idx:
-        _, odS, odT, _, gap = oracle.dtw_grad(gen.as_oracle(S32[p]), gen.as_oracle(T32[p]), w)
-        scale = float(np.max(np.abs(odS)) + np.max(np.abs(odT)))
-        if not (_grad_close(gS[p], odS, scale).all() and _grad_close(gT[p], odT, scale).all()):
-            assert gap <= 1e-4
-            bad += 1
-    assert bad <= 3
+    gout = gen.as_f32(gen.rng(51, S32.shape[0]).uniform(0.5, 2.0, S32.shape[0]))
+    _check(S32, T32, w, gout)
