@@ -144,6 +144,13 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *                      the DTW pass re-checks each survivor's bounds against
  *                      its own best-so-far anyway, and a second pair of
  *                      launches costs more than the probe saves)
+ *   "wf_lanes"       : lanes per pair of the wavefront pair kernels (the
+ *                      equal-length and uneven batches): 0 = chosen by the
+ *                      pair's size and the number of pairs (default), or 16,
+ *                      32, 64 when a class with that many lanes holds the pair
+ *                      (recorded sweeps: only among the classes that keep the
+ *                      pair's codes in LDS, so the record size never depends
+ *                      on it).  Same results for every value
  * Returns EINVAL for an unknown key or value. */
 int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
 int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);
@@ -259,25 +266,30 @@ int eapdtw_tune_load(eapdtw_ctx *ctx, const char *path);
  * Differentiable batch of equal-length pairs (Section 2: DTW is the cost of an
  * optimal warping path; its gradient is the gradient of that path's cost,
  * dD/dS(i) = 2 sum_j (S(i)-T(j)), dD/dT(j) = -2 sum_i (S(i)-T(j)) over the
- * path cells).  Each pair is swept by 16 or 64 SIMD lanes along the
- * anti-diagonals of its band, one matrix row per lane; no bound, plain DTW.
+ * path cells).  Each pair is swept by 16, 32 or 64 SIMD lanes along the
+ * anti-diagonals of its band, one matrix row per lane and cell slot (1-8
+ * slots); no bound, plain DTW.
  *   S, T [npairs][len] : DEVICE float32, row-major.
  *   window             : r >= 0 (clipped to len - 1).  Supported: len <= 8191
  *                        and min(window + 1, len) <= 511 (rows active at
  *                        once); otherwise EINVAL.
  *
- * eapdtw_dtw_ckpt_bytes: size of the direction record of such a batch: two
- *   bits per swept cell (which predecessor gave the minimum; ties: the
- *   diagonal, then (i-1,j), then (i,j-1)) plus a status word per pair.  The
- *   len x len matrix is never stored.  -1 for unsupported sizes.
+ * eapdtw_dtw_ckpt_bytes: size of the record the forward leaves for the
+ *   backward: a status word per pair and the optimal path as one column range
+ *   per row and one row range per column (ties: the diagonal, then (i-1,j),
+ *   then (i,j-1)); when a pair's 2-bit argmin codes (one per swept cell) do
+ *   not fit in LDS beside its series, also those codes, which the backward
+ *   then follows.  The len x len matrix is never stored.  -1 for unsupported
+ *   sizes.
  * eapdtw_dtw_fwd: out_dist [npairs] DEVICE.  ckpt: DEVICE buffer of
- *   eapdtw_dtw_ckpt_bytes bytes that receives the direction record (consumed
- *   by eapdtw_dtw_bwd), or NULL for the distances alone (the backward then
- *   sweeps the forward again).  A pair with a non-finite value gets NaN.
- *   Asynchronous.
- * eapdtw_dtw_bwd: follows each pair's record from (len,len) back to (1,1)
- *   (ckpt = the forward's record, or NULL: the forward is swept again with a
- *   record in the context's scratch) and writes
+ *   eapdtw_dtw_ckpt_bytes bytes that receives the record (consumed by
+ *   eapdtw_dtw_bwd), or NULL for the distances alone (the backward then
+ *   sweeps the forward again).  With a record, each pair's forward follows its
+ *   codes back from (len,len) to (1,1) when they are held in LDS.  A pair with
+ *   a non-finite value gets NaN.  Asynchronous.
+ * eapdtw_dtw_bwd: takes the path from the record (following the recorded
+ *   codes first where the forward kept them in memory; ckpt = NULL: the
+ *   forward is swept again with a record in the context's scratch) and writes
  *   grad_S[p][i] = 2 g sum over the path cells (i,j) of (S(i)-T(j)),
  *   grad_T[p][j] = -2 g sum over the path cells (i,j) of (S(i)-T(j)),
  *   g = grad_out[p]; a pair with a non-finite value gets NaN gradients.
@@ -307,10 +319,10 @@ int eapdtw_dtw_path(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npa
  * lS != lT; Section 2.1 window per pair).  Series live in two DEVICE pools:
  * pair p is S[s_off .. s_off + s_len) against T[t_off .. t_off + t_len) under
  * window r_p (clipped to max(s_len, t_len) - 1; |s_len - t_len| > r_p has no
- * warping path: +inf).  Pairs are grouped by the lanes they need (16 or 64 per
- * pair) and run longest first, one launch per group.  Supported: lengths up
- * to 8191 and min(r_p + 1, s_len, t_len) <= 511; otherwise EINVAL.  Both
- * series empty: 0; one empty: +inf (Eq. 2-4).
+ * warping path: +inf).  Pairs are grouped by kernel class (16, 32 or 64 lanes
+ * per pair, 1-8 rows per lane) and run longest first, one launch per group.
+ * Supported: lengths up to 8191 and min(r_p + 1, s_len, t_len) <= 511;
+ * otherwise EINVAL.  Both series empty: 0; one empty: +inf (Eq. 2-4).
  *   pairs [npairs] : HOST array (copied before the call returns). */
 typedef struct {
   int64_t s_off, s_len;
@@ -331,9 +343,10 @@ int eapdtw_dtw_pairs_batch(eapdtw_ctx *ctx, const float *S, int64_t s_total, con
 /* Differentiable form (as eapdtw_dtw_fwd / eapdtw_dtw_bwd): the record size
  * (-1 when unsupported), the forward (record may be NULL) and the backward
  * into pool-shaped gradients grad_S [s_total], grad_T [t_total] (elements
- * outside every pair are not written).  The backward needs pairs whose S
- * regions do not overlap, nor their T regions (EINVAL otherwise); it must get
- * the same pairs as the forward that wrote the record. */
+ * outside every pair are not written).  A forward with a record and the
+ * backward need pairs whose S regions do not overlap, nor their T regions
+ * (EINVAL otherwise: the record holds the path ranges in the pools' layout);
+ * the backward must get the same pairs as the forward that wrote the record. */
 int64_t eapdtw_dtw_batch_record_bytes(const eapdtw_pair *pairs, int64_t npairs);
 int eapdtw_dtw_batch_fwd(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
                          int64_t t_total, const eapdtw_pair *pairs, int64_t npairs, float *out,

@@ -45,6 +45,7 @@ struct eapdtw_ctx {
   int64_t ed = 1;
   int64_t autotune = 0;
   int64_t lanes = 0;  // band search with lane refill where it applies
+  int64_t wf_lanes = 0;  // wavefront pair kernels: lanes per pair (0 = by size, 16, 32 or 64)
   int64_t lb_ec = 0;         // cascade: apply the candidate-envelope LB_Keogh
   int64_t lb_probe_div = 0;  // cascade: first pass over K / div candidates (0: one pass)
   float lb_ms = 0.f, lb_dp_ms = 0.f;  // cascade timing of the last timed call
@@ -338,6 +339,7 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "lanes")) return &ctx->lanes;
   if (!strcmp(key, "lb_ec")) return &ctx->lb_ec;
   if (!strcmp(key, "lb_probe_div")) return &ctx->lb_probe_div;
+  if (!strcmp(key, "wf_lanes")) return &ctx->wf_lanes;
   return nullptr;
 }
 
@@ -352,6 +354,7 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
            !strcmp(key, "lanes") || !strcmp(key, "lb_ec"))
     ok = value == 0 || value == 1;
   else if (!strcmp(key, "lb_probe_div")) ok = value == 0 || (value >= 2 && value <= 4096);
+  else if (!strcmp(key, "wf_lanes")) ok = value == 0 || value == 16 || value == 32 || value == 64;
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
   else if (!strcmp(key, "seed_stride")) ok = value >= 0 && value <= (1 << 20);
@@ -1757,6 +1760,10 @@ static int64_t clip_window(int64_t window, int64_t ls, int64_t lt) {
   return lmax > 0 && window > lmax - 1 ? lmax - 1 : window;
 }
 
+static bool wf_has_path(const WfHostPair &h) {
+  return h.ls > 0 && h.lt > 0 && std::llabs(h.ls - h.lt) <= h.r;
+}
+
 // Validates a host array of eapdtw_pair against the pools and clips the
 // windows.  `disjoint`: the pairs' S regions must not overlap, nor their T
 // regions (their gradients and path ranges are written in place).
@@ -1799,83 +1806,111 @@ static int wf_validate(eapdtw_ctx *ctx, const float *S, int64_t s_total, const f
   return EAPDTW_OK;
 }
 
-static int wf_class_of(const WfHostPair &h) {
-  if (h.ls == 0 || h.lt == 0) return 0;
-  return wf_class_for((int)h.ls, (int)h.lt, (int)h.r);
+// Kernel class of a distance-only sweep in a launch of npairs pairs: by size
+// and launch width, or with the lanes per pair that option wf_lanes asks for,
+// if such a class holds the pair.
+static int wf_pick(const eapdtw_ctx *ctx, int64_t ls, int64_t lt, int64_t r, int64_t npairs) {
+  if (ls == 0 || lt == 0) return 0;
+  if (ctx && ctx->wf_lanes) {
+    const int c = wf_choose((int)ls, (int)lt, (int)r, npairs, (int)ctx->wf_lanes, false);
+    if (c >= 0) return c;
+  }
+  return wf_choose((int)ls, (int)lt, (int)r, npairs, 0, false);
 }
 
-// Per-pair device descriptors, record offsets and per-class launch orders
-// (most steps first) of a batch.
+// Launch groups of a planned batch: (class, mode); mode 0 distances, 1 codes
+// to memory (then the walk kernel), 2 codes in LDS and the backtrack in the
+// forward.
+constexpr int kWfGroups = 3 * kWfClasses;
+
+// A recorded batch in one device buffer (the caller's record or scratch):
+// the status word of every pair, the path ranges in the layout of the two
+// pools (pair p's rows at s_off, columns at t_off) and the code words of the
+// pairs whose sweep keeps them in memory (mode 1).
+struct WfRecLayout {
+  size_t status = 0, rowrng = 0, colrng = 0, codes = 0, bytes = 0;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static WfRecLayout wf_layout(int64_t npairs, int64_t s_extent, int64_t t_extent,
+                             int64_t code_words) {
+  WfRecLayout L;
+  L.status = 0;
+  L.rowrng = align256(sizeof(unsigned) * (size_t)npairs);
+  L.colrng = L.rowrng + align256(sizeof(unsigned) * (size_t)s_extent);
+  L.codes = L.colrng + align256(sizeof(unsigned) * (size_t)t_extent);
+  L.bytes = L.codes + sizeof(unsigned) * (size_t)code_words;
+  if (L.bytes < 4) L.bytes = 4;
+  return L;
+}
+
+// Per-pair device descriptors and per-group launch orders (most steps first).
 struct WfBatchPlan {
   std::vector<WfPair> desc;
-  std::vector<int32_t> order;        // pairs grouped by class
-  int64_t begin[kWfClasses + 1] = {};
-  int lds_stride[kWfClasses] = {};
-  int max_chunks[kWfClasses] = {};  // record chunks of the class's longest pair
-  int max_ranges[kWfClasses] = {};  // ls + lt of the class's longest pair
-  int64_t rec_words = 0;
+  std::vector<int32_t> order;       // pairs grouped by launch group
+  int64_t begin[kWfGroups + 1] = {};
+  int lds_stride[kWfGroups] = {};
+  int max_chunks[kWfGroups] = {};   // record chunks of the group's longest pair
+  int max_ranges[kWfGroups] = {};   // ls + lt of the group's longest pair
+  int64_t code_words = 0;
+  int64_t s_extent = 0, t_extent = 0;
   uint64_t band_cells = 0;
 };
 
-static void wf_plan(const std::vector<WfHostPair> &hp, WfBatchPlan &pl) {
+// path = false: distance-only classes (mode 0, ctx options apply); true:
+// recorded classes (mode 2 where the codes fit in LDS, else mode 1).
+static void wf_plan(const eapdtw_ctx *ctx, const std::vector<WfHostPair> &hp, bool path,
+                    WfBatchPlan &pl) {
   const int64_t n = (int64_t)hp.size();
   pl.desc.resize((size_t)n);
-  std::vector<int> cls((size_t)n);
-  int64_t cnt[kWfClasses] = {};
+  std::vector<int> grp((size_t)n);
+  int64_t cnt[kWfGroups] = {};
   for (int64_t p = 0; p < n; ++p) {
     const WfHostPair &h = hp[(size_t)p];
-    const int c = wf_class_of(h);
-    cls[(size_t)p] = c;
-    ++cnt[c];
+    int c = 0, mode = 0;
+    if (h.ls > 0 && h.lt > 0) {
+      if (path) {
+        bool fused = false;
+        c = wf_path_class((int)h.ls, (int)h.lt, (int)h.r, n, ctx ? (int)ctx->wf_lanes : 0, &fused);
+        mode = fused ? 2 : 1;
+      } else {
+        c = wf_pick(ctx, h.ls, h.lt, h.r, n);
+      }
+    } else if (path) {
+      mode = 2;  // no sweep: the status word only
+    }
+    const int gi = mode * kWfClasses + c;
+    grp[(size_t)p] = gi;
+    ++cnt[gi];
     WfPair &d = pl.desc[(size_t)p];
     d.s_off = h.s_off;
     d.t_off = h.t_off;
-    d.rec_off = pl.rec_words;
+    d.rec_off = pl.code_words;
     d.ls = (int32_t)h.ls;
     d.lt = (int32_t)h.lt;
     d.r = (int32_t)h.r;
     d.pad = 0;
-    pl.rec_words += wf_rec_words((int)h.ls, (int)h.lt, c);
-    const int need = (int)(h.ls + h.lt + 2 * kWfPad);
-    if (need > pl.lds_stride[c]) pl.lds_stride[c] = need;
+    if (mode == 1) pl.code_words += wf_rec_words((int)h.ls, (int)h.lt, c);
+    const int need = (int)(mode == 2 ? wf_fused_words((int)h.ls, (int)h.lt, c)
+                                     : h.ls + h.lt + 2 * kWfPad);
+    if (need > pl.lds_stride[gi]) pl.lds_stride[gi] = need;
     const int nch = wf_chunks((int)h.ls, (int)h.lt);
-    if (nch > pl.max_chunks[c]) pl.max_chunks[c] = nch;
-    if (h.ls + h.lt > pl.max_ranges[c]) pl.max_ranges[c] = (int)(h.ls + h.lt);
-    if (h.ls > 0 && h.lt > 0 && std::llabs(h.ls - h.lt) <= h.r)
-      pl.band_cells += (uint64_t)band_cells_total(h.ls, h.lt, h.r);
+    if (nch > pl.max_chunks[gi]) pl.max_chunks[gi] = nch;
+    if (h.ls + h.lt > pl.max_ranges[gi]) pl.max_ranges[gi] = (int)(h.ls + h.lt);
+    if (h.s_off + h.ls > pl.s_extent) pl.s_extent = h.s_off + h.ls;
+    if (h.t_off + h.lt > pl.t_extent) pl.t_extent = h.t_off + h.lt;
+    if (wf_has_path(h)) pl.band_cells += (uint64_t)band_cells_total(h.ls, h.lt, h.r);
   }
-  for (int c = 0; c < kWfClasses; ++c) pl.begin[c + 1] = pl.begin[c] + cnt[c];
+  for (int gi = 0; gi < kWfGroups; ++gi) pl.begin[gi + 1] = pl.begin[gi] + cnt[gi];
   pl.order.resize((size_t)n);
-  std::vector<int64_t> fill(pl.begin, pl.begin + kWfClasses);
+  std::vector<int64_t> fill(pl.begin, pl.begin + kWfGroups);
   std::vector<int32_t> idx((size_t)n);
   for (int64_t p = 0; p < n; ++p) idx[(size_t)p] = (int32_t)p;
   std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
     return hp[(size_t)x].ls + hp[(size_t)x].lt > hp[(size_t)y].ls + hp[(size_t)y].lt;
   });
-  for (int32_t p : idx) pl.order[(size_t)fill[cls[(size_t)p]]++] = p;
-}
-
-// Forward launches of a planned batch: one per class present.
-static int wf_launch_batch(eapdtw_ctx *ctx, const float *S, const float *T, const WfBatchPlan &pl,
-                           const WfPair *d_desc, const int32_t *d_order, float *out,
-                           unsigned *rec, const float *ub, unsigned long long *cnt) {
-  for (int c = 0; c < kWfClasses; ++c) {
-    const int64_t n = pl.begin[c + 1] - pl.begin[c];
-    if (n == 0) continue;
-    WfArgs a{};
-    a.S = S;
-    a.T = T;
-    a.pairs = d_desc;
-    a.order = d_order + pl.begin[c];
-    a.nitems = n;
-    a.out = out;
-    a.rec = rec;
-    a.lds_stride = pl.lds_stride[c];
-    a.ub = ub;
-    a.counters = cnt;
-    HIPCHK(launch_wf_fwd(c, rec != nullptr, a, ctx->stream));
-  }
-  return EAPDTW_OK;
+  for (int32_t p : idx) pl.order[(size_t)fill[grp[(size_t)p]]++] = p;
 }
 
 // Uploads a host array into the scratch at `off` (stream-ordered; the host
@@ -1883,6 +1918,76 @@ static int wf_launch_batch(eapdtw_ctx *ctx, const float *S, const float *T, cons
 static int upload(eapdtw_ctx *ctx, size_t off, const void *src, size_t nbytes) {
   if (nbytes == 0) return EAPDTW_OK;
   HIPCHK(hipMemcpyAsync(ctx->scratch + off, src, nbytes, hipMemcpyHostToDevice, ctx->stream));
+  return EAPDTW_OK;
+}
+
+// Device pointers of one recorded batch.
+struct WfRecPtrs {
+  unsigned *status = nullptr, *rowrng = nullptr, *colrng = nullptr, *codes = nullptr;
+};
+
+static WfRecPtrs wf_rec_ptrs(void *base, const WfRecLayout &L) {
+  char *b = static_cast<char *>(base);
+  WfRecPtrs r;
+  r.status = reinterpret_cast<unsigned *>(b + L.status);
+  r.rowrng = reinterpret_cast<unsigned *>(b + L.rowrng);
+  r.colrng = reinterpret_cast<unsigned *>(b + L.colrng);
+  r.codes = reinterpret_cast<unsigned *>(b + L.codes);
+  return r;
+}
+
+// Forward launches of a planned batch, one per launch group present; with a
+// record, the recorded modes write into it (ranges to rowrng/colrng).
+static int wf_launch_batch(eapdtw_ctx *ctx, const float *S, const float *T, const WfBatchPlan &pl,
+                           const WfPair *d_desc, const int32_t *d_order, float *out,
+                           const WfRecPtrs *rec, unsigned *rowrng, unsigned *colrng,
+                           const float *ub, unsigned long long *cnt) {
+  for (int gi = 0; gi < kWfGroups; ++gi) {
+    const int64_t n = pl.begin[gi + 1] - pl.begin[gi];
+    if (n == 0) continue;
+    const int mode = gi / kWfClasses, c = gi % kWfClasses;
+    WfArgs a{};
+    a.S = S;
+    a.T = T;
+    a.pairs = d_desc;
+    a.order = d_order + pl.begin[gi];
+    a.nitems = n;
+    a.out = out;
+    if (rec) {
+      a.rec = rec->codes;
+      a.status = rec->status;
+      a.rowrng = rowrng;
+      a.colrng = colrng;
+    }
+    a.lds_stride = pl.lds_stride[gi];
+    a.ub = ub;
+    a.counters = cnt;
+    HIPCHK(launch_wf_fwd(c, mode, a, ctx->stream));
+  }
+  return EAPDTW_OK;
+}
+
+// The walk kernel for the pairs of mode 1, one launch per class.
+static int wf_walk_batch(eapdtw_ctx *ctx, const WfBatchPlan &pl, const WfPair *d_desc,
+                         const int32_t *d_order, const WfRecPtrs &rec, unsigned *rowrng,
+                         unsigned *colrng) {
+  for (int c = 0; c < kWfClasses; ++c) {
+    const int gi = kWfClasses + c;
+    const int64_t n = pl.begin[gi + 1] - pl.begin[gi];
+    if (n == 0) continue;
+    WfWalkArgs w{};
+    w.pairs = d_desc;
+    w.npairs = (int64_t)pl.desc.size();
+    w.order = d_order + pl.begin[gi];
+    w.nitems = n;
+    w.rec = rec.codes;
+    w.status = rec.status;
+    w.rowrng = rowrng;
+    w.colrng = colrng;
+    w.max_chunks = pl.max_chunks[gi];
+    w.max_ranges = pl.max_ranges[gi];
+    HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
+  }
   return EAPDTW_OK;
 }
 
@@ -1898,7 +2003,7 @@ int eapdtw_dtw_pairs_batch(eapdtw_ctx *ctx, const float *S, int64_t s_total, con
   if (npairs == 0) return EAPDTW_OK;
   HIPCHK(hipSetDevice(ctx->device));
   WfBatchPlan pl;
-  wf_plan(hp, pl);
+  wf_plan(ctx, hp, false, pl);
   Plan sp;
   const size_t o_cnt = sp.add(kCntBytes);
   const size_t o_desc = sp.add(sizeof(WfPair) * pl.desc.size());
@@ -1912,7 +2017,7 @@ int eapdtw_dtw_pairs_batch(eapdtw_ctx *ctx, const float *S, int64_t s_total, con
   if ((rc = upload(ctx, o_ord, pl.order.data(), sizeof(int32_t) * pl.order.size()))) return rc;
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, ctx->stream));
   rc = wf_launch_batch(ctx, S, T, pl, at<WfPair>(ctx, o_desc), at<int32_t>(ctx, o_ord), out,
-                       nullptr, ub, cnt);
+                       nullptr, nullptr, nullptr, ub, cnt);
   if (rc) return rc;
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, ctx->stream));
@@ -1925,79 +2030,61 @@ int eapdtw_dtw_pairs_batch(eapdtw_ctx *ctx, const float *S, int64_t s_total, con
   return EAPDTW_OK;
 }
 
-int64_t eapdtw_dtw_batch_record_bytes(const eapdtw_pair *pairs, int64_t npairs) {
-  if (npairs < 0 || (npairs > 0 && !pairs)) return -1;
-  int64_t words = 0;
+// Validation of a recorded batch's pairs without a context (for the size query).
+static bool wf_plan_of(const eapdtw_pair *pairs, int64_t npairs, std::vector<WfHostPair> &hp) {
+  if (npairs < 0 || (npairs > 0 && !pairs)) return false;
+  hp.resize((size_t)npairs);
   for (int64_t p = 0; p < npairs; ++p) {
     const eapdtw_pair &q = pairs[p];
-    if (q.s_len < 0 || q.t_len < 0 || q.window < 0 || q.s_len > kWfMaxLen || q.t_len > kWfMaxLen)
-      return -1;
+    if (q.s_len < 0 || q.t_len < 0 || q.window < 0 || q.s_off < 0 || q.t_off < 0 ||
+        q.s_len > kWfMaxLen || q.t_len > kWfMaxLen)
+      return false;
     const int64_t r = clip_window(q.window, q.s_len, q.t_len);
-    const int c = (q.s_len == 0 || q.t_len == 0)
-                      ? 0
-                      : wf_class_for((int)q.s_len, (int)q.t_len, (int)r);
-    if (c < 0) return -1;
-    words += wf_rec_words((int)q.s_len, (int)q.t_len, c);
+    if (q.s_len > 0 && q.t_len > 0 && wf_class_for((int)q.s_len, (int)q.t_len, (int)r) < 0)
+      return false;
+    hp[(size_t)p] = WfHostPair{q.s_off, q.t_off, q.s_len, q.t_len, r};
   }
-  return words * (int64_t)sizeof(unsigned);
+  return true;
 }
 
-// Backtrack of a recorded batch into path ranges, one launch per class.
-static int wf_walk_batch(eapdtw_ctx *ctx, const WfBatchPlan &pl, const WfPair *d_desc,
-                         const int32_t *d_order, const unsigned *rec, unsigned *rowrng,
-                         unsigned *colrng) {
-  (void)d_order;
-  // the walk runs per pair; each class has its own record chunk width
-  for (int c = 0; c < kWfClasses; ++c) {
-    const int64_t n = pl.begin[c + 1] - pl.begin[c];
-    if (n == 0) continue;
-    WfWalkArgs w{};
-    w.pairs = d_desc;
-    w.npairs = (int64_t)pl.desc.size();
-    w.order = d_order + pl.begin[c];
-    w.nitems = n;
-    w.rec = rec;
-    w.rowrng = rowrng;
-    w.colrng = colrng;
-    w.max_chunks = pl.max_chunks[c];
-    w.max_ranges = pl.max_ranges[c];
-    HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
-  }
-  return EAPDTW_OK;
+int64_t eapdtw_dtw_batch_record_bytes(const eapdtw_pair *pairs, int64_t npairs) {
+  std::vector<WfHostPair> hp;
+  if (!wf_plan_of(pairs, npairs, hp)) return -1;
+  WfBatchPlan pl;
+  wf_plan(nullptr, hp, true, pl);
+  return (int64_t)wf_layout(npairs, pl.s_extent, pl.t_extent, pl.code_words).bytes;
 }
 
-// Common part of the batched forward / backward / path entry points: plan,
-// upload the descriptors and run the recording forward into `rec` (or a
-// scratch record).  Returns the scratch offsets through the plan.
+// A recorded batch: descriptors in scratch and the record's pointers (the
+// caller's record, or scratch when `record` is NULL).
 struct WfBatchRun {
   WfBatchPlan pl;
   WfPair *desc = nullptr;
   int32_t *order = nullptr;
-  unsigned *rec = nullptr;
+  WfRecPtrs rec;
   float *dist = nullptr;
-  unsigned *rowrng = nullptr, *colrng = nullptr;
 };
 
-static int wf_batch_prepare(eapdtw_ctx *ctx, const std::vector<WfHostPair> &hp, int64_t s_total,
-                            int64_t t_total, bool own_record, bool ranges, WfBatchRun &run) {
-  wf_plan(hp, run.pl);
+// `extra` bytes of scratch are reserved after the batch's buffers (offset in
+// *o_extra).
+static int wf_batch_prepare(eapdtw_ctx *ctx, const std::vector<WfHostPair> &hp, void *record,
+                            WfBatchRun &run, size_t extra = 0, size_t *o_extra = nullptr) {
+  wf_plan(ctx, hp, true, run.pl);
+  const WfRecLayout L = wf_layout((int64_t)hp.size(), run.pl.s_extent, run.pl.t_extent,
+                                  run.pl.code_words);
   Plan sp;
   const size_t o_desc = sp.add(sizeof(WfPair) * run.pl.desc.size());
   const size_t o_ord = sp.add(sizeof(int32_t) * run.pl.order.size());
-  const size_t o_rec = own_record ? sp.add(sizeof(unsigned) * (size_t)run.pl.rec_words) : 0;
   const size_t o_dist = sp.add(sizeof(float) * run.pl.desc.size());
-  const size_t o_rr = ranges ? sp.add(sizeof(unsigned) * (size_t)s_total) : 0;
-  const size_t o_cr = ranges ? sp.add(sizeof(unsigned) * (size_t)t_total) : 0;
+  const size_t o_rec = record ? 0 : sp.add(L.bytes);
+  const size_t o_x = sp.add(extra);
+  if (o_extra) *o_extra = o_x;
   int rc = ensure_scratch(ctx, sp.off);
   if (rc) return rc;
   run.desc = at<WfPair>(ctx, o_desc);
   run.order = at<int32_t>(ctx, o_ord);
-  if (own_record) run.rec = at<unsigned>(ctx, o_rec);
   run.dist = at<float>(ctx, o_dist);
-  if (ranges) {
-    run.rowrng = at<unsigned>(ctx, o_rr);
-    run.colrng = at<unsigned>(ctx, o_cr);
-  }
+  run.rec = wf_rec_ptrs(record ? record : ctx->scratch + o_rec, L);
   if ((rc = upload(ctx, o_desc, run.pl.desc.data(), sizeof(WfPair) * run.pl.desc.size())))
     return rc;
   return upload(ctx, o_ord, run.pl.order.data(), sizeof(int32_t) * run.pl.order.size());
@@ -2008,41 +2095,52 @@ int eapdtw_dtw_batch_fwd(eapdtw_ctx *ctx, const float *S, int64_t s_total, const
                          void *record) {
   CHECK_CTX();
   std::vector<WfHostPair> hp;
-  int rc = wf_validate(ctx, S, s_total, T, t_total, pairs, npairs, false, hp);
+  int rc = wf_validate(ctx, S, s_total, T, t_total, pairs, npairs, record != nullptr, hp);
   if (rc) return rc;
   if (npairs > 0 && !out) return fail(ctx, EAPDTW_EINVAL, "out is NULL");
   if (npairs == 0) return EAPDTW_OK;
   HIPCHK(hipSetDevice(ctx->device));
+  if (!record) {
+    WfBatchPlan pl;
+    wf_plan(ctx, hp, false, pl);
+    Plan sp;
+    const size_t o_desc = sp.add(sizeof(WfPair) * pl.desc.size());
+    const size_t o_ord = sp.add(sizeof(int32_t) * pl.order.size());
+    if ((rc = ensure_scratch(ctx, sp.off))) return rc;
+    if ((rc = upload(ctx, o_desc, pl.desc.data(), sizeof(WfPair) * pl.desc.size()))) return rc;
+    if ((rc = upload(ctx, o_ord, pl.order.data(), sizeof(int32_t) * pl.order.size()))) return rc;
+    return wf_launch_batch(ctx, S, T, pl, at<WfPair>(ctx, o_desc), at<int32_t>(ctx, o_ord), out,
+                           nullptr, nullptr, nullptr, nullptr, nullptr);
+  }
   WfBatchRun run;
-  if ((rc = wf_batch_prepare(ctx, hp, s_total, t_total, false, false, run))) return rc;
-  return wf_launch_batch(ctx, S, T, run.pl, run.desc, run.order, out,
-                         static_cast<unsigned *>(record), nullptr, nullptr);
+  if ((rc = wf_batch_prepare(ctx, hp, record, run))) return rc;
+  return wf_launch_batch(ctx, S, T, run.pl, run.desc, run.order, out, &run.rec, run.rec.rowrng,
+                         run.rec.colrng, nullptr, nullptr);
 }
 
-// Walk + gradient (+ the recording forward into scratch without a record).
-static int wf_batch_backward(eapdtw_ctx *ctx, const float *S, int64_t s_total, const float *T,
-                             int64_t t_total, const std::vector<WfHostPair> &hp,
-                             const void *record, const float *grad_out, float *grad_S,
-                             float *grad_T, unsigned *rowrng_out, unsigned *colrng_out) {
+// Walk (mode-1 pairs) + gradient; without a record the recording forward
+// runs first into scratch.  With rowrng_out the ranges go to the caller's
+// arrays and no gradient is made.
+static int wf_batch_backward(eapdtw_ctx *ctx, const float *S, const float *T,
+                             const std::vector<WfHostPair> &hp, void *record,
+                             const float *grad_out, float *grad_S, float *grad_T,
+                             unsigned *rowrng_out, unsigned *colrng_out) {
   WfBatchRun run;
-  const bool own = record == nullptr;
-  const bool ranges = rowrng_out == nullptr;
-  int rc = wf_batch_prepare(ctx, hp, s_total, t_total, own, ranges, run);
+  int rc = wf_batch_prepare(ctx, hp, record, run);
   if (rc) return rc;
-  const unsigned *rec = own ? run.rec : static_cast<const unsigned *>(record);
-  if (own) {
-    rc = wf_launch_batch(ctx, S, T, run.pl, run.desc, run.order, run.dist, run.rec, nullptr,
-                         nullptr);
+  unsigned *rr = rowrng_out ? rowrng_out : run.rec.rowrng;
+  unsigned *cr = colrng_out ? colrng_out : run.rec.colrng;
+  if (!record || rowrng_out) {
+    rc = wf_launch_batch(ctx, S, T, run.pl, run.desc, run.order, run.dist, &run.rec, rr, cr,
+                         nullptr, nullptr);
     if (rc) return rc;
   }
-  unsigned *rr = ranges ? run.rowrng : rowrng_out;
-  unsigned *cr = ranges ? run.colrng : colrng_out;
-  if ((rc = wf_walk_batch(ctx, run.pl, run.desc, run.order, rec, rr, cr))) return rc;
+  if ((rc = wf_walk_batch(ctx, run.pl, run.desc, run.order, run.rec, rr, cr))) return rc;
   if (!grad_S) return EAPDTW_OK;
   WfGradArgs g{};
   g.pairs = run.desc;
   g.npairs = (int64_t)hp.size();
-  g.rec = rec;
+  g.status = run.rec.status;
   g.S = S;
   g.T = T;
   g.rowrng = rr;
@@ -2065,7 +2163,7 @@ int eapdtw_dtw_batch_bwd(eapdtw_ctx *ctx, const float *S, int64_t s_total, const
   if (npairs == 0) return EAPDTW_OK;
   if (!grad_out || !grad_S || !grad_T) return fail(ctx, EAPDTW_EINVAL, "NULL gradient buffer");
   HIPCHK(hipSetDevice(ctx->device));
-  return wf_batch_backward(ctx, S, s_total, T, t_total, hp, record, grad_out, grad_S, grad_T,
+  return wf_batch_backward(ctx, S, T, hp, const_cast<void *>(record), grad_out, grad_S, grad_T,
                            nullptr, nullptr);
 }
 
@@ -2079,26 +2177,48 @@ int eapdtw_dtw_batch_path(eapdtw_ctx *ctx, const float *S, int64_t s_total, cons
   if (npairs == 0) return EAPDTW_OK;
   if (!rowrng || !colrng) return fail(ctx, EAPDTW_EINVAL, "NULL range buffer");
   HIPCHK(hipSetDevice(ctx->device));
-  return wf_batch_backward(ctx, S, s_total, T, t_total, hp, nullptr, nullptr, nullptr, nullptr,
-                           rowrng, colrng);
+  return wf_batch_backward(ctx, S, T, hp, nullptr, nullptr, nullptr, nullptr, rowrng, colrng);
 }
 
 // --------------------------------------------------------------------------- differentiable batch (equal lengths)
 
-static int wf_uniform_class(int64_t len, int64_t window, int64_t *r_out) {
+// Class of a distance-only sweep of uniform pairs (-1: unsupported).
+static int wf_uniform_class(const eapdtw_ctx *ctx, int64_t npairs, int64_t len, int64_t window,
+                            int64_t *r_out) {
   const int64_t r = clip_window(window, len, len);
   if (r_out) *r_out = r;
   if (len == 0) return 0;
   if (len > kWfMaxLen) return -1;
-  return wf_class_for((int)len, (int)len, (int)r);
+  return wf_pick(ctx, len, len, r, npairs);
+}
+
+// Class, mode (1 or 2) and record layout of a recorded sweep of uniform pairs.
+struct WfUniformRec {
+  int cls = 0, mode = 2;
+  int64_t r = 0, words = 0;
+  WfRecLayout L;
+};
+
+static bool wf_uniform_rec(int64_t npairs, int64_t len, int64_t window, int lanes,
+                           WfUniformRec &u) {
+  u.r = clip_window(window, len, len);
+  if (len > kWfMaxLen) return false;
+  if (len > 0) {
+    if (wf_class_for((int)len, (int)len, (int)u.r) < 0) return false;
+    bool fused = false;
+    u.cls = wf_path_class((int)len, (int)len, (int)u.r, npairs, lanes, &fused);
+    u.mode = fused ? 2 : 1;
+  }
+  u.words = u.mode == 1 ? wf_rec_words((int)len, (int)len, u.cls) : 0;
+  u.L = wf_layout(npairs, npairs * len, npairs * len, npairs * u.words);
+  return true;
 }
 
 int64_t eapdtw_dtw_ckpt_bytes(int64_t npairs, int64_t len, int64_t window) {
   if (npairs < 0 || len < 0 || window < 0) return -1;
-  const int c = wf_uniform_class(len, window, nullptr);
-  if (c < 0) return -1;
-  const int64_t bytes = npairs * wf_rec_words((int)len, (int)len, c) * (int64_t)sizeof(unsigned);
-  return bytes > 4 ? bytes : 4;
+  WfUniformRec u;
+  if (!wf_uniform_rec(npairs, len, window, 0, u)) return -1;
+  return (int64_t)u.L.bytes;
 }
 
 static int diff_validate(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
@@ -2107,29 +2227,35 @@ static int diff_validate(eapdtw_ctx *ctx, const float *S, const float *T, int64_
   if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
   if (npairs > INT_MAX) return fail(ctx, EAPDTW_EINVAL, "too many pairs");
   if (npairs > 0 && len > 0 && (!S || !T)) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
-  if (wf_uniform_class(len, window, nullptr) < 0)
+  WfUniformRec u;
+  if (!wf_uniform_rec(npairs, len, window, 0, u))
     return fail(ctx, EAPDTW_EINVAL,
                 "the differentiable batch supports lengths up to 8191 with at most 511 rows "
                 "active at once (min(window + 1, len) <= 511)");
   return EAPDTW_OK;
 }
 
-// Forward of uniform pairs through the wavefront kernel (record optional).
-static int wf_uniform_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
-                          int64_t len, int64_t window, float *out, unsigned *rec) {
-  int64_t r = 0;
-  const int c = wf_uniform_class(len, window, &r);
+// Recorded forward of uniform pairs into the layout u at `base`; ranges to
+// rr / cr (the record's own unless given).
+static int wf_uniform_rec_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
+                              int64_t len, const WfUniformRec &u, void *base, float *out,
+                              unsigned *rr, unsigned *cr) {
+  const WfRecPtrs p = wf_rec_ptrs(base, u.L);
   WfArgs a{};
   a.S = S;
   a.T = T;
   a.nitems = npairs;
   a.ls = a.lt = (int)len;
-  a.r = (int)r;
-  a.rec_words_u = wf_rec_words((int)len, (int)len, c);
+  a.r = (int)u.r;
+  a.rec_words_u = u.words;
   a.out = out;
-  a.rec = rec;
-  a.lds_stride = (int)(2 * len + 2 * kWfPad);
-  HIPCHK(launch_wf_fwd(c, rec != nullptr, a, ctx->stream));
+  a.rec = p.codes;
+  a.status = p.status;
+  a.rowrng = rr ? rr : p.rowrng;
+  a.colrng = cr ? cr : p.colrng;
+  a.lds_stride = (int)(u.mode == 2 ? wf_fused_words((int)len, (int)len, u.cls)
+                                   : 2 * len + 2 * kWfPad);
+  HIPCHK(launch_wf_fwd(u.cls, u.mode, a, ctx->stream));
   return EAPDTW_OK;
 }
 
@@ -2141,53 +2267,68 @@ int eapdtw_dtw_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npai
   if (npairs == 0) return EAPDTW_OK;
   if (!out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL output");
   HIPCHK(hipSetDevice(ctx->device));
-  return wf_uniform_fwd(ctx, S, T, npairs, len, window, out_dist, static_cast<unsigned *>(ckpt));
+  if (ckpt) {
+    WfUniformRec u;
+    wf_uniform_rec(npairs, len, window, (int)ctx->wf_lanes, u);
+    return wf_uniform_rec_fwd(ctx, S, T, npairs, len, u, ckpt, out_dist, nullptr, nullptr);
+  }
+  int64_t r = 0;
+  const int c = wf_uniform_class(ctx, npairs, len, window, &r);
+  WfArgs a{};
+  a.S = S;
+  a.T = T;
+  a.nitems = npairs;
+  a.ls = a.lt = (int)len;
+  a.r = (int)r;
+  a.out = out_dist;
+  a.lds_stride = (int)(2 * len + 2 * kWfPad);
+  HIPCHK(launch_wf_fwd(c, 0, a, ctx->stream));
+  return EAPDTW_OK;
 }
 
-// Walk + gradient of uniform pairs (recording forward into scratch when no
-// record is given); with rowrng_out the ranges go there and no gradient is made.
+// Walk (mode 1) + gradient of uniform pairs; without a record the recorded
+// forward runs first into scratch.  With rowrng_out the ranges go there and
+// no gradient is made.
 static int wf_uniform_backward(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npairs,
                                int64_t len, int64_t window, const void *record,
                                const float *grad_out, float *grad_S, float *grad_T,
                                unsigned *rowrng_out, unsigned *colrng_out, float *dist_out) {
-  int64_t r = 0;
-  const int c = wf_uniform_class(len, window, &r);
-  const int64_t words = wf_rec_words((int)len, (int)len, c);
-  const bool own = record == nullptr;
-  const bool ranges = rowrng_out == nullptr;
+  WfUniformRec u;
+  wf_uniform_rec(npairs, len, window, (int)ctx->wf_lanes, u);
   Plan sp;
-  const size_t o_rec = own ? sp.add(sizeof(unsigned) * (size_t)(npairs * words)) : 0;
   const size_t o_dist = sp.add(sizeof(float) * (size_t)npairs);
-  const size_t o_rr = ranges ? sp.add(sizeof(unsigned) * (size_t)(npairs * len)) : 0;
-  const size_t o_cr = ranges ? sp.add(sizeof(unsigned) * (size_t)(npairs * len)) : 0;
+  const size_t o_rec = record ? 0 : sp.add(u.L.bytes);
   int rc = ensure_scratch(ctx, sp.off);
   if (rc) return rc;
-  const unsigned *rec = own ? at<unsigned>(ctx, o_rec) : static_cast<const unsigned *>(record);
-  if (own) {
-    rc = wf_uniform_fwd(ctx, S, T, npairs, len, window, dist_out ? dist_out : at<float>(ctx, o_dist),
-                        at<unsigned>(ctx, o_rec));
+  void *base = record ? const_cast<void *>(record) : ctx->scratch + o_rec;
+  const WfRecPtrs p = wf_rec_ptrs(base, u.L);
+  unsigned *rr = rowrng_out ? rowrng_out : p.rowrng;
+  unsigned *cr = colrng_out ? colrng_out : p.colrng;
+  if (!record) {
+    rc = wf_uniform_rec_fwd(ctx, S, T, npairs, len, u, base,
+                            dist_out ? dist_out : at<float>(ctx, o_dist), rr, cr);
     if (rc) return rc;
   }
-  unsigned *rr = ranges ? at<unsigned>(ctx, o_rr) : rowrng_out;
-  unsigned *cr = ranges ? at<unsigned>(ctx, o_cr) : colrng_out;
-  WfWalkArgs w{};
-  w.npairs = npairs;
-  w.nitems = npairs;
-  w.ls = w.lt = (int)len;
-  w.r = (int)r;
-  w.rec_words_u = words;
-  w.rec = rec;
-  w.rowrng = rr;
-  w.colrng = cr;
-  w.max_chunks = wf_chunks((int)len, (int)len);
-  w.max_ranges = (int)(2 * len);
-  HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
+  if (u.mode == 1) {
+    WfWalkArgs w{};
+    w.npairs = npairs;
+    w.nitems = npairs;
+    w.ls = w.lt = (int)len;
+    w.r = (int)u.r;
+    w.rec_words_u = u.words;
+    w.rec = p.codes;
+    w.status = p.status;
+    w.rowrng = rr;
+    w.colrng = cr;
+    w.max_chunks = wf_chunks((int)len, (int)len);
+    w.max_ranges = (int)(2 * len);
+    HIPCHK(launch_wf_walk(kWfG[u.cls] * kWfNC[u.cls], w, ctx->stream));
+  }
   if (!grad_S) return EAPDTW_OK;
   WfGradArgs g{};
   g.npairs = npairs;
   g.ls = g.lt = (int)len;
-  g.rec_words_u = words;
-  g.rec = rec;
+  g.status = p.status;
   g.S = S;
   g.T = T;
   g.rowrng = rr;
@@ -2233,54 +2374,35 @@ int eapdtw_dba_step(eapdtw_ctx *ctx, const float *B, int64_t lb, const float *X,
   if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
   if (!B || !X || !out_B) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
   if (n > INT_MAX / 2) return fail(ctx, EAPDTW_EINVAL, "too many series");
-  if (std::llabs(lb - len) > clip_window(window, lb, len))
-    return fail(ctx, EAPDTW_EINVAL, "no warping path: |lb - len| exceeds the window");
   const int64_t r = clip_window(window, lb, len);
+  if (std::llabs(lb - len) > r)
+    return fail(ctx, EAPDTW_EINVAL, "no warping path: |lb - len| exceeds the window");
   if (lb > kWfMaxLen || len > kWfMaxLen || wf_class_for((int)lb, (int)len, (int)r) < 0)
     return fail(ctx, EAPDTW_EINVAL, "more than 511 rows active at once, or series too long");
   HIPCHK(hipSetDevice(ctx->device));
-  const int c = wf_class_for((int)lb, (int)len, (int)r);
-  const int64_t words = wf_rec_words((int)lb, (int)len, c);
+  // the pairs (B, X[p]) as a batch over a broadcast copy of B
+  std::vector<WfHostPair> hp((size_t)n);
+  for (int64_t p = 0; p < n; ++p) hp[(size_t)p] = WfHostPair{p * lb, p * len, lb, len, r};
   const int64_t nchunk = (n + kDbaPairs - 1) / kDbaPairs;
-  Plan sp;
-  const size_t o_Bx = sp.add(sizeof(float) * (size_t)(n * lb));
-  const size_t o_rec = sp.add(sizeof(unsigned) * (size_t)(n * words));
-  const size_t o_dist = sp.add(sizeof(float) * (size_t)n);
-  const size_t o_rr = sp.add(sizeof(unsigned) * (size_t)(n * lb));
-  const size_t o_cr = sp.add(sizeof(unsigned) * (size_t)(n * len));
-  const size_t o_ps = sp.add(sizeof(double) * (size_t)(nchunk * lb));
-  const size_t o_pc = sp.add(sizeof(double) * (size_t)(nchunk * lb));
-  int rc = ensure_scratch(ctx, sp.off);
+  // scratch beside the batch: the broadcast copy of B and the partial sums
+  const size_t b_Bx = align256(sizeof(float) * (size_t)(n * lb));
+  const size_t b_p = align256(sizeof(double) * (size_t)(nchunk * lb));
+  WfBatchRun run;
+  size_t o_x = 0;
+  int rc = wf_batch_prepare(ctx, hp, nullptr, run, b_Bx + 2 * b_p, &o_x);
   if (rc) return rc;
-  // the barycentre is the row series of every pair
-  HIPCHK(launch_broadcast_rows(B, lb, n, at<float>(ctx, o_Bx), ctx->stream));
-  WfArgs a{};
-  a.S = at<float>(ctx, o_Bx);
-  a.T = X;
-  a.nitems = n;
-  a.ls = (int)lb;
-  a.lt = (int)len;
-  a.r = (int)r;
-  a.rec_words_u = words;
-  a.out = at<float>(ctx, o_dist);
-  a.rec = at<unsigned>(ctx, o_rec);
-  a.lds_stride = (int)(lb + len + 2 * kWfPad);
-  HIPCHK(launch_wf_fwd(c, true, a, ctx->stream));
-  WfWalkArgs w{};
-  w.npairs = n;
-  w.nitems = n;
-  w.ls = (int)lb;
-  w.lt = (int)len;
-  w.r = (int)r;
-  w.rec_words_u = words;
-  w.rec = a.rec;
-  w.rowrng = at<unsigned>(ctx, o_rr);
-  w.colrng = at<unsigned>(ctx, o_cr);
-  w.max_chunks = wf_chunks((int)lb, (int)len);
-  w.max_ranges = (int)(lb + len);
-  HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
-  HIPCHK(launch_wf_dba(X, n, (int)len, (int)lb, w.rowrng, a.rec, words, at<double>(ctx, o_ps),
-                       at<double>(ctx, o_pc), nchunk, out_B, out_count, ctx->stream));
+  const size_t o_Bx = o_x, o_ps = o_x + b_Bx, o_pc = o_ps + b_p;
+  float *Bx = at<float>(ctx, o_Bx);
+  HIPCHK(launch_broadcast_rows(B, lb, n, Bx, ctx->stream));
+  rc = wf_launch_batch(ctx, Bx, X, run.pl, run.desc, run.order, run.dist, &run.rec,
+                       run.rec.rowrng, run.rec.colrng, nullptr, nullptr);
+  if (rc) return rc;
+  if ((rc = wf_walk_batch(ctx, run.pl, run.desc, run.order, run.rec, run.rec.rowrng,
+                          run.rec.colrng)))
+    return rc;
+  HIPCHK(launch_wf_dba(X, n, (int)len, (int)lb, run.rec.rowrng, run.rec.status,
+                       at<double>(ctx, o_ps), at<double>(ctx, o_pc), nchunk, out_B, out_count,
+                       ctx->stream));
   return EAPDTW_OK;
 }
 

@@ -24,19 +24,22 @@ struct WfPair {
   int32_t ls, lt, r, pad;
 };
 
-// Kernel classes: lanes per pair G and cell slots per lane NC.  A pair needs
-// G * NC >= min(r+1, ls, lt) + 1 (r clipped to max(ls, lt) - 1), and its two
-// series must fit the class's LDS share (G = 16: four pairs per wave).
-constexpr int kWfClasses = 7;
-constexpr int kWfG[kWfClasses] = {16, 16, 16, 64, 64, 64, 64};
-constexpr int kWfNC[kWfClasses] = {1, 2, 4, 1, 2, 4, 8};
+// Kernel classes: lanes per pair G and cell slots per lane NC, by lane-slots
+// P = G NC.  A pair needs P >= min(r+1, ls, lt) + 1 (r clipped to
+// max(ls, lt) - 1), and its two series must fit the class's LDS share
+// (64 / G pairs per wave).
+constexpr int kWfClasses = 9;
+constexpr int kWfG[kWfClasses] = {16, 16, 32, 16, 32, 64, 64, 64, 64};
+constexpr int kWfNC[kWfClasses] = {1, 2, 1, 4, 2, 1, 2, 4, 8};
 constexpr int kWfMaxP = 512;
 constexpr int kWfChunk = 16;               // steps per direction word (2 bits each)
-constexpr int kWfRecHead = 64;             // status words before a pair's direction chunks
 constexpr int kWfLdsFloats = 16384;        // LDS of one wave (64 KB)
 constexpr int kWfPad = kWfChunk + 1;       // guard cells on each side of a staged T
 constexpr int kWfMaxLen = 8191;            // longest series of a wavefront pair
 constexpr int kDbaPairs = 64;              // pairs per partial sum of the DBA update
+// Waves a launch should reach: two per SIMD lets the SIMDs issue VALU
+// instructions of two waves in the same cycle.
+constexpr int64_t kWfTargetWaves = 2048;
 
 // Status word of a pair's record.
 enum WfStatus : unsigned { kWfOk = 1u, kWfNoPath = 2u, kWfNonFinite = 3u };
@@ -48,15 +51,8 @@ __host__ __device__ inline int wf_active_rows(int ls, int lt, int r) {
   return a;
 }
 
-// Class of a pair (r clipped), or -1 when no class holds it.
-__host__ inline int wf_class_for(int ls, int lt, int r) {
-  const int need = wf_active_rows(ls, lt, r) + 1;
-  for (int c = 0; c < kWfClasses; ++c) {
-    const int G = kWfG[c], P = G * kWfNC[c];
-    const int per = kWfLdsFloats / (kWave / G);
-    if (P >= need && ls + lt + 2 * kWfPad <= per) return c;
-  }
-  return -1;
+__host__ inline bool wf_plain_fits(int ls, int lt, int cls) {
+  return (int64_t)(ls + lt + 2 * kWfPad) * (kWave / kWfG[cls]) <= kWfLdsFloats;
 }
 
 __host__ __device__ inline int64_t wf_steps(int ls, int lt) { return (int64_t)ls + lt - 1; }
@@ -67,11 +63,67 @@ __host__ __device__ inline int wf_chunks(int ls, int lt) {
   return ns > 0 ? (int)((ns + kWfChunk - 1) / kWfChunk) : 0;
 }
 
-// Words of a pair's direction record in class c: the status head plus one
-// word per lane-slot and chunk of kWfChunk steps.
+// Code words of a pair's direction record in class c: one word per lane-slot
+// and chunk of kWfChunk steps.
 __host__ inline int64_t wf_rec_words(int ls, int lt, int cls) {
   const int64_t P = (int64_t)kWfG[cls] * kWfNC[cls];
-  return kWfRecHead + (int64_t)wf_chunks(ls, lt) * P;
+  return (int64_t)wf_chunks(ls, lt) * P;
+}
+
+// LDS words of one group in a forward of mode 2 (series, guards, code words
+// and path ranges) and whether a wave of class c holds them.
+__host__ inline int64_t wf_fused_words(int ls, int lt, int cls) {
+  return (int64_t)ls + lt + 2 * kWfPad + wf_rec_words(ls, lt, cls) + ls + lt;
+}
+// (a mode-2 wave keeps kWfScratchWords after its groups' regions: 9 words
+// per lane)
+constexpr int kWfScratchWords = 9 * kWave;
+__host__ inline bool wf_fused_fits(int ls, int lt, int cls) {
+  return wf_fused_words(ls, lt, cls) * (kWave / kWfG[cls]) <= kWfLdsFloats - kWfScratchWords;
+}
+
+// Class of a pair in a launch of about `npairs` pairs (0: many): the fewest
+// lane-slots that hold the pair; among classes with as many, the most cell
+// slots per lane (more independent work per lane) that still gives the
+// launch kWfTargetWaves waves, else the one with the most waves.  `lanes`
+// (16, 32, 64) restricts G; `fused` asks for a class whose codes fit in LDS.
+// -1 when no class qualifies.
+__host__ inline int wf_choose(int ls, int lt, int r, int64_t npairs, int lanes, bool fused) {
+  const int need = wf_active_rows(ls, lt, r) + 1;
+  int best = -1;
+  for (int c = 0; c < kWfClasses; ++c) {
+    const int P = kWfG[c] * kWfNC[c];
+    if (P < need || (lanes && kWfG[c] != lanes) || !wf_plain_fits(ls, lt, c)) continue;
+    if (fused && !wf_fused_fits(ls, lt, c)) continue;
+    if (best < 0) {
+      best = c;
+      continue;
+    }
+    if (P > kWfG[best] * kWfNC[best]) break;  // classes are ordered by P
+    const int64_t gb = kWave / kWfG[best], gc = kWave / kWfG[c];
+    const int64_t wb = npairs > 0 ? (npairs + gb - 1) / gb : kWfTargetWaves;
+    const int64_t wc = npairs > 0 ? (npairs + gc - 1) / gc : kWfTargetWaves;
+    const bool ok_b = wb >= kWfTargetWaves, ok_c = wc >= kWfTargetWaves;
+    if ((ok_c && !ok_b) || (ok_c && ok_b && kWfNC[c] > kWfNC[best]) ||
+        (!ok_c && !ok_b && wc > wb))
+      best = c;
+  }
+  return best;
+}
+
+// Class of a pair (r clipped) by size, or -1 when no class holds it.
+__host__ inline int wf_class_for(int ls, int lt, int r) { return wf_choose(ls, lt, r, 0, 0, false); }
+
+// Class of a pair whose path is wanted: the chosen class that keeps its codes
+// in LDS (*fused = true), else the chosen class (codes in memory).  `lanes`
+// (16, 32, 64; 0: any) picks the lanes per pair among the classes that keep
+// the codes in LDS, so that the record's size does not depend on it.
+__host__ inline int wf_path_class(int ls, int lt, int r, int64_t npairs, int lanes, bool *fused) {
+  const int c = wf_choose(ls, lt, r, npairs, 0, true);
+  *fused = c >= 0;
+  if (c < 0) return wf_choose(ls, lt, r, npairs, 0, false);
+  const int cl = lanes ? wf_choose(ls, lt, r, npairs, lanes, true) : -1;
+  return cl >= 0 ? cl : c;
 }
 
 struct WfArgs {
@@ -80,16 +132,20 @@ struct WfArgs {
   const int32_t *order;      // pair of launch item q (nullptr: q)
   int64_t nitems;            // pairs of this launch
   int ls, lt, r;             // uniform pairs: pair p = S[p ls ..], T[p lt ..]
-  int64_t rec_words_u;       // uniform pairs: record words per pair
+  int64_t rec_words_u;       // uniform pairs: code words per pair
   float *out;                // distances [pair]
-  unsigned *rec;             // direction record (nullptr: distances only)
-  int lds_stride;            // floats of LDS per group (>= ls + lt + 2 kWfPad)
+  unsigned *rec;             // mode 1: code words (pair p's at rec_off)
+  unsigned *status;          // modes 1, 2: WfStatus [pair]
+  unsigned *rowrng, *colrng; // mode 2: path ranges, pool-shaped (as the walk's)
+  int lds_stride;            // floats of LDS per group (>= ls + lt + 2 kWfPad;
+                             // mode 2: wf_fused_words)
   const float *ub;           // early-abandoning bound [pair] (nullptr: none; not with rec)
   unsigned long long *counters;  // kCntEvaluated / kCntComputed / kCntAbandoned (nullable)
 };
 
-// Forward sweep of one class; with a record also the 2-bit argmin codes.
-hipError_t launch_wf_fwd(int cls, bool record, const WfArgs &a, hipStream_t st);
+// Forward sweep of one class: mode 0 distances, 1 also the 2-bit argmin
+// codes, 2 also the path ranges (codes kept in LDS).
+hipError_t launch_wf_fwd(int cls, int mode, const WfArgs &a, hipStream_t st);
 
 // Backtrack of every pair from its record: per row i the column range of its
 // path cells (jlo | jhi << 16 at rowrng[s_off + i]) and per column j the row
@@ -101,7 +157,8 @@ struct WfWalkArgs {
   int64_t nitems;            // pairs of this launch
   int ls, lt, r;             // uniform pairs (pairs == nullptr)
   int64_t rec_words_u;
-  const unsigned *rec;
+  const unsigned *rec;       // code words
+  const unsigned *status;    // WfStatus [pair]
   unsigned *rowrng, *colrng;
   int max_chunks;            // record chunks of the launch's longest pair
   int max_ranges;            // ls + lt of the launch's longest pair
@@ -118,8 +175,7 @@ struct WfGradArgs {
   const WfPair *pairs;
   int64_t npairs;
   int ls, lt;
-  int64_t rec_words_u;
-  const unsigned *rec;
+  const unsigned *status;    // WfStatus [pair]
   const float *S, *T;
   const unsigned *rowrng, *colrng;
   const float *gout;
@@ -133,8 +189,7 @@ hipError_t launch_wf_grad(const WfGradArgs &a, hipStream_t st);
 // (partial [nchunk][lb], float64), then their totals in chunk order:
 // out_B[i] = sum / count.
 hipError_t launch_wf_dba(const float *X, int64_t n, int len, int lb, const unsigned *rowrng,
-                         const unsigned *rec, int64_t rec_words_u, double *partial_sum,
-                         double *partial_cnt, int64_t nchunk, float *out_B, float *out_count,
-                         hipStream_t st);
+                         const unsigned *status, double *partial_sum, double *partial_cnt,
+                         int64_t nchunk, float *out_B, float *out_count, hipStream_t st);
 
 }  // namespace eapdtw

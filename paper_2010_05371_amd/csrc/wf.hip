@@ -20,14 +20,35 @@ namespace {
 constexpr int kNever = 0x3fffffff;
 
 // rotation by one lane inside groups of G lanes (lane g reads lane g-1, lane 0
-// reads lane G-1): DPP row_ror:1 for G = 16, wave_ror:1 for G = 64
+// reads lane G-1): DPP row_ror:1 for G = 16, wave_ror:1 for G = 64.  For
+// G = 32 the wave_ror:1 result is right except on lanes 0 and 32, which hold
+// lanes 63 and 31; group_fix swaps them (below).
 template <int G>
 __device__ __forceinline__ float rot1(float x) {
-  static_assert(G == 16 || G == 64, "groups of 16 or 64 lanes");
+  static_assert(G == 16 || G == 32 || G == 64, "groups of 16, 32 or 64 lanes");
   constexpr int ctrl = (G == 16) ? 0x121 : 0x13C;
-  // every lane reads a lane of its own group: the old value is never used
+  // every lane reads a lane of the wave: the old value is never used
   return __builtin_bit_cast(
       float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), ctrl, 0xf, 0xf, true));
+}
+
+// rotation by one lane the other way (lane g reads lane g+1, lane G-1 reads
+// lane 0): row_ror:15 for G = 16, wave_rol:1 for G = 32 and 64 (G = 32: lanes
+// 31 and 63 then need group_fix32 with the lanes G-1 taking the other half).
+template <int G>
+__device__ __forceinline__ uint32_t rot1_back(uint32_t x) {
+  static_assert(G == 16 || G == 32 || G == 64, "groups of 16, 32 or 64 lanes");
+  constexpr int ctrl = (G == 16) ? 0x12F : 0x134;
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, 0xf, 0xf, true);
+}
+
+// G = 32: lanes 0 and 32 of a wave_ror:1 result y take each other's values.
+// v_permlane32_swap of (y, y) gives lo = (y[0..31], y[0..31]) and
+// hi = (y[32..63], y[32..63]); lanes 1..31 and 32 read lo, lanes 0 and
+// 33..63 read hi (half_lo: all ones where lo is read).
+__device__ __forceinline__ uint32_t group_fix32(uint32_t y, uint32_t half_lo) {
+  const auto r = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+  return (half_lo & r[0]) | (~half_lo & r[1]);
 }
 
 struct PairView {
@@ -87,9 +108,12 @@ __device__ __forceinline__ bool has_path(const PairView &v) {
 // steps apart, so a chunk involves at most its current row a and the next
 // row b = a + P: per chunk it prepares b's state, the steps that use b, and
 // the mask of its active steps; a step then only selects between the two.
-// With REC every cell's argmin code goes to the record: chunk k = (t + e) / 16
-// is word rec[rec_off + kWfRecHead + k P + c G + g], step t at bits
-// 2 (15 - (t + e) % 16).
+// MODE 0 computes distances only.  MODE 1 also writes every cell's argmin
+// code to the record: chunk k = (t + e) / 16 is word rec[rec_off + k P + c G + g],
+// step t at bits 2 ((t + e) % 16).  MODE 2 keeps those words in the
+// group's LDS and, after the sweep, follows them back from (ls-1, lt-1) itself
+// (the backtrack of wf_walk_kernel, one path cell per iteration on the group's
+// lanes) and writes the path ranges.
 
 // (m & a) | (~m & b): with m all ones or all zeros, a or b (v_bfi_b32)
 __device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
@@ -114,8 +138,9 @@ __device__ __forceinline__ unsigned bit_range(int lo, int hi) {
 
 __device__ __forceinline__ int wf_lead(int ns) { return (kWfChunk - ns % kWfChunk) % kWfChunk; }
 
-template <int G, int NC, bool REC>
+template <int G, int NC, int MODE>
 __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
+  constexpr bool REC = MODE != 0;
   constexpr int P = G * NC;
   constexpr int GPW = kWave / G;
   extern __shared__ float lds[];
@@ -197,9 +222,15 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
     cur[c] = (l == P - 1 && e >= 1) ? 0.0f : qnan;
     up[c] = (l == 0 && e == 0) ? 0.0f : qnan;
   }
-  unsigned *rec = REC ? a.rec + v.rec_off + kWfRecHead : nullptr;
+  const int nch = run ? wf_chunks(ls, lt) : 0;
+  // MODE 2: the group's code words and path ranges follow its series in LDS
+  unsigned *codes_l = reinterpret_cast<unsigned *>(Tl + lt + kWfPad);
+  unsigned *rr_l = codes_l + nch * P;
+  unsigned *cr_l = rr_l + ls;
+  unsigned *rec = MODE == 1 ? a.rec + v.rec_off : codes_l;
   const float *tbase = Tl;
   const uint32_t lane0 = g == 0 ? ~0u : 0u;
+  const uint32_t half_lo = ((lane < 32) != (g == 0)) ? ~0u : 0u;  // G = 32 only
   // Early abandoning (Section 2.2): every warping path visits one of any two
   // consecutive anti-diagonals, and cell values never decrease along a path,
   // so once every cell of the chunk's last two anti-diagonals exceeds the
@@ -261,7 +292,8 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
       }
 #pragma unroll
       for (int u = 0; u < SUB; ++u) {
-        if (s0 + u == kWfChunk - 1) {
+        const int s = s0 + u;
+        if (s == kWfChunk - 1) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) c14[c] = cur[c];
         }
@@ -272,9 +304,10 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
         for (int c = 0; c < NC; ++c) {
           // the previous row: the previous lane of this slot, or for lane 0 the
           // last lane of the previous slot
-          const uint32_t topb =
+          uint32_t topb =
               NC > 1 ? bit_select(lane0, cell_bits(rot[(c + NC - 1) % NC]), cell_bits(rot[c]))
                      : cell_bits(rot[c]);
+          if constexpr (G == 32) topb = group_fix32(topb, half_lo);
           // cells are never negative (NaN: inactive): the unsigned order of
           // the bits is their order
           const uint32_t upb = cell_bits(up[c]);
@@ -283,7 +316,7 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
             // code 0: diagonal, 1: (i-1, j), 2: (i, j-1), ties in that order
             const uint32_t x = umin2(upb - mb, 1u);
             const uint32_t y = umin2(topb - mb, x);
-            cw[c] = (cw[c] << 2) + x + y;
+            cw[c] |= (x + y) << (2 * s);
           }
           up[c] = __uint_as_float(topb);
           cur[c] = __builtin_fmaf(dv[c][u], dv[c][u], __uint_as_float(mb));
@@ -292,7 +325,7 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
     }
     if constexpr (REC) {
       if (tau0 < nsp) {
-        unsigned *w = rec + (int64_t)(tau0 / kWfChunk) * P + g;
+        unsigned *w = rec + (tau0 / kWfChunk) * P + g;
 #pragma unroll
         for (int c = 0; c < NC; ++c) w[c * G] = cw[c];
       }
@@ -351,6 +384,111 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
       if (ab) atomicAdd(&cs[kCntAbandoned], (unsigned long long)ab);
     }
   }
+  if constexpr (MODE == 2) {
+    // Reverse sweep.  The path is the chain of recorded predecessors from
+    // (ls-1, lt-1) back to (0, 0); it holds at most one cell per
+    // anti-diagonal.  Sweeping the steps backwards in the same lane layout,
+    // a cell is on the path when a path cell names it: its own cell of step
+    // t+1 (i, j+1) with code 2, the next lane-slot's cell of step t+1 (i+1, j)
+    // with code 1, or that lane-slot's cell of step t+2 (i+1, j+1) with code
+    // 0.  A path cell emits the bit of its code (bit 0 diagonal, 1 up, 2 left)
+    // and the emissions rotate one lane-slot back per step, so the codes are
+    // read from LDS once per chunk and the chain costs a few instructions per
+    // step, with no memory access on it.  Each step's path cell leaves its
+    // lane-slot at the step's halfword of `pslot` (in the series' LDS, no
+    // longer read); a second pass turns each path cell and its neighbours on
+    // the chain into the row and column ranges.
+    constexpr unsigned kNoCell = 0xFFFFu;
+    unsigned *pw = reinterpret_cast<unsigned *>(Sl);
+    for (int k = g; k < (nsp + 1) / 2; k += G) pw[k] = 0xFFFFFFFFu;
+    __syncthreads();
+    const uint32_t pslot = lds_addr(Sl);
+    // lanes off the path store to a word of their own (9-word stride: 64 banks)
+    const uint32_t scratch = lds_addr(lds + GPW * a.lds_stride) + 36u * (uint32_t)lane;
+    const uint32_t lane_last = g == G - 1 ? ~0u : 0u;
+    const uint32_t half_lo_r = ((lane < 32) != (g == G - 1)) ? ~0u : 0u;  // G = 32 only
+    uint32_t own[NC], rcv[NC], rcvp[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) own[c] = rcv[c] = rcvp[c] = 0u;
+    const unsigned *cw_l = codes_l;
+#pragma unroll 1
+    for (int tau0 = nsw - kWfChunk; tau0 >= 0; tau0 -= kWfChunk) {
+      const bool mine = tau0 < nsp;
+      const int k = mine ? tau0 / kWfChunk : 0;
+      uint32_t cw[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const uint32_t w = cw_l[k * P + c * G + g];
+        cw[c] = mine ? w : 0u;
+        // the path's last cell: named by a virtual cell (ls-1, lt)
+        if (tau0 + kWfChunk == nsp && c * G + g == le) own[c] |= 4u;
+      }
+      const uint32_t base = pslot + 2u * (uint32_t)tau0;
+#pragma unroll
+      for (int s = kWfChunk - 1; s >= 0; --s) {
+        uint32_t emit[NC], on_any = 0u, slot = 0u;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const uint32_t on = umin2((own[c] & 4u) | (rcv[c] & 2u) | (rcvp[c] & 1u), 1u);
+          emit[c] = on << ((cw[c] >> (2 * s)) & 3u);
+          own[c] = emit[c];
+          on_any |= on;
+          if (NC > 1) slot = on ? (uint32_t)(c * G + g) : slot;
+        }
+        const uint32_t at = (on_any ? base : scratch) + 2u * (uint32_t)s;
+        *(__attribute__((address_space(3))) uint16_t *)(uintptr_t)at =
+            (uint16_t)(NC > 1 ? slot : (uint32_t)g);
+        uint32_t r[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] = rot1_back<G>(emit[c]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          // from the next lane-slot: the next lane, or for lane G-1 lane 0 of
+          // the next slot
+          uint32_t x = NC > 1 ? bit_select(lane_last, r[(c + 1) % NC], r[c]) : r[c];
+          if constexpr (G == 32) x = group_fix32(x, half_lo_r);
+          rcvp[c] = rcv[c];
+          rcv[c] = x;
+        }
+      }
+    }
+    __syncthreads();
+    // Ranges.  A path cell (i, j) at step t opens its row's range unless the
+    // path came from (i, j-1) (same lane-slot at t-1), closes it unless the
+    // path goes on to (i, j+1) (same lane-slot at t+1); it opens its column's
+    // range unless the path came from (i-1, j) (another lane-slot at t-1), and
+    // closes it unless it goes on to (i+1, j).  (0, 0) opens both, the last
+    // cell closes both.  The cell's row is the one active row of its
+    // lane-slot at step t.
+    if (run) {
+      const uint16_t *ps = reinterpret_cast<const uint16_t *>(Sl);
+      uint16_t *rr16 = reinterpret_cast<uint16_t *>(rr_l);
+      uint16_t *cr16 = reinterpret_cast<uint16_t *>(cr_l);
+      for (int tau = e + g; tau < nsp; tau += G) {
+        const int t = tau - e;
+        const unsigned v = ps[tau];
+        if (v == kNoCell) continue;
+        int lo = (t - r + 1) >> 1;  // first active row of step t
+        lo = lo > t - (lt - 1) ? lo : t - (lt - 1);
+        lo = lo > 0 ? lo : 0;
+        const int i = lo + (((int)v - lo) & (P - 1));
+        const int j = t - i;
+        const unsigned vp = t >= 1 ? ps[tau - 1] : kNoCell;
+        const unsigned vn = t + 1 < ns ? ps[tau + 1] : kNoCell;
+        if (vp != v) rr16[2 * i] = (uint16_t)j;
+        if (vn != v) rr16[2 * i + 1] = (uint16_t)j;
+        if (vp == v || vp == kNoCell) cr16[2 * j] = (uint16_t)i;
+        if (vn == v || vn == kNoCell) cr16[2 * j + 1] = (uint16_t)i;
+      }
+    }
+    __syncthreads();
+    if (run) {
+      unsigned *grr = a.rowrng + v.s_off;
+      unsigned *gcr = a.colrng + v.t_off;
+      for (int k = g; k < ls; k += G) grr[k] = rr_l[k];
+      for (int k = g; k < lt; k += G) gcr[k] = cr_l[k];
+    }
+  }
   if (!valid) return;
   if (g == le % G) {
     float d;
@@ -363,7 +501,7 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
       d = (ls == 0 && lt == 0) ? 0.0f : kInf;
     }
     a.out[p] = d;
-    if constexpr (REC) a.rec[v.rec_off] = run ? kWfOk : (pair_bad ? kWfNonFinite : kWfNoPath);
+    if constexpr (REC) a.status[p] = run ? kWfOk : (pair_bad ? kWfNonFinite : kWfNoPath);
   }
 }
 
@@ -388,13 +526,12 @@ __global__ __launch_bounds__(64) void wf_walk_kernel(WfWalkArgs a) {
   if (q >= a.nitems) return;
   const int64_t p = a.order ? (int64_t)a.order[q] : q;
   const PairView v = pair_view(a.pairs, p, a.ls, a.lt, a.r, a.rec_words_u);
-  const unsigned *rec = a.rec + v.rec_off;
-  if (rec[0] != kWfOk) return;  // no path or non-finite input: the gradient kernel handles it
+  if (a.status[p] != kWfOk) return;  // no path or non-finite input: the gradient kernel handles it
   unsigned *win = wsh;
   const bool in_lds = a.lds_ranges != 0;
   unsigned *rr = in_lds ? wsh + a.win_words : a.rowrng + v.s_off;
   unsigned *cr = in_lds ? rr + v.ls : a.colrng + v.t_off;
-  const unsigned *chunks = rec + kWfRecHead;
+  const unsigned *chunks = a.rec + v.rec_off;
   const int lead = wf_lead((int)wf_steps(v.ls, v.lt));
   int i = v.ls - 1, j = v.lt - 1;
   int row_hi = j, col_hi = i;
@@ -436,7 +573,7 @@ __global__ __launch_bounds__(64) void wf_walk_kernel(WfWalkArgs a) {
     } else {
       word = __builtin_amdgcn_readfirstlane(win[(ch - w0) * P + i % P]);
     }
-    unsigned code = (word >> (2 * (kWfChunk - 1 - t % kWfChunk))) & 3u;
+    unsigned code = (word >> (2 * (t % kWfChunk))) & 3u;
     code = i == 0 ? 2u : (j == 0 ? 1u : code);
     // code 0: diagonal (i-1, j-1), 1: (i-1, j), 2: (i, j-1)
     if (lane == 0) {
@@ -469,8 +606,8 @@ __global__ __launch_bounds__(64) void wf_walk_kernel(WfWalkArgs a) {
 __global__ __launch_bounds__(256) void wf_grad_kernel(WfGradArgs a) {
   const int64_t p = blockIdx.x;
   if (p >= a.npairs) return;
-  const PairView v = pair_view(a.pairs, p, a.ls, a.lt, 0, a.rec_words_u);
-  const unsigned st = a.rec[v.rec_off];
+  const PairView v = pair_view(a.pairs, p, a.ls, a.lt, 0, 0);
+  const unsigned st = a.status[p];
   const float *Sp = a.S + v.s_off;
   const float *Tp = a.T + v.t_off;
   float *gS = a.gS + v.s_off;
@@ -512,8 +649,7 @@ __global__ __launch_bounds__(256) void wf_grad_kernel(WfGradArgs a) {
 
 __global__ __launch_bounds__(256) void wf_dba_partial_kernel(const float *X, int64_t n, int len,
                                                              int lb, const unsigned *rowrng,
-                                                             const unsigned *rec,
-                                                             int64_t rec_words_u, double *psum,
+                                                             const unsigned *status, double *psum,
                                                              double *pcnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = blockIdx.y;
@@ -521,7 +657,7 @@ __global__ __launch_bounds__(256) void wf_dba_partial_kernel(const float *X, int
   double s = 0.0, c = 0.0;
   const int64_t p1 = (k + 1) * kDbaPairs < n ? (k + 1) * kDbaPairs : n;
   for (int64_t p = k * kDbaPairs; p < p1; ++p) {
-    if (rec[p * rec_words_u] != kWfOk) continue;
+    if (status[p] != kWfOk) continue;
     const unsigned w = rowrng[p * lb + i];
     const int lo = (int)(w & 0xffffu);
     int hi = (int)(w >> 16);
@@ -551,29 +687,30 @@ __global__ __launch_bounds__(256) void wf_dba_total_kernel(const double *psum, c
 // ---------------------------------------------------------------------------
 // launchers
 
-template <int G, int NC, bool REC>
+template <int G, int NC, int MODE>
 static hipError_t launch_fwd_t(const WfArgs &a, hipStream_t st) {
   constexpr int GPW = kWave / G;
   const int64_t nb = (a.nitems + GPW - 1) / GPW;
   if (nb <= 0) return hipSuccess;
-  const size_t lds = sizeof(float) * (size_t)a.lds_stride * GPW;
-  hipLaunchKernelGGL((wf_fwd_kernel<G, NC, REC>), dim3((unsigned)nb), dim3(kWave), lds, st, a);
+  // mode 2: kWfScratchWords after the groups' regions
+  const size_t lds = sizeof(float) * ((size_t)a.lds_stride * GPW + (MODE == 2 ? kWfScratchWords : 0));
+  hipLaunchKernelGGL((wf_fwd_kernel<G, NC, MODE>), dim3((unsigned)nb), dim3(kWave), lds, st, a);
   return hipGetLastError();
 }
 
 typedef hipError_t (*WfFwdFn)(const WfArgs &, hipStream_t);
-static const WfFwdFn kWfFwd[2][kWfClasses] = {
-    {&launch_fwd_t<16, 1, false>, &launch_fwd_t<16, 2, false>, &launch_fwd_t<16, 4, false>,
-     &launch_fwd_t<64, 1, false>, &launch_fwd_t<64, 2, false>, &launch_fwd_t<64, 4, false>,
-     &launch_fwd_t<64, 8, false>},
-    {&launch_fwd_t<16, 1, true>, &launch_fwd_t<16, 2, true>, &launch_fwd_t<16, 4, true>,
-     &launch_fwd_t<64, 1, true>, &launch_fwd_t<64, 2, true>, &launch_fwd_t<64, 4, true>,
-     &launch_fwd_t<64, 8, true>}};
+#define EAPDTW_WF_MODE(M)                                                            \
+  {&launch_fwd_t<16, 1, M>, &launch_fwd_t<16, 2, M>, &launch_fwd_t<32, 1, M>,      \
+   &launch_fwd_t<16, 4, M>, &launch_fwd_t<32, 2, M>, &launch_fwd_t<64, 1, M>,      \
+   &launch_fwd_t<64, 2, M>, &launch_fwd_t<64, 4, M>, &launch_fwd_t<64, 8, M>}
+static const WfFwdFn kWfFwd[3][kWfClasses] = {EAPDTW_WF_MODE(0), EAPDTW_WF_MODE(1),
+                                              EAPDTW_WF_MODE(2)};
+#undef EAPDTW_WF_MODE
 
-hipError_t launch_wf_fwd(int cls, bool record, const WfArgs &a, hipStream_t st) {
-  if (cls < 0 || cls >= kWfClasses) return hipErrorInvalidValue;
+hipError_t launch_wf_fwd(int cls, int mode, const WfArgs &a, hipStream_t st) {
+  if (cls < 0 || cls >= kWfClasses || mode < 0 || mode > 2) return hipErrorInvalidValue;
   if (a.lds_stride * (kWave / kWfG[cls]) > kWfLdsFloats) return hipErrorInvalidValue;
-  return kWfFwd[record ? 1 : 0][cls](a, st);
+  return kWfFwd[mode][cls](a, st);
 }
 
 template <int P>
@@ -610,13 +747,12 @@ hipError_t launch_wf_grad(const WfGradArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_wf_dba(const float *X, int64_t n, int len, int lb, const unsigned *rowrng,
-                         const unsigned *rec, int64_t rec_words_u, double *partial_sum,
-                         double *partial_cnt, int64_t nchunk, float *out_B, float *out_count,
-                         hipStream_t st) {
+                         const unsigned *status, double *partial_sum, double *partial_cnt,
+                         int64_t nchunk, float *out_B, float *out_count, hipStream_t st) {
   if (n <= 0 || lb <= 0) return hipSuccess;
   const unsigned bx = (unsigned)((lb + 255) / 256);
   hipLaunchKernelGGL(wf_dba_partial_kernel, dim3(bx, (unsigned)nchunk), dim3(256), 0, st, X, n,
-                     len, lb, rowrng, rec, rec_words_u, partial_sum, partial_cnt);
+                     len, lb, rowrng, status, partial_sum, partial_cnt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(wf_dba_total_kernel, dim3(bx), dim3(256), 0, st, partial_sum, partial_cnt,

@@ -43,6 +43,27 @@ def test_forward_backward_on_the_gpu_path(P, L, w):
     _check(S32, T32, w, gout)
 
 
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+@pytest.mark.parametrize("P,L,w", [(70, 64, 7), (33, 100, 40), (12, 300, 200)])
+def test_every_lane_count(P, L, w, lanes):
+    """Distances, paths and gradients with 16, 32 and 64 lanes per pair."""
+    old = eap.get_option("wf_lanes")
+    eap.set_option("wf_lanes", lanes)
+    try:
+        S32, T32, _ = gen.c5(P=P, L=L)
+        gout = gen.as_f32(gen.rng(52, P).uniform(0.5, 2.0, P))
+        d, _, _ = _check(S32, T32, w, gout)
+        with torch.no_grad():
+            d0 = eap.DTWFunction.apply(torch.from_numpy(S32).cuda(), torch.from_numpy(T32).cuda(),
+                                       w, False).cpu().numpy()
+        assert np.array_equal(d0, d), "distance-only and recorded sweeps differ"
+        want = np.array([oracle.dtw(S32[p].astype(float), T32[p].astype(float), w)
+                         for p in range(P)])
+        assert_close_array(d, want, what=f"{lanes} lanes")
+    finally:
+        eap.set_option("wf_lanes", old)
+
+
 def test_integer_data_follows_the_oracle_tie_order():
     """Small integers: float32 arithmetic is exact, ties are exact, and the
     GPU's path must be the oracle's (diagonal, then (i-1,j), then (i,j-1))."""
@@ -138,16 +159,28 @@ def test_central_finite_differences():
 
 def test_ckpt_bytes():
     lib = eap._lib.load()
-    # 64 status words + one word per lane-slot (32 for window 26) and 16 steps
-    assert lib.eapdtw_dtw_ckpt_bytes(4096, 256, 26) == 4096 * (64 + 32 * 32) * 4
-    assert lib.eapdtw_dtw_ckpt_bytes(10, 256, 100) == 10 * (64 + 32 * 128) * 4
+    # a status word per pair and the path ranges (one word per row and per
+    # column); the code words stay in LDS at these sizes
+    for P, L, w in ((4096, 256, 26), (10, 256, 100), (7, 200, 100)):
+        b = lib.eapdtw_dtw_ckpt_bytes(P, L, w)
+        assert P * (1 + 2 * L) * 4 <= b < P * (1 + 2 * L) * 4 + 3 * 256, (P, L, w, b)
+    # 300 rows active at once: 512 lane-slots, whose codes (38 chunks of 16
+    # steps) do not fit in LDS and stay in the record
+    b = lib.eapdtw_dtw_ckpt_bytes(7, 300, 299)
+    assert b == 256 + 2 * 8448 + 7 * 38 * 512 * 4, b
     assert lib.eapdtw_dtw_ckpt_bytes(10, 600, 599) == -1   # 600 rows active at once
     assert lib.eapdtw_dtw_ckpt_bytes(10, 9000, 3) == -1    # longer than 8191
 
 
-def test_c5_full_size():
+@pytest.mark.parametrize("lanes", [0, 16])
+def test_c5_full_size(lanes):
     """4,096 warped pairs of length 256, window 26: every pair's distance,
-    path and gradient."""
-    S32, T32, w = gen.c5()
-    gout = gen.as_f32(gen.rng(51, S32.shape[0]).uniform(0.5, 2.0, S32.shape[0]))
-    _check(S32, T32, w, gout)
+    path and gradient (the default class, and 16 lanes per pair)."""
+    old = eap.get_option("wf_lanes")
+    eap.set_option("wf_lanes", lanes)
+    try:
+        S32, T32, w = gen.c5()
+        gout = gen.as_f32(gen.rng(51, S32.shape[0]).uniform(0.5, 2.0, S32.shape[0]))
+        _check(S32, T32, w, gout)
+    finally:
+        eap.set_option("wf_lanes", old)

@@ -51,6 +51,46 @@ def test_uneven_batch_vs_oracle():
     assert st["cells_evaluated"] == st["cells_nominal"] > 0
 
 
+@pytest.fixture
+def wf_lanes():
+    """Sets option wf_lanes for one test and restores it."""
+    old = eap.get_option("wf_lanes")
+    yield lambda v: eap.set_option("wf_lanes", v)
+    eap.set_option("wf_lanes", old)
+
+
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+def test_uneven_batch_every_lane_count(wf_lanes, lanes):
+    """The same pairs swept with 16, 32 and 64 lanes per pair (each class
+    that holds a pair: 1 to 8 cells per lane): distances against the oracle,
+    the recorded paths valid and optimal, bounds honoured."""
+    wf_lanes(lanes)
+    S, T, W = _uneven(11, 160, 140)
+    S2, T2, W2 = _uneven(12, 6, 500, extra=300)
+    S, T, W = S + S2, T + T2, W + W2
+    want = _oracle(S, T, W)
+    d = eap.dtw_pairs_batch(S, T, W).cpu().numpy()
+    assert_close_array(d, want, what=f"uneven batch, {lanes} lanes")
+    g = np.random.default_rng(13)
+    ub = gen.as_f32(want * g.choice([0.5, 0.999, 1.001, 2.0], size=want.size))
+    db = eap.dtw_pairs_batch(S, T, W, ub=torch.from_numpy(ub)).cpu().numpy()
+    assert_bounded(db, want, ub.astype(np.float64), what=f"bound, {lanes} lanes")
+    S_pool, T_pool, pairs = eap.pack_pairs(S, T, W)
+    rr, cr = eap.dtw_batch_path(S_pool, T_pool, pairs, len(S))
+    lo, hi = unpack(rr.cpu().numpy())
+    for k in range(len(S)):
+        if math.isinf(want[k]):
+            continue
+        p = pairs[k]
+        ls, lt = p.s_len, p.t_len
+        sl = slice(p.s_off, p.s_off + ls)
+        r = min(W[k], max(ls, lt) - 1)
+        assert ranges_are_path(lo[sl], hi[sl], ls, lt, r), (lanes, k)
+        clo, chi = column_ranges(lo[sl], hi[sl], lt)
+        cost, _, _ = range_path_cost_grad(S[k], T[k], lo[sl], hi[sl], clo, chi, 1.0)
+        assert close(cost, want[k]), (lanes, k, cost, want[k])
+
+
 def test_uneven_edges():
     """No admissible path (|lS - lT| > r: +inf), empty series (Eq. 2-4), a
     single cell, window 0 (squared Euclidean distance) and windows past the
@@ -137,16 +177,21 @@ def test_uneven_autograd_on_the_gpu_paths():
         assert np.all(np.abs(gT[tl] - dT) <= tol + 1e-5 * np.abs(dT)), k
 
 
-def test_uneven_backward_rejects_overlapping_pairs():
+def test_uneven_recorded_forward_rejects_overlapping_pairs():
+    """The record holds the path ranges in the pools' layout, so a forward
+    that records (a gradient is wanted) needs disjoint pairs; distances alone
+    do not."""
     a = torch.ones(10, device="cuda", requires_grad=True)
     b = torch.ones(12, device="cuda")
     pairs = (eap.Pair * 2)()
     for k in range(2):
         pairs[k].s_off, pairs[k].s_len, pairs[k].t_off, pairs[k].t_len = 0, 10, 0, 12
         pairs[k].window = 5
-    d = eap.DTWBatchFunction.apply(a, b, pairs, 2)
     with pytest.raises(eap.EapdtwError):
-        d.sum().backward()
+        eap.DTWBatchFunction.apply(a, b, pairs, 2)
+    with torch.no_grad():
+        d = eap.DTWBatchFunction.apply(a.detach(), b, pairs, 2)
+    assert d.tolist() == [0.0, 0.0]
 
 
 def test_dba_worked_example():
