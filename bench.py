@@ -138,6 +138,215 @@ def batched(eap, q, x, windows, K, steps, plain_rec):
             "same_as_plain": same, "streams": eap.get_option("batch_branches")}
 
 
+def _events_ms(pairs):
+    return float(sum(a.elapsed_time(b) for a, b in pairs) / max(len(pairs), 1))
+
+
+def c5_section(eap, steps, cpu_budget):
+    """Differentiation workload: 4,096 pairs of z-normalised random walks of
+    length 256 (the second a warped noisy copy), window 26.  Forward with the
+    path record, backward to both series' gradients, and the distance-only
+    forward, called through the C ABI on torch's current stream with inputs
+    resident on the GPU.  Per-launch times come from HIP events around each
+    call (the recorded forward and the distance-only forward are one kernel
+    launch each); the autograd.Function wall time is reported beside them."""
+    import ctypes
+
+    import torch
+
+    import gen
+    S32, T32, w = gen.c5()
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(S32).to(dev)
+    T = torch.from_numpy(T32).to(dev)
+    P, L = S.shape
+    ctx = eap.context(0)
+    ctx.bind_stream()
+    lib, h, p = ctx._lib, ctx.handle, eap._ptr
+    rec = torch.empty(int(lib.eapdtw_dtw_ckpt_bytes(P, L, w)), device=dev, dtype=torch.uint8)
+    out = torch.empty(P, device=dev)
+    gout = torch.ones(P, device=dev)
+    gS, gT = torch.empty_like(S), torch.empty_like(T)
+    cls_rec = eap.dtw_kernel_class(P, L, w, True)
+    cls_fwd = eap.dtw_kernel_class(P, L, w, False)
+
+    def fwd_rec():
+        ctx.check(lib.eapdtw_dtw_fwd(h, p(S), p(T), P, L, w, p(out), ctypes.c_void_p(rec.data_ptr())))
+
+    def bwd():
+        ctx.check(lib.eapdtw_dtw_bwd(h, p(S), p(T), P, L, w, ctypes.c_void_p(rec.data_ptr()),
+                                     p(gout), p(gS), p(gT)))
+
+    def fwd_only():
+        ctx.check(lib.eapdtw_dtw_fwd(h, p(S), p(T), P, L, w, p(out), None))
+
+    def wall_ms(fns):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for fn in fns:
+                fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    def launch_ms(fn):
+        """Average GPU time of one call in a burst of back-to-back calls (the
+        host queues ahead of the GPU, so the events bracket the launch
+        itself)."""
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        evs[0].record()
+        for k in range(steps):
+            fn()
+            evs[k + 1].record()
+        torch.cuda.synchronize()
+        return _events_ms(list(zip(evs[:-1], evs[1:])))
+
+    for _ in range(3):
+        fwd_rec()
+        bwd()
+        fwd_only()
+    fb_ms = wall_ms((fwd_rec, bwd))
+    f_ms = wall_ms((fwd_only,))
+    fwd_rec_ms = launch_ms(fwd_rec)
+    bwd_ms = launch_ms(bwd)
+    fwd_ms = launch_ms(fwd_only)
+    # the same through autograd.Function (Python wall time per step)
+    Sg, Tg = S.clone().requires_grad_(True), T.clone().requires_grad_(True)
+    for _ in range(2):
+        eap.DTWFunction.apply(Sg, Tg, w).sum().backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Sg.grad = None
+        Tg.grad = None
+        eap.DTWFunction.apply(Sg, Tg, w).sum().backward()
+    torch.cuda.synchronize()
+    ag_ms = (time.perf_counter() - t0) * 1e3 / steps
+    same = bool(torch.equal(Sg.grad, gS) and torch.equal(Tg.grad, gT))
+    cells = P * _band_cells(L, L, w)
+    k_rec = f"wf_fwd_kernel<{cls_rec['lanes']}, {cls_rec['slots']}, {2 if cls_rec['codes_in_lds'] else 1}>"
+    k_fwd = f"wf_fwd_kernel<{cls_fwd['lanes']}, {cls_fwd['slots']}, 0>"
+    res = {
+        "workload": "dtw fwd+bwd: 4,096 warped random-walk pairs, length 256, window 26",
+        "pairs": P, "len": L, "window": w, "steps": steps,
+        "fwd_bwd_pairs_per_s": P / (fb_ms / 1e3), "fwd_bwd_ms": round(fb_ms, 4),
+        "fwd_pairs_per_s": P / (f_ms / 1e3), "fwd_ms": round(f_ms, 4),
+        "autograd_fwd_bwd_pairs_per_s": P / (ag_ms / 1e3), "autograd_fwd_bwd_ms": round(ag_ms, 4),
+        "autograd_grads_equal_c_abi": same,
+        "recorded_fwd_launch_ms": round(fwd_rec_ms, 4), "bwd_launch_ms": round(bwd_ms, 4),
+        "fwd_launch_ms": round(fwd_ms, 4),
+        "band_cells": cells,
+        "roofline_fwd_bwd": _valu_roofline(k_rec, cells, fwd_rec_ms),
+        "roofline_fwd": _valu_roofline(k_fwd, cells, fwd_ms),
+    }
+    if cpu_budget > 0:
+        res["cpu_baseline"] = _c5_cpu(S32, T32, w, cpu_budget)
+    return res
+
+
+def _band_cells(ls, lt, r):
+    """In-band cells of an ls x lt matrix under window r (Section 2.1)."""
+    n = 0
+    for i in range(ls):
+        lo, hi = max(0, i - r), min(lt - 1, i + r)
+        n += max(0, hi - lo + 1)
+    return n
+
+
+def _valu_roofline(kernel, cells, ms):
+    achieved = OPS_PER_CELL * cells / (ms / 1e3)
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
+            "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+            "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells, "launch_ms": round(ms, 5)}
+
+
+def _c5_cpu(S32, T32, w, budget_s):
+    """The FP64 oracle's DTW with its path gradient on a sample of the pairs."""
+    import gen
+    import oracle
+    t0 = time.perf_counter()
+    n = 0
+    while n < S32.shape[0] and time.perf_counter() - t0 < budget_s:
+        oracle.dtw_grad(gen.as_oracle(S32[n]), gen.as_oracle(T32[n]), w)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {n} pairs, FP64 full-matrix DTW with the optimal path's "
+                      f"gradient, one thread ({dt:.1f} s)"}
+
+
+def c3_section(eap, steps):
+    """All pairs (Section 2.3 pruning, bound = squared Euclidean distance per
+    pair): 2,000 z-normalised random walks of length 512, full window; the
+    unordered pairs (DTW is symmetric, so they give the ordered 2M)."""
+    import torch
+
+    import gen
+    X32, w = gen.c3()
+    X = torch.from_numpy(X32).cuda()
+    N = X.shape[0]
+    eap.pairwise(X, w)
+    torch.cuda.synchronize()
+    sts = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = eap.pairwise(X, w, stats=True)
+        sts.append(st)
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    st = sts[-1]
+    main_ms = sum(s["main_kernel_ms"] for s in sts) / len(sts)
+    npairs = N * (N - 1) // 2
+    r = _valu_roofline("wide_kernel (pairwise)", st["cells_evaluated"], main_ms)
+    r["cells_computed_per_launch"] = st["cells_computed"]
+    return {"workload": "all pairs: 2,000 random walks of length 512, full window, ub = ED",
+            "pairs": npairs, "steps": steps, "pairs_per_s": npairs / (wall / 1e3),
+            "call_ms": round(wall, 4), "main_kernel_ms": round(main_ms, 4),
+            "cells_nominal": st["cells_nominal"], "cells_evaluated": st["cells_evaluated"],
+            "pruned_fraction": 1.0 - st["cells_evaluated"] / st["cells_nominal"],
+            "roofline": r}
+
+
+def c4_section(eap, steps):
+    """Batched uneven search: 64 random-walk queries (lengths 64-1024, windows
+    5-20 %) against a 10,000,000-point random walk, as one batched call and as
+    64 single-query calls."""
+    import torch
+
+    import gen
+    queries, windows, series = gen.c4()
+    x = torch.from_numpy(series).cuda()
+    qs = [(torch.from_numpy(q).cuda(), w) for q, w in zip(queries, windows)]
+    cands = sum(x.numel() - q.numel() + 1 for q, _ in qs)
+    eap.nn_search_batch(qs, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, st = eap.nn_search_batch(qs, x, stats=True)
+    b_ms = (time.perf_counter() - t0) * 1e3 / steps
+    single = [eap.nn_search(q, x, w) for q, w in qs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev = 0
+    for _ in range(steps):
+        single = []
+        for q, w in qs:
+            r1, s1 = eap.nn_search(q, x, w, stats=True)
+            single.append(r1)
+            ev += s1["cells_evaluated"]
+    s_ms = (time.perf_counter() - t0) * 1e3 / steps
+    same = all(a == b for a, b in zip(res, single))
+    return {"workload": "batched uneven search: 64 queries (m 64-1024, r 5-20%) vs 10,000,000 points",
+            "queries": len(qs), "candidates": cands, "steps": steps,
+            "batched_candidates_per_s": cands / (b_ms / 1e3), "batched_ms": round(b_ms, 3),
+            "single_calls_candidates_per_s": cands / (s_ms / 1e3), "single_calls_ms": round(s_ms, 3),
+            "speedup_batched_vs_single": s_ms / b_ms, "same_answers": same,
+            "batched_cells_evaluated": st["cells_evaluated"],
+            "batched_cells_nominal": st["cells_nominal"],
+            "single_cells_evaluated": ev // steps,
+            "batched_effective_gcups": st["cells_evaluated"] / (b_ms / 1e3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +364,14 @@ def main():
     ap.add_argument("--batch-streams", type=int, default=0,
                     help="streams of the batched call's band launches (0 = the library's "
                          "default)")
+    ap.add_argument("--c5-steps", type=int, default=50,
+                    help="steps of the differentiation workload (4,096 pairs fwd and fwd+bwd; "
+                         "0 = skip)")
+    ap.add_argument("--c3-steps", type=int, default=3,
+                    help="repetitions of the all-pairs workload (0 = skip)")
+    ap.add_argument("--c4-steps", type=int, default=2,
+                    help="repetitions of the batched uneven search and of its 64 single calls "
+                         "(0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-mebibyte buffer once (a plain copy of known size "
                          "that calibrates HBM byte counters in a profiler run)")
@@ -257,6 +474,12 @@ def main():
         if args.batch_streams > 0:
             eap.set_option("batch_branches", args.batch_streams)
         line["batched"] = batched(eap, q, x, windows, K, args.batch_steps, rec)
+    if args.c5_steps > 0:
+        line["c5_fwd_bwd"] = c5_section(eap, args.c5_steps, min(args.cpu_budget, 5.0))
+    if args.c3_steps > 0:
+        line["c3_pairwise"] = c3_section(eap, args.c3_steps)
+    if args.c4_steps > 0:
+        line["c4_batched"] = c4_section(eap, args.c4_steps)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(q32, x32, windows, args.cpu_budget)
     else:

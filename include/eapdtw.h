@@ -302,6 +302,14 @@ int eapdtw_dtw_bwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npai
                    int64_t window, const void *ckpt, const float *grad_out, float *grad_S,
                    float *grad_T);
 
+/* The kernel class eapdtw_dtw_fwd would use for this batch: lanes per pair
+ * (16, 32, 64) and matrix rows per lane and anti-diagonal step (1-8); for a
+ * recorded forward (recorded != 0) also whether the argmin codes stay in LDS
+ * (the forward then recovers the path itself).  Any output may be NULL.
+ * Host only; depends on option "wf_lanes".  EINVAL for unsupported sizes. */
+int eapdtw_dtw_kernel_class(eapdtw_ctx *ctx, int64_t npairs, int64_t len, int64_t window,
+                            int recorded, int64_t *lanes, int64_t *slots, int64_t *codes_in_lds);
+
 /* The optimal warping path of each pair of an equal-length batch, as the
  * backward follows it (Section 2; ties as above), and the distances.
  *   out_dist [npairs] : DEVICE float32 (may be NULL).

@@ -449,6 +449,18 @@ def dtw_path(S, T, window: int):
     return dist, rr, cr
 
 
+def dtw_kernel_class(npairs: int, len_: int, window: int, recorded: bool, device=None) -> dict:
+    """The wavefront kernel class eapdtw_dtw_fwd picks for such a batch: lanes
+    per pair, rows per lane and, for a recorded forward, whether the codes stay
+    in LDS."""
+    ctx = context(device)
+    lanes, slots, lds = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    ctx.check(ctx._lib.eapdtw_dtw_kernel_class(ctx.handle, int(npairs), int(len_), int(window),
+                                               1 if recorded else 0, ctypes.byref(lanes),
+                                               ctypes.byref(slots), ctypes.byref(lds)))
+    return {"lanes": lanes.value, "slots": slots.value, "codes_in_lds": bool(lds.value)}
+
+
 def pack_pairs(S_list, T_list, windows, device=None):
     """Pools and descriptors of an uneven batch: S_list / T_list are sequences
     of 1-D series, windows an int or a sequence.  Returns (S_pool, T_pool,

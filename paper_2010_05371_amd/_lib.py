@@ -100,6 +100,8 @@ def load():
         "eapdtw_dtw_fwd": ([vp, vp, vp, i64, i64, i64, vp, vp], i32),
         "eapdtw_dtw_bwd": ([vp, vp, vp, i64, i64, i64, vp, vp, vp, vp], i32),
         "eapdtw_dtw_path": ([vp, vp, vp, i64, i64, i64, vp, vp, vp], i32),
+        "eapdtw_dtw_kernel_class": ([vp, i64, i64, i64, i32, ctypes.POINTER(i64),
+                                     ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "eapdtw_dtw_pairs_batch": ([vp, vp, i64, vp, i64, ctypes.POINTER(Pair), i64, vp, vp, sp],
                                    i32),
         "eapdtw_dtw_batch_record_bytes": ([ctypes.POINTER(Pair), i64], i64),

@@ -400,8 +400,7 @@ static int64_t seed_stride_for(int64_t opt, int64_t nblk) {
 // device work on the context stream; with `stats` it also waits and fills them.
 static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs,
                         int64_t lrow, int64_t lcol, int64_t r, int ub_mode, const float *ub,
-                        float ub_scalar, float *out, float *ckpt, int ckpt_every,
-                        eapdtw_stats *stats) {
+                        float ub_scalar, float *out, eapdtw_stats *stats) {
   hipStream_t st = ctx->stream;
   const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
   const bool band = use_band(ctx, r);
@@ -433,12 +432,9 @@ static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
     a.ub = ub;
     a.ub_scalar = ub_scalar;
     a.out = out;
-    a.ckpt = ckpt;
-    a.ckpt_every = ckpt_every;
     a.counters = cnt;
     HIPCHK(pair_band_launcher((int)r)(a, ntasks, pick_rows(ctx, (int)r), st));
   } else {
-    if (ckpt) return fail(ctx, EAPDTW_EINVAL, "checkpoints need a window of at most 64");
     WideArgs w{};
     w.lrow = (int)lrow;
     w.lcol = (int)lcol;
@@ -505,7 +501,7 @@ int eapdtw_dtw(eapdtw_ctx *ctx, const float *S, int64_t lS, const float *T, int6
   int rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   rc = pairs_engine(ctx, S, T, 1, lS, lT, r, 3, nullptr, bound_down(ub), at<float>(ctx, o_out),
-                    nullptr, 0, stats);
+                    stats);
   if (rc) return rc;
   rc = readback(ctx, o_out, sizeof(float));
   if (rc) return rc;
@@ -517,7 +513,7 @@ int eapdtw_dtw(eapdtw_ctx *ctx, const float *S, int64_t lS, const float *T, int6
 
 static int pairs_common(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs,
                         int64_t len, int64_t window, int ub_mode, const float *ub, float *out,
-                        eapdtw_stats *stats, float *ckpt, int ckpt_every) {
+                        eapdtw_stats *stats) {
   if (npairs < 0 || len < 0) return fail(ctx, EAPDTW_EINVAL, "negative size");
   if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
   if (ub_mode < 0 || ub_mode > 2) return fail(ctx, EAPDTW_EINVAL, "ub_mode must be 0, 1 or 2");
@@ -532,14 +528,13 @@ static int pairs_common(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
     return EAPDTW_OK;
   }
   const int64_t r = window < len - 1 ? window : len - 1;
-  return pairs_engine(ctx, X, Y, npairs, len, len, r, ub_mode, ub, 0.0f, out, ckpt, ckpt_every,
-                      stats);
+  return pairs_engine(ctx, X, Y, npairs, len, len, r, ub_mode, ub, 0.0f, out, stats);
 }
 
 int eapdtw_dtw_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs, int64_t len,
                      int64_t window, int ub_mode, const float *ub, float *out, eapdtw_stats *stats) {
   CHECK_CTX();
-  return pairs_common(ctx, X, Y, npairs, len, window, ub_mode, ub, out, stats, nullptr, 0);
+  return pairs_common(ctx, X, Y, npairs, len, window, ub_mode, ub, out, stats);
 }
 
 int eapdtw_pairwise(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t window,
@@ -2256,6 +2251,29 @@ static int wf_uniform_rec_fwd(eapdtw_ctx *ctx, const float *S, const float *T, i
   a.lds_stride = (int)(u.mode == 2 ? wf_fused_words((int)len, (int)len, u.cls)
                                    : 2 * len + 2 * kWfPad);
   HIPCHK(launch_wf_fwd(u.cls, u.mode, a, ctx->stream));
+  return EAPDTW_OK;
+}
+
+int eapdtw_dtw_kernel_class(eapdtw_ctx *ctx, int64_t npairs, int64_t len, int64_t window,
+                            int recorded, int64_t *lanes, int64_t *slots, int64_t *codes_in_lds) {
+  CHECK_CTX();
+  if (npairs < 0 || len < 0 || window < 0) return fail(ctx, EAPDTW_EINVAL, "negative size");
+  int c = 0;
+  bool lds = false;
+  if (recorded) {
+    WfUniformRec u;
+    if (!wf_uniform_rec(npairs, len, window, (int)ctx->wf_lanes, u))
+      return fail(ctx, EAPDTW_EINVAL, "unsupported sizes for the differentiable batch");
+    c = u.cls;
+    lds = u.mode == 2;
+  } else {
+    int64_t r = 0;
+    c = wf_uniform_class(ctx, npairs, len, window, &r);
+    if (c < 0) return fail(ctx, EAPDTW_EINVAL, "unsupported sizes for the differentiable batch");
+  }
+  if (lanes) *lanes = kWfG[c];
+  if (slots) *slots = kWfNC[c];
+  if (codes_in_lds) *codes_in_lds = lds ? 1 : 0;
   return EAPDTW_OK;
 }
 

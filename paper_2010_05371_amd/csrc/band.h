@@ -959,7 +959,6 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
   bool stopped = !wave_any(alive);
   uint64_t evaluated = 0, computed = 0;
   const int mg = lrow - lrow % U;
-  int ck = 0;
   for (int i0 = 0; i0 < mg && !stopped; i0 += U) {
     float rv[U];
 #pragma unroll
@@ -968,14 +967,6 @@ __global__ __launch_bounds__(64) void pair_band_kernel(PairArgs a) {
     const int cells = rows_cells<U>(i0, lcol, R);
     evaluated += (uint64_t)cells * (uint64_t)__popcll(__ballot(alive));
     computed += (uint64_t)cells * kWave;
-    if (a.ckpt && ((i0 + U) % a.ckpt_every) == 0 && i0 + U < lrow) {
-      float *cp = a.ckpt + (int64_t)ck * W * ld + p;
-      if (active) {
-#pragma unroll
-        for (int d = 0; d < W; ++d) cp[(int64_t)d * ld] = v[d];
-      }
-      ++ck;
-    }
     if (bounded) {
       alive = alive && band_min<R>(v) <= ub;
       if (!wave_any(alive)) stopped = true;

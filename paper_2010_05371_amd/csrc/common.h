@@ -167,8 +167,6 @@ struct PairArgs {
   const float *ub;        // [npairs] when ub_mode == 1
   float ub_scalar;        // bound for every pair when ub_mode == 3
   float *out;             // [npairs]
-  float *ckpt;            // optional checkpoints: [nck][2R+1][ld]
-  int ckpt_every;         // rows between checkpoints (multiple of the row group)
   unsigned long long *counters;
 };
 

@@ -120,6 +120,33 @@ __device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t 
   return (m & a) | (~m & b);
 }
 __device__ __forceinline__ uint32_t umin2(uint32_t a, uint32_t b) { return a < b ? a : b; }
+// bit s of m sign-extended to all ones / zeros (v_bfe_i32).  Written as asm so
+// that the selections built on it stay v_bfi_b32 instead of becoming a
+// compare and a v_cndmask each.
+// The value of x, unknown to the optimiser (no instruction): keeps the
+// selections and minimum below single VALU instructions instead of forms
+// derived from known value ranges.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm("" : "+v"(x));
+  return x;
+}
+// Reverse sweep: 1 when a cell is named by a path cell (bit 2 of own, bit 1
+// of rcv or bit 0 of rcvp; at most one of them is set), else 0.  One asm
+// block: three VALU instructions.
+__device__ __forceinline__ uint32_t path_named(uint32_t own, uint32_t rcv, uint32_t rcvp) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, 2, %2, %3\n\t"
+      "v_bfi_b32 %0, 4, %1, %0\n\t"
+      "v_min_u32 %0, 1, %0"
+      : "=&v"(r)
+      : "v"(own), "v"(rcv), "v"(rcvp));
+  return r;
+}
+__device__ __forceinline__ uint32_t mask_bit(uint32_t m, int s) {
+  uint32_t r;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(m), "n"(s));
+  return r;
+}
 // byte address of an LDS location and a load from one
 __device__ __forceinline__ uint32_t lds_addr(const float *p) {
   return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)p;
@@ -278,16 +305,23 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
 #pragma unroll
     for (int s0 = 0; s0 < kWfChunk; s0 += SUB) {
       float dv[NC][SUB];
+      // all reads first, then the arithmetic: one wait for the whole batch
+      uint32_t bm[NC][SUB];
+      float tv[NC][SUB];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
 #pragma unroll
         for (int u = 0; u < SUB; ++u) {
-          const int s = s0 + u;
-          const uint32_t b = (uint32_t)__builtin_amdgcn_sbfe((int)bsel[c], s, 1);
-          const float tv = lds_load(bit_select(b, pb[c], pa[c]) + 4u * s);
-          const float d = __uint_as_float(bit_select(b, svBb[c], svA[c])) - tv;
-          dv[c][u] = __uint_as_float(__float_as_uint(d) |
-                                     (uint32_t)__builtin_amdgcn_sbfe((int)idle[c], s, 1));
+          bm[c][u] = mask_bit(bsel[c], s0 + u);
+          tv[c][u] = lds_load(bit_select(bm[c][u], pb[c], pa[c]) + 4u * (s0 + u));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int u = 0; u < SUB; ++u) {
+          const float d = __uint_as_float(bit_select(bm[c][u], svBb[c], svA[c])) - tv[c][u];
+          dv[c][u] = __uint_as_float(__float_as_uint(d) | mask_bit(idle[c], s0 + u));
         }
       }
 #pragma unroll
@@ -423,19 +457,22 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
         // the path's last cell: named by a virtual cell (ls-1, lt)
         if (tau0 + kWfChunk == nsp && c * G + g == le) own[c] |= 4u;
       }
-      const uint32_t base = pslot + 2u * (uint32_t)tau0;
+      // a path cell stores at base + 2 s, the others at scratch + 2 s
+      const int32_t to_base = (int32_t)(pslot + 2u * (uint32_t)tau0) - (int32_t)scratch;
 #pragma unroll
       for (int s = kWfChunk - 1; s >= 0; --s) {
         uint32_t emit[NC], on_any = 0u, slot = 0u;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const uint32_t on = umin2((own[c] & 4u) | (rcv[c] & 2u) | (rcvp[c] & 1u), 1u);
+          // bit 2 of own, bit 1 of rcv, bit 0 of rcvp (emissions use bits 0-2)
+          const uint32_t on = path_named(own[c], rcv[c], rcvp[c]);
           emit[c] = on << ((cw[c] >> (2 * s)) & 3u);
           own[c] = emit[c];
           on_any |= on;
           if (NC > 1) slot = on ? (uint32_t)(c * G + g) : slot;
         }
-        const uint32_t at = (on_any ? base : scratch) + 2u * (uint32_t)s;
+        const uint32_t at =
+            (uint32_t)__mul24((int)opaque(on_any), to_base) + scratch + 2u * (uint32_t)s;
         *(__attribute__((address_space(3))) uint16_t *)(uintptr_t)at =
             (uint16_t)(NC > 1 ? slot : (uint32_t)g);
         uint32_t r[NC];

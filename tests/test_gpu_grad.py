@@ -172,6 +172,28 @@ def test_ckpt_bytes():
     assert lib.eapdtw_dtw_ckpt_bytes(10, 9000, 3) == -1    # longer than 8191
 
 
+def test_kernel_class_follows_the_lanes_option():
+    """4,096 pairs of length 256, window 26 (28 rows active at once): 32
+    lane-slots per pair; by default two pairs per wave, each lane one row, the
+    codes kept in LDS; option wf_lanes = 16 takes two rows per lane."""
+    old = eap.get_option("wf_lanes")
+    try:
+        eap.set_option("wf_lanes", 0)
+        assert eap.dtw_kernel_class(4096, 256, 26, True) == {"lanes": 32, "slots": 1,
+                                                              "codes_in_lds": True}
+        assert eap.dtw_kernel_class(4096, 256, 26, False)["lanes"] == 32
+        eap.set_option("wf_lanes", 16)
+        assert eap.dtw_kernel_class(4096, 256, 26, True) == {"lanes": 16, "slots": 2,
+                                                              "codes_in_lds": True}
+        # 8,192 pairs give two waves per SIMD with four pairs per wave
+        eap.set_option("wf_lanes", 0)
+        assert eap.dtw_kernel_class(8192, 256, 26, False) == {"lanes": 16, "slots": 2,
+                                                              "codes_in_lds": False}
+        assert not eap.dtw_kernel_class(7, 300, 299, True)["codes_in_lds"]
+    finally:
+        eap.set_option("wf_lanes", old)
+
+
 @pytest.mark.parametrize("lanes", [0, 16])
 def test_c5_full_size(lanes):
     """4,096 warped pairs of length 256, window 26: every pair's distance,
