@@ -449,6 +449,23 @@ typedef struct {
   float lb_ms;
 } eapdtw_lb_stats;
 
+/* Allocation-free form of eapdtw_nn_search, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments and results (offset and distance,
+ * bit for bit), no stats.  It calls no hipMalloc, hipFree or other
+ * allocating routine: its counters, best-so-far words and normalised query
+ * live in a fixed 64 KiB device array, one per GPU, held until the process
+ * ends (looked up at eapdtw_create), and the result comes back through the
+ * pinned buffer eapdtw_create allocates.  Limits: window <= 64 (the band and
+ * window-0 kernels) and m <= 4096; larger sizes return EINVAL before any
+ * device work.  The bound-seeding pass runs on the context's stream before
+ * the search.  Every call on one GPU uses that GPU's one array, from any
+ * context: calls that overlap in time on one GPU (two streams, two threads)
+ * race and must be serialised by the caller.  Synchronous. */
+int eapdtw_nn_search_noalloc(eapdtw_ctx *ctx, const float *query, int64_t m,
+                             const float *series, int64_t n, int64_t window, int64_t *out_offset,
+                             double *out_dist);
+
 /* As eapdtw_nn_search, with the cascade.  Synchronous. */
 int eapdtw_nn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                         int64_t n, int64_t window, int64_t *out_offset, double *out_dist,

@@ -94,6 +94,8 @@ def load():
         "eapdtw_pairwise": ([vp, vp, i64, i64, i64, vp, sp], i32),
         "eapdtw_nn_search": ([vp, vp, i64, vp, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(f64),
                               sp], i32),
+        "eapdtw_nn_search_noalloc": ([vp, vp, i64, vp, i64, i64, ctypes.POINTER(i64),
+                                      ctypes.POINTER(f64)], i32),
         "eapdtw_nn_search_batch": ([vp, ctypes.POINTER(Query), i64, vp, i64,
                                     ctypes.POINTER(Result), sp], i32),
         "eapdtw_dtw_ckpt_bytes": ([i64, i64, i64], i64),

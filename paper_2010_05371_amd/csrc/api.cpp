@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/eapdtw.h"
@@ -17,6 +18,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <vector>
 
 using namespace eapdtw;
@@ -71,6 +73,8 @@ struct eapdtw_ctx {
   hipStream_t branch[kMaxBranches] = {};
   hipEvent_t ev_bfork = nullptr;
   hipEvent_t ev_bjoin[kMaxBranches] = {};
+  // device address of this GPU's fixed scratch array (eapdtw_nn_search_noalloc)
+  char *noalloc = nullptr;
 };
 
 static thread_local std::string g_create_error;
@@ -228,6 +232,33 @@ extern "C" {
 
 const char *eapdtw_version(void) { return "eapdtw 0.1 gfx950"; }
 
+// ---------------------------------------------------------------------------
+// Scratch of eapdtw_nn_search_noalloc: a fixed device array (one copy per GPU,
+// held until the process ends) instead of the context's allocated scratch.
+// Host code uses the device address hipGetSymbolAddress returns for the GPU,
+// never the array's name (which is a host-side stand-in).
+constexpr size_t kNoAllocScratchBytes = 64 * 1024;
+constexpr int64_t kNoAllocMaxM = 4096;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) unsigned char g_noalloc_scratch[kNoAllocScratchBytes];
+static std::mutex g_noalloc_mu;
+static char *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// Looks the array's address up once per device (the device must be current).
+static char *noalloc_scratch(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_noalloc_ptr[device] = static_cast<char *>(p);
+  }
+  return g_noalloc_ptr[device];
+}
+
 int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out) {
   g_create_error.clear();
   if (!out) {
@@ -268,6 +299,14 @@ int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out) {
     g_create_error = "hipEventCreate failed";
     delete c;
     return EAPDTW_EDEVICE;
+  }
+  // set-up of the allocation-free search: the device's scratch address and a
+  // pinned read-back buffer large enough for its results
+  c->noalloc = noalloc_scratch(device);
+  if (ensure_pinned(c, 4096) != EAPDTW_OK) {
+    g_create_error = "pinned host buffer allocation failed";
+    eapdtw_destroy(c);
+    return EAPDTW_ENOMEM;
   }
   *out = c;
   return EAPDTW_OK;
@@ -661,7 +700,8 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
                         int64_t n, int64_t r, float *qpad, unsigned long long *bsf,
                         unsigned long long *cnt, float *dists, float fixed_ub, float *bnd,
                         int64_t bnd_waves, bool time_main, const LbBufs *lb = nullptr,
-                        const KnnBufs *kb = nullptr, const float *wgt = nullptr) {
+                        const KnnBufs *kb = nullptr, const float *wgt = nullptr,
+                        bool one_stream = false) {
   hipStream_t st = ctx->stream;
   const int64_t K = n - m + 1;
   const int64_t nblk = (K + kWave - 1) / kWave;
@@ -725,7 +765,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       s.knn = kb->k;
     }
     hipStream_t ss = st;
-    if (use_band(ctx, r)) {
+    if (use_band(ctx, r) && !one_stream) {
       HIPCHK(ensure_seed_stream(ctx));
       HIPCHK(hipEventRecord(ctx->ev_fork, st));
       HIPCHK(hipStreamWaitEvent(ctx->seed_stream, ctx->ev_fork, 0));
@@ -998,6 +1038,53 @@ int eapdtw_nn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
                         eapdtw_stats *stats, eapdtw_lb_stats *lbstats) {
   return nn_search_impl(ctx, query, m, series, n, window, out_offset, out_dist, stats, true,
                         lbstats);
+}
+
+int eapdtw_nn_search_noalloc(eapdtw_ctx *ctx, const float *query, int64_t m,
+                             const float *series, int64_t n, int64_t window, int64_t *out_offset,
+                             double *out_dist) {
+  CHECK_CTX();
+  KnobGuard knobs(ctx);
+  knobs.apply_cached(m, window);
+  if (!out_offset || !out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL output");
+  int rc = search_validate(ctx, query, m, series, n, window);
+  if (rc) return rc;
+  const int64_t r = window < m - 1 ? window : m - 1;
+  if (!use_band(ctx, r))
+    return fail(ctx, EAPDTW_EINVAL, "the allocation-free search takes windows up to 64");
+  if (m > kNoAllocMaxM)
+    return fail(ctx, EAPDTW_EINVAL, "the allocation-free search takes queries up to 4096 points");
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
+  const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  if (pl.off > kNoAllocScratchBytes)
+    return fail(ctx, EAPDTW_EINVAL, "the query exceeds the allocation-free scratch");
+  // flag word .. best-so-far words: what the host reads back
+  const size_t o_rd = sizeof(unsigned long long) * kCntWords;
+  const size_t rd_bytes = o_bsf + 2 * sizeof(unsigned long long) - o_rd;
+  if (!ctx->noalloc) return fail(ctx, EAPDTW_EDEVICE, "no address for the fixed scratch array");
+  if (rd_bytes > ctx->pinned_cap) return fail(ctx, EAPDTW_EDEVICE, "pinned read-back buffer too small");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  char *base = ctx->noalloc;
+  unsigned long long *cnt = reinterpret_cast<unsigned long long *>(base + o_cnt);
+  unsigned long long *bsf = reinterpret_cast<unsigned long long *>(base + o_bsf);
+  // the array keeps the last call's contents (of any context on this GPU):
+  // clear the non-finite flag word; the set-up kernel clears the rest
+  HIPCHK(launch_fill_u64(cnt + kCntWords, 0ull, 1, st));
+  rc = search_queue(ctx, query, m, series, n, r, reinterpret_cast<float *>(base + o_q), bsf, cnt,
+                    nullptr, 0.f, nullptr, 0, false, nullptr, nullptr, nullptr, true);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(ctx->pinned, base + o_rd, rd_bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (*reinterpret_cast<const unsigned *>(ctx->pinned) == ctx->epoch)
+    return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
+  const unsigned long long best =
+      *reinterpret_cast<const unsigned long long *>(ctx->pinned + (o_bsf - o_rd));
+  *out_offset = best_offset(best) == 0xffffffffu ? -1 : (int64_t)best_offset(best);
+  *out_dist = (double)best_dist(best);
+  return EAPDTW_OK;
 }
 
 static int nn_dists_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
