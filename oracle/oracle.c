@@ -35,6 +35,15 @@
 /* The paper inherits this step from the UCR Suite it embeds its DTW in      */
 /* (Section 5, experimental setup); it is not spelled out there.             */
 /* ------------------------------------------------------------------------- */
+/* A window is flat when its variance is at most 1e-14 of its mean square   */
+/* E[x^2] = var + mean^2 (sigma at most 1e-7 of its RMS: variation at the    */
+/* float32 rounding level of its values); a flat window normalises to zeros. */
+#define ORACLE_FLAT_REL 1e-14
+
+static int oracle_flat(double mean, double var) {
+  return !(var > ORACLE_FLAT_REL * (var + mean * mean));
+}
+
 void oracle_znorm(const double *x, int64_t m, double *z) {
   double mean = 0.0;
   for (int64_t t = 0; t < m; ++t) mean += x[t];
@@ -45,11 +54,12 @@ void oracle_znorm(const double *x, int64_t m, double *z) {
     var += dv * dv;
   }
   var /= (double)m;
-  double sd = sqrt(var);
+  double sd = oracle_flat(mean, var) ? 0.0 : sqrt(var);
   for (int64_t t = 0; t < m; ++t) z[t] = (sd > 0.0) ? (x[t] - mean) / sd : 0.0;
 }
 
-/* mean and population sigma of one window (two-pass), for the stats tests. */
+/* mean and population sigma of every window (two-pass; 0 for a flat window), */
+/* for the stats tests. */
 void oracle_window_stats(const double *x, int64_t n, int64_t m, double *mu, double *sigma) {
   for (int64_t k = 0; k + m <= n; ++k) {
     double mean = 0.0;
@@ -60,8 +70,9 @@ void oracle_window_stats(const double *x, int64_t n, int64_t m, double *mu, doub
       double dv = x[k + t] - mean;
       var += dv * dv;
     }
+    var /= (double)m;
     mu[k] = mean;
-    sigma[k] = sqrt(var / (double)m);
+    sigma[k] = oracle_flat(mean, var) ? 0.0 : sqrt(var);
   }
 }
 
@@ -632,7 +643,8 @@ int oracle_nn_lower_bounds(const double *q, int64_t m, const double *x, int64_t 
     for (int64_t s = 0; s < m; ++s) mean += x[k + s];
     mean /= (double)m;
     for (int64_t s = 0; s < m; ++s) var += sqd(x[k + s], mean);
-    const double sd = sqrt(var / (double)m);
+    var /= (double)m;
+    const double sd = oracle_flat(mean, var) ? 0.0 : sqrt(var);
     for (int64_t s = 0; s < m; ++s) {
       zc[s] = sd > 0.0 ? (x[k + s] - mean) / sd : 0.0;
       Uc[s] = sd > 0.0 ? (Ux[k + s] - mean) / sd : 0.0;

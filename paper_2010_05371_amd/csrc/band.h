@@ -25,6 +25,9 @@
 
 namespace eapdtw {
 
+// A window whose variance is at most kFlatRel of its mean square is flat.
+constexpr double kFlatRel = 1e-14;
+
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0ull; }
 
 // Wave-uniform read-only data (the normalised query) is read through the
@@ -108,9 +111,31 @@ __device__ __forceinline__ void wave_window_stats(X x, int64_t n, int m, int64_t
   const double my = sum1 / (double)m;
   const double ey2 = sum2 / (double)m;
   double var = ey2 - my * my;
-  // a window whose deviation is only rounding noise is flat: normalise to 0
-  if (!(var > 1e-14 * ey2)) var = 0.0;
-  mean = pivot + my;
+  double mu = pivot + my;
+  // E[x^2] = E[(x-p)^2] + p (2 E[x-p] + p)
+  double ex2 = ey2 + pivot * (2.0 * my + pivot);
+  // The moments about the shared pivot p lose about log10(E[(x-p)^2] / var)
+  // digits of the variance; a window far from p with a small spread (a
+  // plateau after a step) takes a second pass over its own values about its
+  // first mean instead.
+  if (var < 1e-6 * ey2) {
+    double c1 = 0.0, c2 = 0.0;
+    for (int t = 0; t < m; ++t) {
+      int64_t idx = kb + lane + t;
+      idx = idx < n ? idx : n - 1;
+      const double y = (double)x[idx] - mu;
+      c1 += y;
+      c2 += y * y;
+    }
+    const double d1 = c1 / (double)m;
+    var = c2 / (double)m - d1 * d1;
+    mu += d1;
+    ex2 = var + mu * mu;
+  }
+  // Flat window (normalised to 0): variance at most kFlatRel of the window's
+  // mean square, i.e. variation at the float32 rounding level of its values.
+  if (!(var > kFlatRel * ex2)) var = 0.0;
+  mean = mu;
   sd = sqrt(var);
 }
 

@@ -18,7 +18,7 @@ __device__ __forceinline__ double block_sum_f64(double v, double *sh) {
   return t;
 }
 
-// Two passes in float64, population sigma; zero sigma normalises to zeros.
+// Two passes in float64, population sigma; a flat series normalises to zeros.
 // Writes out[pad + j] for j < m and +inf into the `pad` entries on each side.
 // Returns (in every thread) the number of non-finite inputs.
 __device__ __forceinline__ int znorm_block(const float *__restrict__ q, int m,
@@ -37,7 +37,8 @@ __device__ __forceinline__ int znorm_block(const float *__restrict__ q, int m,
     ss += dv * dv;
   }
   const double var = block_sum_f64(ss, sh) / (double)m;
-  const double sd = sqrt(var);
+  // flat (variance at most kFlatRel of the mean square): zeros
+  const double sd = (var > kFlatRel * (var + mean * mean)) ? sqrt(var) : 0.0;
   for (int j = threadIdx.x; j < m; j += blockDim.x)
     out[pad + j] = sd > 0.0 ? (float)(((double)q[j] - mean) / sd) : 0.0f;
   for (int j = threadIdx.x; j < pad; j += blockDim.x) {

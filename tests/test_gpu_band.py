@@ -35,6 +35,39 @@ def test_window_stats_flat_window_is_zero():
     assert float(_cpu(sd)[104]) == 0.0
 
 
+def _step_plateaus():
+    """A random walk, then a plateau at 1000 with noise of sd 1e-3 (variance
+    1e-12 of the mean square: normalised), a constant plateau at 500 (flat),
+    a plateau at 200 with noise of sd 1e-2 (normalised) and one at 200 with
+    float32-rounding-level noise (a few ulps of 200: flat)."""
+    g = np.random.default_rng(7)
+    ulp = float(np.spacing(np.float32(200.0)))
+    parts = [np.cumsum(g.standard_normal(700)), 1000.0 + 1e-3 * g.standard_normal(600),
+             np.full(500, 500.0), 200.0 + 1e-2 * g.standard_normal(600),
+             200.0 + ulp * g.integers(-1, 2, 600)]
+    return gen.as_f32(np.concatenate(parts))
+
+
+def test_flat_rule_on_step_plateaus():
+    """Flat windows (variance at most 1e-14 of the window's mean square) are
+    the oracle's: the same windows get sigma 0, the others the oracle's
+    statistics; the search distances of every offset follow."""
+    x32 = _step_plateaus()
+    m, w = 64, 6
+    mu, sd = eap.window_stats(torch.from_numpy(x32), m)
+    omu, osd = oracle.window_stats(gen.as_oracle(x32), m)
+    sd, mu = _cpu(sd), _cpu(mu)
+    np.testing.assert_array_equal(sd == 0.0, osd == 0.0)
+    assert (osd == 0.0).sum() > 500 and (osd > 0.0).sum() > 1500
+    np.testing.assert_allclose(mu, omu, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(sd, osd, rtol=1e-6, atol=0)
+    q32 = gen.as_f32(np.cumsum(np.random.default_rng(8).standard_normal(m)))
+    d = _cpu(eap.nn_dists(torch.from_numpy(q32), torch.from_numpy(x32), w))
+    offs = np.arange(x32.size - m + 1)
+    want = oracle.nn_dists(gen.as_oracle(q32), gen.as_oracle(x32), w, offs)
+    assert_close_array(d, want, what="step plateaus")
+
+
 @pytest.mark.parametrize("m", [1, 5, 256, 1000])
 def test_znorm(m):
     x32 = gen.as_f32(gen.random_walk(m, gen.rng(201, m)) + 50.0)

@@ -184,6 +184,23 @@ def test_znorm_constant_window_is_zero():
     np.testing.assert_array_equal(oracle.znorm(np.full(9, 4.25)), np.zeros(9))
 
 
+def test_znorm_flat_rule_is_relative_to_the_mean_square():
+    """c + e (+1, -1, ...): mean c, sigma e.  Normalised to (+1, -1, ...)
+    when e^2 > 1e-14 (c^2 + e^2), else flat (zeros)."""
+    alt = np.tile([1.0, -1.0], 8)
+    for c, e, flat in ((1000.0, 1e-3, False), (1000.0, 1e-5, True), (0.0, 1e-30, False),
+                       (-3.0, 1e-9, True), (-3.0, 1e-6, False)):
+        z = oracle.znorm(c + e * alt)
+        if flat:
+            np.testing.assert_array_equal(z, np.zeros(alt.size))
+        else:
+            np.testing.assert_allclose(z, alt, rtol=0, atol=1e-6)
+        mu, sd = oracle.window_stats(c + e * alt, alt.size)
+        assert (sd[0] == 0.0) == flat
+        if not flat:
+            assert sd[0] == pytest.approx(e, rel=1e-6)
+
+
 def test_window_stats_ramp():
     x = np.arange(50, dtype=np.float64) * 2.0 + 1.0
     mu, sd = oracle.window_stats(x, 10)
