@@ -78,11 +78,68 @@ def cpu_baseline(q32, x32, windows, budget_s: float):
     for w in windows:
         oracle.nn_dists(q, x, w, offs, nthreads=threads)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, on a sample a tenth as large
+    n1 = max(probe // 4, n // (10 * threads))
+    offs1 = np.linspace(0, x.size - q.size, n1).astype(np.int64)
+    t0 = time.perf_counter()
+    for w in windows:
+        oracle.nn_dists(q, x, w, offs1, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n * len(windows) / dt, "unit": "candidates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n} evenly spaced offsets of the 2,000,000-point series, each at windows "
                       f"{list(windows)}, brute-force FP64 full-matrix DTW with two-pass "
-                      f"z-normalisation ({dt:.1f} s on {threads} threads)"}
+                      f"z-normalisation ({dt:.1f} s on {threads} threads)",
+            "one_core_value": n1 * len(windows) / dt1,
+            "one_core_sample": f"{n1} evenly spaced offsets at each window ({dt1:.1f} s)",
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_eap_scan(q32, x32, windows, budget_s: float, gpu_per_window):
+    """The paper's method on the CPU: the nearest-neighbour scan with the
+    EAPrunedDTW model (Algorithm 3) bounded by a shared best-so-far, over a
+    contiguous prefix of the offsets at each window, multi-threaded; its
+    evaluated cells per candidate beside the GPU's."""
+    import numpy as np
+
+    import gen
+    import oracle
+    q, x = gen.as_oracle(q32), gen.as_oracle(x32)
+    threads = oracle.default_threads()
+    K = x.size - q.size + 1
+    probe = 256 * threads
+    t0 = time.perf_counter()
+    for w in windows:
+        oracle.eap_scan(q, x, w, np.arange(probe), nthreads=threads)
+    dt = time.perf_counter() - t0
+    n = int(max(probe, min(K, probe * budget_s / max(dt, 1e-6))))
+    per_window = {}
+    t_all = 0.0
+    for w in windows:
+        t0 = time.perf_counter()
+        k, d, cells = oracle.eap_scan(q, x, w, np.arange(n), nthreads=threads)
+        dtw = time.perf_counter() - t0
+        t_all += dtw
+        g = gpu_per_window[str(w)]
+        per_window[str(w)] = {"candidates_per_s": n / dtw, "best_offset_in_prefix": k,
+                              "cells_per_candidate": cells / n,
+                              "gpu_cells_per_candidate": g["cells_evaluated"] / K}
+    return {"value": n * len(windows) / t_all, "unit": "candidates/s", "cores": threads,
+            "kind": "oracle EAPrunedDTW model scan",
+            "sample": f"the first {n} offsets of the 2,000,000-point series at each window "
+                      f"{list(windows)} ({t_all:.1f} s on {threads} threads)",
+            "per_window": per_window}
 
 
 def lb_cascade(eap, q, x, windows, K, steps, plain_rec):
@@ -482,6 +539,8 @@ def main():
         line["c4_batched"] = c4_section(eap, args.c4_steps)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(q32, x32, windows, args.cpu_budget)
+        line["cpu_eap_scan"] = cpu_eap_scan(q32, x32, windows, min(args.cpu_budget, 8.0),
+                                            per_window)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

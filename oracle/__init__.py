@@ -25,6 +25,9 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
   it), the barycentre use of the path;
 * ``eap_model``   -- a model of Algorithm 3 (Section 4), kept only to check the
   threshold contract and the worked example (never a reference value);
+  ``eap_scan`` -- the nearest-neighbour scan with that model bounded by the
+  shared best-so-far: the paper's method on the CPU, a timed baseline (its
+  answer must be the brute-force answer);
 * ``envelope``, ``lb_kim``, ``lb_keogh``, ``nn_lower_bounds`` -- the lower
   bounds of Section 2.2 that the search experiments of Section 5 put in front
   of the DTW (LB_Kim, LB_Keogh with the query's and with the candidate's
@@ -94,6 +97,8 @@ def _load():
     lib.oracle_nn_dists.restype = ctypes.c_int
     lib.oracle_nn_search.argtypes = [dp, i64, dp, i64, i64, i64, i64, ctypes.c_int, ip, dp]
     lib.oracle_nn_search.restype = ctypes.c_int
+    lib.oracle_eap_scan.argtypes = [dp, i64, dp, i64, i64, ip, i64, ctypes.c_int, ip, dp, ip]
+    lib.oracle_eap_scan.restype = ctypes.c_int
     lib.oracle_dtw_pairs.argtypes = [dp, dp, i64, i64, ip, ip, i64, ctypes.c_int, dp]
     lib.oracle_dtw_pairs.restype = ctypes.c_int
     lib.oracle_eap_model.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double, ip, ip, ip, ip]
@@ -309,6 +314,23 @@ def eap_model(S, T, window: int | None, ub: float):
     v = _load().oracle_eap_model(_ptr(S), S.size, _ptr(T), T.size, r, float(ub), _ptr(cells),
                                  _ptr(trace), _ptr(ai), _ptr(aj))
     return float(v), int(cells[0]), trace[:nl].tolist(), (int(ai[0]), int(aj[0]))
+
+
+def eap_scan(query, series, window: int, offsets, nthreads: int | None = None):
+    """The paper's method on the CPU: nearest-neighbour scan of the listed
+    offsets with the EAPrunedDTW model (Algorithm 3) bounded by the shared
+    best-so-far.  Returns (best offset, distance, evaluated cells)."""
+    q, x = _f64(query), _f64(series)
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    bk = np.zeros(1, dtype=np.int64)
+    bd = np.zeros(1)
+    cells = np.zeros(1, dtype=np.int64)
+    rc = _load().oracle_eap_scan(_ptr(q), q.size, _ptr(x), x.size, int(window), _ptr(offs),
+                                 offs.size, nthreads or default_threads(), _ptr(bk), _ptr(bd),
+                                 _ptr(cells))
+    if rc != 0:
+        raise RuntimeError(f"oracle_eap_scan failed ({rc})")
+    return int(bk[0]), float(bd[0]), int(cells[0])
 
 
 def envelope(a, window: int):

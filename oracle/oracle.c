@@ -15,12 +15,12 @@
  * Paper: Herrmann & Webb, "Early Abandoning PrunedDTW and its application to
  * similarity search" (arXiv 2010.05371).
  *
- * Conventions (readings of the paper, see DESIGN.md "Readings"):
+ * Conventions (readings of the paper):
  *  - rows i = 1..lS index S, columns j = 1..lT index T (1-based, as in Eq. 1-5);
  *  - cost(a, b) = (a - b)^2 (Section 2, "usually the squared Euclidean distance");
  *  - Sakoe-Chiba window r: a cell is admissible iff |i - j| <= r (Section 2.1);
- *  - z-normalisation uses the population standard deviation; a window whose
- *    standard deviation is zero normalises to all zeros.
+ *  - z-normalisation uses the population standard deviation; a flat window
+ *    (variance at most 1e-14 of its mean square) normalises to all zeros.
  */
 #include <math.h>
 #include <pthread.h>
@@ -436,8 +436,8 @@ int oracle_dtw_pairs(const double *X, const double *Y, int64_t L, int64_t r, con
 
 /* ------------------------------------------------------------------------- */
 /* Model of the paper's EAPrunedDTW line sweep (Section 4, Algorithm 3),      */
-/* with a Sakoe-Chiba window (the paper states its algorithms without one,   */
-/* Section 2.1; the windowed reading is documented in the design doc) and with the */
+/* with a Sakoe-Chiba window (the paper states its algorithms without one;   */
+/* a cell is admissible iff |i - j| <= r, Section 2.1) and with the          */
 /* cost recomputed for every column of the last stage.  Kept only to check   */
 /* the threshold contract and the worked example; never a reference value.   */
 /*                                                                           */
@@ -826,3 +826,93 @@ done:
   free(ia); free(ib); free(D);
   return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* The paper's method on the CPU: a nearest-neighbour scan (Section 5's       */
+/* search) whose distance is the EAPrunedDTW model above (Algorithm 3) with  */
+/* the best-so-far as its bound.  The offsets are split into contiguous      */
+/* ranges, one per thread, scanned in order; every thread reads the shared   */
+/* best-so-far before each candidate and publishes a value at most it under  */
+/* a lock (ties: the smaller offset).  Each candidate is z-normalised; lines */
+/* run over the candidate, columns over the query.  Since the model returns  */
+/* the exact DTW whenever it does not exceed the bound, the answer is the     */
+/* brute-force answer.  *cells receives the evaluated cells of all           */
+/* candidates.  Test and baseline infrastructure only.  Returns 0 on success. */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const double *zq, *x;
+  int64_t m, r;
+  const int64_t *offsets;
+  int64_t lo, hi;
+  pthread_mutex_t *mu;
+  volatile double *bsf;
+  volatile int64_t *bk;
+  int64_t cells;
+  int err;
+} eap_scan_job;
+
+static void *eap_scan_worker(void *arg) {
+  eap_scan_job *jb = (eap_scan_job *)arg;
+  double *zc = malloc((size_t)jb->m * sizeof(double));
+  if (!zc) { jb->err = -1; return NULL; }
+  for (int64_t t = jb->lo; t < jb->hi; ++t) {
+    const int64_t k = jb->offsets[t];
+    oracle_znorm(jb->x + k, jb->m, zc);
+    const double ub = *jb->bsf;
+    int64_t cells = 0;
+    const double v = oracle_eap_model(zc, jb->m, jb->zq, jb->m, jb->r, ub, &cells, NULL, NULL,
+                                      NULL);
+    jb->cells += cells;
+    if (v <= ub) {
+      pthread_mutex_lock(jb->mu);
+      if (v < *jb->bsf || (v == *jb->bsf && (*jb->bk < 0 || k < *jb->bk))) {
+        *jb->bsf = v;
+        *jb->bk = k;
+      }
+      pthread_mutex_unlock(jb->mu);
+    }
+  }
+  free(zc);
+  return NULL;
+}
+
+int oracle_eap_scan(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                    const int64_t *offsets, int64_t noff, int nthreads, int64_t *best_k,
+                    double *best_d, int64_t *cells) {
+  if (m <= 0 || n < m || r < 0 || noff <= 0) return -2;
+  for (int64_t t = 0; t < noff; ++t)
+    if (offsets[t] < 0 || offsets[t] + m > n) return -2;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  double *zq = malloc((size_t)m * sizeof(double));
+  if (!zq) return -1;
+  oracle_znorm(q, m, zq);
+  pthread_mutex_t mu = PTHREAD_MUTEX_INITIALIZER;
+  volatile double bsf = ORACLE_INF;
+  volatile int64_t bk = -1;
+  pthread_t th[256];
+  int live[256];
+  eap_scan_job jobs[256];
+  const int64_t per = (noff + nthreads - 1) / nthreads;
+  for (int t = 0; t < nthreads; ++t) {
+    int64_t lo = (int64_t)t * per, hi = lo + per;
+    if (lo > noff) lo = noff;
+    if (hi > noff) hi = noff;
+    jobs[t] = (eap_scan_job){zq, x, m, r, offsets, lo, hi, &mu, &bsf, &bk, 0, 0};
+    live[t] = pthread_create(&th[t], NULL, eap_scan_worker, &jobs[t]) == 0;
+    if (!live[t]) eap_scan_worker(&jobs[t]);
+  }
+  int rc = 0;
+  int64_t total = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    if (live[t]) pthread_join(th[t], NULL);
+    if (jobs[t].err) rc = jobs[t].err;
+    total += jobs[t].cells;
+  }
+  free(zq);
+  *best_k = bk;
+  *best_d = bsf;
+  if (cells) *cells = total;
+  return rc;
+}
+

@@ -65,12 +65,32 @@ def test_c3_full_pairwise_sampled():
     assert np.isfinite(D).all() and (D >= 0).all()
 
 
-def test_c4_full_batch_properties():
+@pytest.fixture(scope="module")
+def c4():
+    return gen.c4()
+
+
+def test_c4_cut_batch_vs_brute_force(c4):
+    """The 64 uneven queries (lengths 64-1024, windows 5-20 %) batched against
+    the first 20,000 points of the series: the oracle scans every offset of
+    every query (Section 2.2's search)."""
+    qs, ws, x32 = c4
+    cut = np.ascontiguousarray(x32[:20_000])
+    x = torch.from_numpy(cut).cuda()
+    batch = eap.nn_search_batch([(torch.from_numpy(q).cuda(), w) for q, w in zip(qs, ws)], x)
+    xo = gen.as_oracle(cut)
+    for (q32, w), (k, d) in zip(zip(qs, ws), batch):
+        qo = gen.as_oracle(q32)
+        ko, do = oracle.nn_search(qo, xo, w)
+        check_nn(k, d, ko, do, oracle.nn_dists(qo, xo, w, [k])[0])
+
+
+def test_c4_full_batch_properties(c4):
     """64 uneven queries against 10,000,000 points: the batched answers equal
     the single-query answers; each reported distance is the oracle's DTW at
-    the reported offset; no sampled offset (64 random plus the 64 around the
-    answer) beats it."""
-    qs, ws, x32 = gen.c4()
+    the reported offset; no sampled offset (4,096 random ones plus every
+    offset within m of the answer) beats it."""
+    qs, ws, x32 = c4
     x = torch.from_numpy(x32).cuda()
     qt = [(torch.from_numpy(q).cuda(), w) for q, w in zip(qs, ws)]
     batch = eap.nn_search_batch(qt, x)
@@ -83,7 +103,8 @@ def test_c4_full_batch_properties():
         K = x32.size - q32.size + 1
         at = oracle.nn_dists(qo, xo, w, [k])[0]
         assert close(d, at), (q32.size, w, k, d, at)
-        offs = np.unique(np.concatenate([g.integers(0, K, 64),
-                                         np.clip(np.arange(k - 32, k + 32), 0, K - 1)]))
+        m = q32.size
+        offs = np.unique(np.concatenate([g.integers(0, K, 4096),
+                                         np.clip(np.arange(k - m, k + m + 1), 0, K - 1)]))
         others = oracle.nn_dists(qo, xo, w, offs)
         assert others.min() >= at * (1 - 1e-5) - 1e-6, (q32.size, w)

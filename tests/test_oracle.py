@@ -433,3 +433,37 @@ def test_grad_central_finite_differences():
                 assert abs(fd - grad[k]) <= 1e-8 * max(1.0, abs(grad[k])), (which, k)
                 checked += 1
     assert checked > 200
+
+
+# ----------------------------------------------------------------------------- EAPrunedDTW scan
+
+@pytest.mark.parametrize("m,w,threads", [(16, 2, 1), (32, 5, 4), (24, 23, 3), (20, 0, 2)])
+def test_eap_scan_is_the_brute_force_search(m, w, threads):
+    """The scan with the EAPrunedDTW model under the shared best-so-far
+    returns the brute-force answer (lexicographic minimum of (distance,
+    offset)) and evaluates no more cells than the window admits."""
+    g = np.random.default_rng(m * 100 + w)
+    x = np.cumsum(g.standard_normal(900))
+    q = np.cumsum(g.standard_normal(m))
+    x[500:500 + m] = q * 2.0 + 7.0          # a planted copy (same z-normalised shape)
+    K = x.size - m + 1
+    k, d, cells = oracle.eap_scan(q, x, w, np.arange(K), nthreads=threads)
+    kb, db = oracle.nn_search(q, x, w)
+    assert (k, d) == (kb, db) or (k == kb and d == pytest.approx(db, rel=1e-12, abs=1e-12))
+    assert k == 500 and d == pytest.approx(0.0, abs=1e-9)
+    per = sum(min(m - 1, i + w) - max(0, i - w) + 1 for i in range(m))
+    assert 0 < cells <= per * K
+
+
+def test_eap_scan_prunes_against_its_bound():
+    """With the planted copy first in scan order, every later candidate meets
+    a bound of 0 and stops early: far fewer cells than the window admits."""
+    g = np.random.default_rng(9)
+    m, w = 32, 6
+    q = np.cumsum(g.standard_normal(m))
+    x = np.concatenate([q, np.cumsum(g.standard_normal(2000))])
+    K = x.size - m + 1
+    k, d, cells = oracle.eap_scan(q, x, w, np.arange(K), nthreads=1)
+    per = sum(min(m - 1, i + w) - max(0, i - w) + 1 for i in range(m))
+    assert k == 0 and d == pytest.approx(0.0, abs=1e-9)
+    assert cells < 0.2 * per * K
