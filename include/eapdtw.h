@@ -211,8 +211,14 @@ int eapdtw_nn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float
                      eapdtw_stats *stats);
 
 /* ---------------------------------------------------------------------------
- * Many queries of uneven length and window against one series, in one
- * persistent launch (each query: the search of eapdtw_nn_search).
+ * Many queries of uneven length and window against one series (Section 2.2's
+ * search per query; each query's answer is that of eapdtw_nn_search), replayed
+ * as one captured hipGraph.  Queries with windows above 64 share one
+ * persistent launch whose workgroups take 64-offset units from a device work
+ * queue; queries with windows up to 64 each get their own band-kernel launch,
+ * spread over concurrent streams (option "batch_branches"): measured faster
+ * than feeding those windows through the persistent tiled kernel, whose
+ * per-tile boundary traffic the band kernels do not pay.
  *   qs [nq] : HOST array of queries (query pointers are DEVICE).
  *   out [nq]: HOST results.
  * Synchronous. */
@@ -247,7 +253,9 @@ typedef struct {
  * query's bucket and returns it in *out (may be NULL).  With option
  * "autotune" = 1, eapdtw_nn_search, eapdtw_nn_dists and eapdtw_nn_search_batch
  * apply the recorded choices of each query's bucket, and the batch tunes a
- * bucket it has no record for on first use.  Synchronous. */
+ * bucket it has no record for on first use.  Off by default: the defaults
+ * were chosen from the same sweeps, and on the 64-query batched workload the
+ * tuned choices were not faster than them.  Synchronous. */
 int eapdtw_autotune(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                     int64_t n, int64_t window, int64_t sample_n, eapdtw_tune *out);
 
