@@ -151,6 +151,13 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *                      (recorded sweeps: only among the classes that keep the
  *                      pair's codes in LDS, so the record size never depends
  *                      on it).  Same results for every value
+ *   "scratch_limit"  : test hook: the largest device scratch (bytes) the
+ *                      context may allocate; a call that needs more returns
+ *                      ENOMEM without allocating (0 = no limit, the default)
+ *   "inject_fault"   : test hook: 1 = the next call on the context fails as if
+ *                      the device had reported a fault (EDEVICE, no device
+ *                      work is done) and poisons the context: every later
+ *                      call returns EPOISONED
  * Returns EINVAL for an unknown key or value. */
 int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
 int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);

@@ -48,6 +48,10 @@ struct eapdtw_ctx {
   int64_t autotune = 0;
   int64_t lanes = 0;  // band search with lane refill where it applies
   int64_t wf_lanes = 0;  // wavefront pair kernels: lanes per pair (0 = by size, 16, 32 or 64)
+  // test hooks (host only; no device work): a cap on the scratch the context
+  // may allocate (0: none), and a device fault reported by the next call
+  int64_t scratch_limit = 0;
+  int64_t inject_fault = 0;
   int64_t lb_ec = 0;         // cascade: apply the candidate-envelope LB_Keogh
   int64_t lb_probe_div = 0;  // cascade: first pass over K / div candidates (0: one pass)
   float lb_ms = 0.f, lb_dp_ms = 0.f;  // cascade timing of the last timed call
@@ -109,6 +113,10 @@ int fail_hip(eapdtw_ctx *c, hipError_t e, const char *what) {
     if (!ctx) return EAPDTW_EINVAL;                                          \
     if (ctx->poisoned) return fail(ctx, EAPDTW_EPOISONED, "context poisoned by an earlier device fault"); \
     ctx->err.clear();                                                        \
+    if (ctx->inject_fault) {                                                 \
+      ctx->inject_fault = 0;                                                 \
+      return fail_hip(ctx, hipErrorLaunchFailure, "injected device fault (test hook)"); \
+    }                                                                        \
   } while (0)
 
 // Byte offsets of the sub-buffers of one call inside the context scratch.
@@ -123,6 +131,8 @@ struct Plan {
 
 int ensure_scratch(eapdtw_ctx *ctx, size_t need) {
   if (need <= ctx->scratch_cap) return EAPDTW_OK;
+  if (ctx->scratch_limit > 0 && need > (size_t)ctx->scratch_limit)
+    return fail(ctx, EAPDTW_ENOMEM, "device scratch above the context's scratch_limit");
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (ctx->scratch) HIPCHK(hipFree(ctx->scratch));
   ctx->scratch = nullptr;
@@ -379,6 +389,8 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "lb_ec")) return &ctx->lb_ec;
   if (!strcmp(key, "lb_probe_div")) return &ctx->lb_probe_div;
   if (!strcmp(key, "wf_lanes")) return &ctx->wf_lanes;
+  if (!strcmp(key, "scratch_limit")) return &ctx->scratch_limit;
+  if (!strcmp(key, "inject_fault")) return &ctx->inject_fault;
   return nullptr;
 }
 
@@ -394,6 +406,8 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
     ok = value == 0 || value == 1;
   else if (!strcmp(key, "lb_probe_div")) ok = value == 0 || (value >= 2 && value <= 4096);
   else if (!strcmp(key, "wf_lanes")) ok = value == 0 || value == 16 || value == 32 || value == 64;
+  else if (!strcmp(key, "scratch_limit")) ok = value >= 0;
+  else if (!strcmp(key, "inject_fault")) ok = value == 0 || value == 1;
   else if (!strcmp(key, "rows_per_group")) ok = value == 0 || value == 2 || value == 4 || value == 8;
   else if (!strcmp(key, "wide_rows")) ok = value == 0 || value == 32 || value == 64;
   else if (!strcmp(key, "seed_stride")) ok = value >= 0 && value <= (1 << 20);
@@ -2222,6 +2236,10 @@ static int wf_batch_backward(eapdtw_ctx *ctx, const float *S, const float *T,
   WfGradArgs g{};
   g.pairs = run.desc;
   g.npairs = (int64_t)hp.size();
+  for (const WfHostPair &h : hp) {
+    if (h.ls > g.max_ls) g.max_ls = (int)h.ls;
+    if (h.lt > g.max_lt) g.max_lt = (int)h.lt;
+  }
   g.status = run.rec.status;
   g.S = S;
   g.T = T;

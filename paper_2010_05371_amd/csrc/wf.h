@@ -34,7 +34,7 @@ constexpr int kWfNC[kWfClasses] = {1, 2, 1, 4, 2, 1, 2, 4, 8};
 constexpr int kWfMaxP = 512;
 constexpr int kWfChunk = 16;               // steps per direction word (2 bits each)
 constexpr int kWfLdsFloats = 16384;        // LDS of one wave (64 KB)
-constexpr int kWfPad = kWfChunk + 1;       // guard cells on each side of a staged T
+constexpr int kWfPad = 2 * kWfChunk + 1;   // guard cells on each side of a staged T (chunks of up to 32 steps)
 constexpr int kWfMaxLen = 8191;            // longest series of a wavefront pair
 constexpr int kDbaPairs = 64;              // pairs per partial sum of the DBA update
 // Waves a launch should reach: two per SIMD lets the SIMDs issue VALU
@@ -174,7 +174,8 @@ hipError_t launch_wf_walk(int P, const WfWalkArgs &a, hipStream_t st);
 struct WfGradArgs {
   const WfPair *pairs;
   int64_t npairs;
-  int ls, lt;
+  int ls, lt;                // uniform pairs (pairs == nullptr)
+  int max_ls, max_lt;        // pairs != nullptr: the longest series of the launch
   const unsigned *status;    // WfStatus [pair]
   const float *S, *T;
   const unsigned *rowrng, *colrng;

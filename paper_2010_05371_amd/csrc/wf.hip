@@ -98,22 +98,22 @@ __device__ __forceinline__ bool has_path(const PairView &v) {
 // inactive lane-slot acts as a border cell.
 //
 // Time.  The pair's steps are t = 0 .. ns-1 (ns = ls + lt - 1); the group
-// starts at t = -e with e = (-ns) mod 16, so its last step closes a chunk of
-// 16 and the distance is read at a chunk's end.  Before t = 0, lane-slot P-1
-// holds a virtual row -1 whose cells cost (0 - 0)^2 = 0 (the left guard is 0)
-// and carry the value 0 up to step -2: it is M(0,0) = 0, the diagonal
-// predecessor of cell (0,0), and then leaves (+inf above row 0).
+// starts at t = -e with e = (-ns) mod 16, so its last step closes a 16-step
+// code word and the distance is read at the end of one.  Before t = 0,
+// lane-slot P-1 holds a virtual row -1 whose cells cost (0 - 0)^2 = 0 (the
+// left guard is 0) and carry the value 0 up to step -2: it is M(0,0) = 0, the
+// diagonal predecessor of cell (0,0), and then leaves (+inf above row 0).
 //
-// Steps run in chunks of kWfChunk.  A lane-slot's rows start at least P >= 16
-// steps apart, so a chunk involves at most its current row a and the next
-// row b = a + P: per chunk it prepares b's state, the steps that use b, and
-// the mask of its active steps; a step then only selects between the two.
+// Steps run in chunks of CH = 16 steps (32 when P >= 32).  A lane-slot's
+// rows start at least P >= CH steps apart, so a chunk involves at most its
+// current row a and the next row b = a + P: per chunk it prepares b's state,
+// the steps that use b, and the mask of its active steps; a step then only
+// selects between the two.
 // MODE 0 computes distances only.  MODE 1 also writes every cell's argmin
-// code to the record: chunk k = (t + e) / 16 is word rec[rec_off + k P + c G + g],
-// step t at bits 2 ((t + e) % 16).  MODE 2 keeps those words in the
-// group's LDS and, after the sweep, follows them back from (ls-1, lt-1) itself
-// (the backtrack of wf_walk_kernel, one path cell per iteration on the group's
-// lanes) and writes the path ranges.
+// code to the record: word k = (t + e) / 16 of lane-slot l is
+// rec[rec_off + k P + l], step t at bits 2 ((t + e) % 16).  MODE 2 keeps those
+// words in the group's LDS and recovers the path in the same launch (the
+// reverse sweep below), then writes the path ranges.
 
 // (m & a) | (~m & b): with m all ones or all zeros, a or b (v_bfi_b32)
 __device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
@@ -155,12 +155,14 @@ __device__ __forceinline__ float lds_load(uint32_t a) {
   return *(const __attribute__((address_space(3))) float *)(uintptr_t)a;
 }
 
+// bits lo..hi of a CH-bit mask (empty when lo > hi), lo/hi clipped to 0..CH-1
+template <int CH>
 __device__ __forceinline__ unsigned bit_range(int lo, int hi) {
-  // bits lo..hi of a 16-bit mask (empty when lo > hi), lo/hi clipped to 0..15
   lo = lo < 0 ? 0 : lo;
-  hi = hi > kWfChunk - 1 ? kWfChunk - 1 : hi;
+  hi = hi > CH - 1 ? CH - 1 : hi;
   if (lo > hi) return 0u;
-  return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
+  const unsigned top = hi == 31 ? ~0u : ((2u << hi) - 1u);
+  return top & ~((1u << lo) - 1u);
 }
 
 __device__ __forceinline__ int wf_lead(int ns) { return (kWfChunk - ns % kWfChunk) % kWfChunk; }
@@ -169,6 +171,13 @@ template <int G, int NC, int MODE>
 __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
   constexpr bool REC = MODE != 0;
   constexpr int P = G * NC;
+  // steps per chunk: a chunk of at most P steps meets at most two rows of a
+  // lane-slot (its rows start at least P steps apart), so classes with 32 or
+  // more lane-slots and at most two cells per lane take 32 steps per chunk
+  // (half the per-chunk work per step; with more cells per lane the longer
+  // chunk's registers would not fit)
+  constexpr int CH = (P >= 32 && NC <= 2) ? 32 : kWfChunk;
+  constexpr int NW = CH / kWfChunk;  // code words per lane-slot and chunk
   constexpr int GPW = kWave / G;
   extern __shared__ float lds[];
   const int lane = threadIdx.x;
@@ -270,7 +279,7 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
   uint64_t evaluated = 0, chunks = 0;
 
 #pragma unroll 1
-  for (int tau0 = 0; tau0 < nsw; tau0 += kWfChunk) {
+  for (int tau0 = 0; tau0 < nsw; tau0 += CH) {
     const int t0 = tau0 - e;  // the group's step at the chunk's start
     // per slot: row b's state, the steps of the chunk that use row b
     // (bsel), the inactive steps (idle), and the T reads of both rows
@@ -284,26 +293,28 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
       svA[c] = __float_as_uint(sv[c]);
       svBb[c] = __float_as_uint(s_of(rowB[c]));
       const int ea = te[c] - t0 + 1;  // row a is current for steps s < sw
-      const int sw = ea > kWfChunk ? kWfChunk : ea;
-      bsel[c] = bit_range(sw, kWfChunk - 1);
-      idle[c] = ~(bit_range(ts[c] - t0, sw - 1) | bit_range(tsB[c] - t0, teB[c] - t0));
+      const int sw = ea > CH ? CH : ea;
+      bsel[c] = bit_range<CH>(sw, CH - 1);
+      idle[c] = ~(bit_range<CH>(ts[c] - t0, sw - 1) | bit_range<CH>(tsB[c] - t0, teB[c] - t0));
       int ja = t0 - row[c], jb = t0 - rowB[c];
       ja = ja < -kWfPad ? -kWfPad : (ja > lt ? lt : ja);
       jb = jb < -kWfPad ? -kWfPad : (jb > lt ? lt : jb);
       pa[c] = lds_addr(tbase + ja);
       pb[c] = lds_addr(tbase + jb);
     }
-    unsigned cw[NC];
+    unsigned cw[NC][NW];
     float c14[NC];  // values of the chunk's second-to-last step
 #pragma unroll
-    for (int c = 0; c < NC; ++c) cw[c] = 0u;
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int h = 0; h < NW; ++h) cw[c][h] = 0u;
     // The cost differences of SUB steps, prepared ahead of their sweep so that
     // the LDS reads are in flight together: S(row) - T(t - row) on the
     // lane-slot's active steps, all-ones (a NaN) on the others.  Selections
     // use sign-extended mask bits (no compares).
-    constexpr int SUB = NC >= 4 ? 4 : kWfChunk;
+    constexpr int SUB = NC >= 4 ? 4 : (NC == 2 ? 16 : CH);
 #pragma unroll
-    for (int s0 = 0; s0 < kWfChunk; s0 += SUB) {
+    for (int s0 = 0; s0 < CH; s0 += SUB) {
       float dv[NC][SUB];
       // all reads first, then the arithmetic: one wait for the whole batch
       uint32_t bm[NC][SUB];
@@ -327,9 +338,16 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
 #pragma unroll
       for (int u = 0; u < SUB; ++u) {
         const int s = s0 + u;
-        if (s == kWfChunk - 1) {
+        if (s == CH - 1) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) c14[c] = cur[c];
+        }
+        if (s == kWfChunk && t0 + kWfChunk - 1 == ns - 1) {
+          // the group's last step closed the chunk's first half: the cell
+          // (ls-1, lt-1) of lane-slot (ls-1) mod P
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (le / G == c) fin = cur[c];
         }
         float rot[NC];
 #pragma unroll
@@ -350,7 +368,7 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
             // code 0: diagonal, 1: (i-1, j), 2: (i, j-1), ties in that order
             const uint32_t x = umin2(upb - mb, 1u);
             const uint32_t y = umin2(topb - mb, x);
-            cw[c] |= (x + y) << (2 * s);
+            cw[c][s / kWfChunk] |= (x + y) << (2 * (s % kWfChunk));
           }
           up[c] = __uint_as_float(topb);
           cur[c] = __builtin_fmaf(dv[c][u], dv[c][u], __uint_as_float(mb));
@@ -358,13 +376,16 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
       }
     }
     if constexpr (REC) {
-      if (tau0 < nsp) {
-        unsigned *w = rec + (tau0 / kWfChunk) * P + g;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) w[c * G] = cw[c];
+      for (int h = 0; h < NW; ++h) {
+        if (tau0 + h * kWfChunk < nsp) {
+          unsigned *w = rec + (tau0 / kWfChunk + h) * P + g;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) w[c * G] = cw[c][h];
+        }
       }
     }
-    if (t0 + kWfChunk - 1 == ns - 1) {
+    if (t0 + CH - 1 == ns - 1) {
       // the group's last step: the cell (ls-1, lt-1) of lane-slot (ls-1) mod P
 #pragma unroll
       for (int c = 0; c < NC; ++c)
@@ -372,7 +393,7 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
     }
     if (alive) {
       // matrix cells only (not the virtual row)
-      const unsigned lim = bit_range(-t0, ns - 1 - t0);
+      const unsigned lim = bit_range<CH>(-t0, ns - 1 - t0);
 #pragma unroll
       for (int c = 0; c < NC; ++c) evaluated += __builtin_popcount(~idle[c] & lim);
     }
@@ -386,9 +407,9 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
       // a bound of NaN never abandons
       if (alive && __uint_as_float(m) > ubv) alive = false;
     }
-    if (!__builtin_amdgcn_ballot_w64(alive && tau0 + kWfChunk < nsp)) break;
+    if (!__builtin_amdgcn_ballot_w64(alive && tau0 + CH < nsp)) break;
     // the first row not ended by the chunk's last step: a, b or b + P
-    const int tl = t0 + kWfChunk - 1;
+    const int tl = t0 + CH - 1;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (te[c] > tl) continue;
@@ -414,7 +435,7 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
     if (lane == 0) {
       unsigned long long *cs = counter_stripe(a.counters, blockIdx.x);
       atomicAdd(&cs[kCntEvaluated], (unsigned long long)ev);
-      atomicAdd(&cs[kCntComputed], (unsigned long long)(chunks * kWfChunk * kWave * NC));
+      atomicAdd(&cs[kCntComputed], (unsigned long long)(chunks * CH * kWave * NC));
       if (ab) atomicAdd(&cs[kCntAbandoned], (unsigned long long)ab);
     }
   }
@@ -655,6 +676,12 @@ __global__ __launch_bounds__(256) void wf_grad_kernel(WfGradArgs a) {
     for (int k = threadIdx.x; k < v.lt; k += blockDim.x) gT[k] = fill;
     return;
   }
+  // both series staged in LDS (coalesced), then every range sum reads LDS
+  extern __shared__ float gsh[];
+  float *Sl = gsh, *Tl = gsh + v.ls;
+  for (int k = threadIdx.x; k < v.ls; k += blockDim.x) Sl[k] = Sp[k];
+  for (int k = threadIdx.x; k < v.lt; k += blockDim.x) Tl[k] = Tp[k];
+  __syncthreads();
   const float g2 = 2.0f * a.gout[p];
   const unsigned *rr = a.rowrng + v.s_off;
   const unsigned *cr = a.colrng + v.t_off;
@@ -663,9 +690,9 @@ __global__ __launch_bounds__(256) void wf_grad_kernel(WfGradArgs a) {
     const int lo = (int)(w & 0xffffu);
     int hi = (int)(w >> 16);
     hi = hi < v.lt - 1 ? hi : v.lt - 1;
-    const float s = Sp[i];
+    const float s = Sl[i];
     float acc = 0.0f;
-    for (int jj = lo; jj <= hi; ++jj) acc += s - Tp[jj];
+    for (int jj = lo; jj <= hi; ++jj) acc += s - Tl[jj];
     gS[i] = g2 * acc;
   }
   for (int j = threadIdx.x; j < v.lt; j += blockDim.x) {
@@ -673,9 +700,9 @@ __global__ __launch_bounds__(256) void wf_grad_kernel(WfGradArgs a) {
     const int lo = (int)(w & 0xffffu);
     int hi = (int)(w >> 16);
     hi = hi < v.ls - 1 ? hi : v.ls - 1;
-    const float tv = Tp[j];
+    const float tv = Tl[j];
     float acc = 0.0f;
-    for (int ii = lo; ii <= hi; ++ii) acc += Sp[ii] - tv;
+    for (int ii = lo; ii <= hi; ++ii) acc += Sl[ii] - tv;
     gT[j] = -g2 * acc;
   }
 }
@@ -779,7 +806,10 @@ hipError_t launch_wf_walk(int P, const WfWalkArgs &a, hipStream_t st) {
 
 hipError_t launch_wf_grad(const WfGradArgs &a, hipStream_t st) {
   if (a.npairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(wf_grad_kernel, dim3((unsigned)a.npairs), dim3(256), 0, st, a);
+  const int mls = a.pairs ? a.max_ls : a.ls, mlt = a.pairs ? a.max_lt : a.lt;
+  if (mls < 0 || mlt < 0 || mls > kWfMaxLen || mlt > kWfMaxLen) return hipErrorInvalidValue;
+  const size_t lds = sizeof(float) * (size_t)(mls + mlt);
+  hipLaunchKernelGGL(wf_grad_kernel, dim3((unsigned)a.npairs), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
