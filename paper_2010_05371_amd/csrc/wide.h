@@ -167,6 +167,29 @@ __device__ __forceinline__ void wide_fetch(const WideArgs &a, const WideProblem 
   cv = in ? wide_col_value<KIND>(a, p, c) : 0.0f;
 }
 
+// Unconditional form for the rotating queue: both loads are issued for every
+// column (from a clamped, valid column) with no branch around them, and the
+// boundary value's validity travels beside it as a wave-uniform flag applied
+// when the column is used -- so the compiler waits only for the loads of the
+// column about to be computed.  (A column past the tile's end is never used.)
+template <int KIND, int PD>
+__device__ __forceinline__ void wide_fetch_raw(const WideArgs &a, const WideProblem &p,
+                                               const float *Bw, int lane, const Sweep<PD> &s,
+                                               int c, float &top, float &cv, bool &have_top) {
+  have_top = c <= s.jend && s.t > 0 && c >= s.bv_lo && c <= s.bv_hi;
+  const int cc = c < 0 ? 0 : (c > a.lcol - 1 ? a.lcol - 1 : c);
+  top = Bw[(int64_t)(cc + 1) * kWave + lane];
+  cv = wide_col_value<KIND>(a, p, cc);
+}
+
+template <int H, int KIND, int H_LO, int H_HI, int PD>
+__device__ __forceinline__ void wide_step_body(const WideArgs &a, float *Bw, int lane,
+                                               float (&col)[H], const float (&rv)[H], Sweep<PD> &s,
+                                               float ub, int tlast, int hans, float &ans,
+                                               float top0, float cv);
+
+// One column: its prefetched values leave the front of the queue, whose
+// entries shift down, and column j + PD enters at the back.
 template <int H, int KIND, int H_LO, int H_HI, int PD>
 __device__ __forceinline__ void wide_step(const WideArgs &a, const WideProblem &p, float *Bw,
                                           int lane, float (&col)[H], const float (&rv)[H],
@@ -180,6 +203,32 @@ __device__ __forceinline__ void wide_step(const WideArgs &a, const WideProblem &
     s.qcv[k] = s.qcv[k + 1];
   }
   wide_fetch<KIND, PD>(a, p, Bw, lane, s, j + PD, s.qtop[PD - 1], s.qcv[PD - 1]);
+  wide_step_body<H, KIND, H_LO, H_HI, PD>(a, Bw, lane, col, rv, s, ub, tlast, hans, ans, top0, cv);
+}
+
+// One column taking queue slot K (the column's index from the queue's start,
+// mod PD) and refilling the same slot with column j + PD.  Slots rotate
+// statically over PD unrolled steps, so no register is moved while its load
+// is in flight: a move would have to wait for the load, and the queue's
+// moves made every column wait for the loads issued just before it.
+template <int H, int KIND, int PD, int K>
+__device__ __forceinline__ void wide_step_slot(const WideArgs &a, const WideProblem &p, float *Bw,
+                                               int lane, float (&col)[H], const float (&rv)[H],
+                                               Sweep<PD> &s, bool (&qhave)[PD], float ub,
+                                               int tlast, int hans, float &ans) {
+  const int j = s.j;
+  const float top0 = qhave[K] ? s.qtop[K] : kInf;
+  const float cv = s.qcv[K];
+  wide_fetch_raw<KIND, PD>(a, p, Bw, lane, s, j + PD, s.qtop[K], s.qcv[K], qhave[K]);
+  wide_step_body<H, KIND, 0, H - 1, PD>(a, Bw, lane, col, rv, s, ub, tlast, hans, ans, top0, cv);
+}
+
+template <int H, int KIND, int H_LO, int H_HI, int PD>
+__device__ __forceinline__ void wide_step_body(const WideArgs &a, float *Bw, int lane,
+                                               float (&col)[H], const float (&rv)[H], Sweep<PD> &s,
+                                               float ub, int tlast, int hans, float &ans,
+                                               float top0, float cv) {
+  const int j = s.j;
   wide_column<H, H_LO, H_HI, false>(col, rv, cv, top0, s.diag0);
   s.diag0 = top0;
   Bw[(int64_t)(j + 1) * kWave + lane] = col[H - 1];
@@ -384,11 +433,26 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
       ExitPhase<H, KIND, 0, PD>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 + r + 1);
     } else {
       // the window covers the whole matrix: every column is a full column
-      while (s.go) {
-        // (two-column steps only pay off while the doubled state still fits
-        // in registers at a useful occupancy)
-        if (H <= 32 && wide_pair_ok(s, s.jend, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ub);
-        else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+      if constexpr (H > 32) {
+        // PD columns per iteration, queue slots in static rotation
+        static_assert(PD == 4, "four queue slots per rotation");
+        bool qhave[PD];
+#pragma unroll
+        for (int k = 0; k < PD; ++k)
+          wide_fetch_raw<KIND, PD>(a, p, Bw, lane, s, s.j + k, s.qtop[k], s.qcv[k], qhave[k]);
+        while (s.go) {
+          wide_step_slot<H, KIND, PD, 0>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
+          if (s.go) wide_step_slot<H, KIND, PD, 1 % PD>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
+          if (s.go) wide_step_slot<H, KIND, PD, 2 % PD>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
+          if (s.go) wide_step_slot<H, KIND, PD, 3 % PD>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
+        }
+      } else {
+        while (s.go) {
+          // (two-column steps only pay off while the doubled state still fits
+          // in registers at a useful occupancy)
+          if (wide_pair_ok(s, s.jend, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ub);
+          else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+        }
       }
     }
     evaluated += s.evaluated;
