@@ -268,6 +268,36 @@ def c5_section(eap, steps, cpu_budget):
     fwd_rec_ms = launch_ms(fwd_rec)
     bwd_ms = launch_ms(bwd)
     fwd_ms = launch_ms(fwd_only)
+    # the same two calls captured once as a HIP graph and replayed: one host
+    # launch per step keeps the GPU fed back to back (the C-ABI loop above is
+    # bound by the host's per-call work, and the GPU idles between calls)
+    gS_eager, gT_eager = gS.clone(), gT.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.bind_stream()
+        for _ in range(3):
+            fwd_rec()
+            bwd()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ctx.bind_stream()
+        fwd_rec()
+        bwd()
+    ctx.bind_stream()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
+    graph_same = bool(torch.equal(gS, gS_eager) and torch.equal(gT, gT_eager))
+    del graph
     # the same through autograd.Function (Python wall time per step)
     Sg, Tg = S.clone().requires_grad_(True), T.clone().requires_grad_(True)
     for _ in range(2):
@@ -289,6 +319,8 @@ def c5_section(eap, steps, cpu_budget):
         "pairs": P, "len": L, "window": w, "steps": steps,
         "fwd_bwd_pairs_per_s": P / (fb_ms / 1e3), "fwd_bwd_ms": round(fb_ms, 4),
         "fwd_pairs_per_s": P / (f_ms / 1e3), "fwd_ms": round(f_ms, 4),
+        "graph_fwd_bwd_pairs_per_s": P / (graph_ms / 1e3), "graph_fwd_bwd_ms": round(graph_ms, 4),
+        "graph_grads_equal_eager": graph_same,
         "autograd_fwd_bwd_pairs_per_s": P / (ag_ms / 1e3), "autograd_fwd_bwd_ms": round(ag_ms, 4),
         "autograd_grads_equal_c_abi": same,
         "recorded_fwd_launch_ms": round(fwd_rec_ms, 4), "bwd_launch_ms": round(bwd_ms, 4),

@@ -91,7 +91,14 @@ int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out);
 /* Releases the context and its device scratch.  NULL is ignored. */
 void eapdtw_destroy(eapdtw_ctx *ctx);
 
-/* Re-targets the context's stream (hipStream_t, NULL = null stream). */
+/* Re-targets the context's stream (hipStream_t, NULL = null stream).  The
+ * context first waits for its old stream (its scratch may still be in use
+ * there), except when the new stream is being captured into a graph, where no
+ * wait is allowed: the caller then orders the two streams (as graph capture
+ * requires anyway).  Entry points that read results back to the host, or
+ * whose scratch must grow, cannot run under capture; the differentiable
+ * batch's forward with a record and its backward can, once a first call has
+ * sized the scratch. */
 int eapdtw_set_stream(eapdtw_ctx *ctx, void *hip_stream);
 
 /* Text of the context's last failure ("" if none).  With ctx == NULL: the

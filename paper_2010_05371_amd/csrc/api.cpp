@@ -357,8 +357,12 @@ void eapdtw_destroy(eapdtw_ctx *ctx) {
 int eapdtw_set_stream(eapdtw_ctx *ctx, void *hip_stream) {
   CHECK_CTX();
   if ((hipStream_t)hip_stream != ctx->stream) {
-    // scratch may still be in use on the old stream
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // scratch may still be in use on the old stream; a stream that is being
+    // captured into a graph cannot wait here (no synchronisation is allowed
+    // during a capture): the capturing caller orders the two streams itself
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing((hipStream_t)hip_stream, &cs));
+    if (cs == hipStreamCaptureStatusNone) HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->stream = (hipStream_t)hip_stream;
   }
   return EAPDTW_OK;

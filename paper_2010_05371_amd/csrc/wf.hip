@@ -165,6 +165,33 @@ __device__ __forceinline__ unsigned bit_range(int lo, int hi) {
   return top & ~((1u << lo) - 1u);
 }
 
+// Copies src[0 .. n) (n >= 1) to LDS with the group's G lanes, eight loads per
+// lane in flight before their stores (from clamped, always valid indexes, so
+// no branch splits them): when the series come from HBM rather than the
+// caches, a load-store-load chain would cost one memory latency per element.
+// Notes a non-finite value in `bad`.
+template <int G>
+__device__ __forceinline__ void stage_series(const float *__restrict__ src, float *dst, int n,
+                                             int g, bool &bad) {
+  constexpr int B = 8;
+  for (int k0 = g; k0 < n; k0 += B * G) {
+    float x[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int k = k0 + u * G;
+      x[u] = src[k < n ? k : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int k = k0 + u * G;
+      if (k < n) {
+        bad = bad || !__builtin_isfinite(x[u]);
+        dst[k] = x[u];
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ int wf_lead(int ns) { return (kWfChunk - ns % kWfChunk) % kWfChunk; }
 
 template <int G, int NC, int MODE>
@@ -196,16 +223,8 @@ __global__ __launch_bounds__(64) void wf_fwd_kernel(WfArgs a) {
   float *Tl = Sl + ls + kWfPad;  // Tl[j] for j in [-kWfPad, lt + kWfPad)
   bool bad = false;
   if (path) {
-    for (int k = g; k < ls; k += G) {
-      const float x = a.S[v.s_off + k];
-      bad = bad || !__builtin_isfinite(x);
-      Sl[k] = x;
-    }
-    for (int k = g; k < lt; k += G) {
-      const float x = a.T[v.t_off + k];
-      bad = bad || !__builtin_isfinite(x);
-      Tl[k] = x;
-    }
+    stage_series<G>(a.S + v.s_off, Sl, ls, g, bad);
+    stage_series<G>(a.T + v.t_off, Tl, lt, g, bad);
     for (int k = g; k < kWfPad; k += G) {
       Tl[-1 - k] = 0.0f;
       Tl[lt + k] = kInf;
@@ -679,8 +698,9 @@ __global__ __launch_bounds__(256) void wf_grad_kernel(WfGradArgs a) {
   // both series staged in LDS (coalesced), then every range sum reads LDS
   extern __shared__ float gsh[];
   float *Sl = gsh, *Tl = gsh + v.ls;
-  for (int k = threadIdx.x; k < v.ls; k += blockDim.x) Sl[k] = Sp[k];
-  for (int k = threadIdx.x; k < v.lt; k += blockDim.x) Tl[k] = Tp[k];
+  bool unused = false;
+  stage_series<256>(Sp, Sl, v.ls, threadIdx.x, unused);
+  stage_series<256>(Tp, Tl, v.lt, threadIdx.x, unused);
   __syncthreads();
   const float g2 = 2.0f * a.gout[p];
   const unsigned *rr = a.rowrng + v.s_off;

@@ -206,3 +206,54 @@ def test_c5_full_size(lanes):
         _check(S32, T32, w, gout)
     finally:
         eap.set_option("wf_lanes", old)
+
+
+def test_fwd_bwd_replayed_from_a_captured_graph():
+    """The recorded forward and the backward through the C ABI, captured once
+    as a HIP graph (no memset nodes) and replayed several times with eager
+    work and synchronisations between the replays: every replay gives the
+    eager distances and gradients bit for bit."""
+    import ctypes
+    S32, T32, w = gen.c5(P=512, L=200)
+    P, L = S32.shape
+    S, T = torch.from_numpy(S32).cuda(), torch.from_numpy(T32).cuda()
+    ctx = eap.context(0)
+    lib, h, p = ctx._lib, ctx.handle, eap._ptr
+    rec = torch.empty(int(lib.eapdtw_dtw_ckpt_bytes(P, L, w)), device="cuda", dtype=torch.uint8)
+    out = torch.empty(P, device="cuda")
+    gout = torch.from_numpy(gen.as_f32(gen.rng(53, P).uniform(0.5, 2.0, P))).cuda()
+    gS, gT = torch.empty_like(S), torch.empty_like(T)
+
+    def step():
+        ctx.check(lib.eapdtw_dtw_fwd(h, p(S), p(T), P, L, w, p(out), ctypes.c_void_p(rec.data_ptr())))
+        ctx.check(lib.eapdtw_dtw_bwd(h, p(S), p(T), P, L, w, ctypes.c_void_p(rec.data_ptr()),
+                                     p(gout), p(gS), p(gT)))
+
+    ctx.bind_stream()
+    step()
+    torch.cuda.synchronize()
+    want = (out.clone(), gS.clone(), gT.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.bind_stream()
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    try:
+        with torch.cuda.graph(graph):
+            ctx.bind_stream()
+            step()
+    finally:
+        ctx.bind_stream()
+    for k in range(4):
+        out.fill_(-1.0)
+        gS.zero_()
+        gT.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want[0]) and torch.equal(gS, want[1]) and torch.equal(gT, want[2]), k
+        # eager work between the replays
+        d = eap.DTWFunction.apply(S, T, w)
+        assert torch.equal(d, want[0])
+        torch.cuda.synchronize()
