@@ -36,26 +36,42 @@ M = 256
 N_SERIES = 2_000_000
 
 
-def kernel_source_hash() -> str:
+# The sources each measured kernel is compiled from (by name prefix): a
+# counter figure taken on other sources no longer describes the kernel.
+KERNEL_SOURCES = {
+    "nn_band_kernel": ("band.h", "common.h"),
+    "ed_search_kernel": ("ed.hip", "band.h", "common.h"),
+    "wide_kernel": ("wide.h", "band.h", "common.h"),
+    "wf_fwd_kernel": ("wf.hip", "wf.h", "common.h"),
+    "wf_grad_kernel": ("wf.hip", "wf.h", "common.h"),
+}
+
+
+def kernel_source_hash(kernel: str):
+    files = next((v for k, v in KERNEL_SOURCES.items() if kernel.startswith(k)), None)
+    if files is None:
+        return None
     h = hashlib.sha256()
-    for f in ("band.h", "common.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2010_05371_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (scaled FETCH_SIZE + WRITE_SIZE), if they were taken on the
+    kernel's current source; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(p) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != kernel_source_hash():
+    e = d.get("kernels", {}).get(kernel)
+    if not isinstance(e, dict) or e.get("source_hash") != kernel_source_hash(kernel):
         return None
-    return d.get("kernels", {}).get(kernel)
+    return e.get("bytes")
 
 
 def cpu_baseline(q32, x32, windows, budget_s: float):
@@ -259,12 +275,29 @@ def c5_section(eap, steps, cpu_budget):
         torch.cuda.synchronize()
         return _events_ms(list(zip(evs[:-1], evs[1:])))
 
+    def step_launch_ms():
+        """GPU time of the recorded forward and of the backward as they run
+        in the forward + backward loop (events between the alternating calls;
+        a gap where the GPU waits for the host counts in the launch after it)."""
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+        torch.cuda.synchronize()
+        evs[0].record()
+        for k in range(steps):
+            fwd_rec()
+            evs[2 * k + 1].record()
+            bwd()
+            evs[2 * k + 2].record()
+        torch.cuda.synchronize()
+        return (_events_ms([(evs[2 * k], evs[2 * k + 1]) for k in range(steps)]),
+                _events_ms([(evs[2 * k + 1], evs[2 * k + 2]) for k in range(steps)]))
+
     for _ in range(3):
         fwd_rec()
         bwd()
         fwd_only()
     fb_ms = wall_ms((fwd_rec, bwd))
     f_ms = wall_ms((fwd_only,))
+    fwd_rec_step_ms, bwd_step_ms = step_launch_ms()
     fwd_rec_ms = launch_ms(fwd_rec)
     bwd_ms = launch_ms(bwd)
     fwd_ms = launch_ms(fwd_only)
@@ -323,10 +356,13 @@ def c5_section(eap, steps, cpu_budget):
         "graph_grads_equal_eager": graph_same,
         "autograd_fwd_bwd_pairs_per_s": P / (ag_ms / 1e3), "autograd_fwd_bwd_ms": round(ag_ms, 4),
         "autograd_grads_equal_c_abi": same,
-        "recorded_fwd_launch_ms": round(fwd_rec_ms, 4), "bwd_launch_ms": round(bwd_ms, 4),
+        # per-launch GPU times: in the forward + backward loop, and in bursts
+        # of back-to-back calls of one kind
+        "recorded_fwd_launch_ms": round(fwd_rec_step_ms, 4), "bwd_launch_ms": round(bwd_step_ms, 4),
+        "recorded_fwd_burst_launch_ms": round(fwd_rec_ms, 4), "bwd_burst_launch_ms": round(bwd_ms, 4),
         "fwd_launch_ms": round(fwd_ms, 4),
         "band_cells": cells,
-        "roofline_fwd_bwd": _valu_roofline(k_rec, cells, fwd_rec_ms),
+        "roofline_fwd_bwd": _valu_roofline(k_rec, cells, fwd_rec_step_ms),
         "roofline_fwd": _valu_roofline(k_fwd, cells, fwd_ms),
     }
     if cpu_budget > 0:
@@ -345,9 +381,12 @@ def _band_cells(ls, lt, r):
 
 def _valu_roofline(kernel, cells, ms):
     achieved = OPS_PER_CELL * cells / (ms / 1e3)
+    traffic = load_traffic(kernel)
     return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
             "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-            "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells, "launch_ms": round(ms, 5)}
+            "traffic": traffic, "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
+            "launch_ms": round(ms, 5),
+            "hbm_gbs": traffic / (ms / 1e3) / 1e9 if traffic else None}
 
 
 def _c5_cpu(S32, T32, w, budget_s):
@@ -363,6 +402,9 @@ def _c5_cpu(S32, T32, w, budget_s):
     return {"value": n / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"the first {n} pairs, FP64 full-matrix DTW with the optimal path's "
                       f"gradient, one thread ({dt:.1f} s)"}
+
+
+C3_KERNEL = "wide_kernel<64, 1, false>"  # the tiled kernel: 64-row tiles, pairwise, whole window
 
 
 def c3_section(eap, steps):
@@ -386,7 +428,7 @@ def c3_section(eap, steps):
     st = sts[-1]
     main_ms = sum(s["main_kernel_ms"] for s in sts) / len(sts)
     npairs = N * (N - 1) // 2
-    r = _valu_roofline("wide_kernel (pairwise)", st["cells_evaluated"], main_ms)
+    r = _valu_roofline(C3_KERNEL, st["cells_evaluated"], main_ms)
     r["cells_computed_per_launch"] = st["cells_computed"]
     return {"workload": "all pairs: 2,000 random walks of length 512, full window, ub = ED",
             "pairs": npairs, "steps": steps, "pairs_per_s": npairs / (wall / 1e3),

@@ -165,6 +165,11 @@ const char *eapdtw_last_error(const eapdtw_ctx *ctx);
  *                      the device had reported a fault (EDEVICE, no device
  *                      work is done) and poisons the context: every later
  *                      call returns EPOISONED
+ *   "log"            : 1 = one line on stderr per kernel choice ("[eapdtw] "
+ *                      then the kernel, its template parameters or class and
+ *                      the launch shape); 0 = silent (default, unless the
+ *                      environment variable EAPDTW_LOG is set to a value
+ *                      other than 0 when the context is created)
  * Returns EINVAL for an unknown key or value. */
 int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value);
 int eapdtw_get_option(const eapdtw_ctx *ctx, const char *key, int64_t *value);

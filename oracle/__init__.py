@@ -77,9 +77,14 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    # ORACLE_LIB names another build of oracle.c (the sanitizer run of the
+    # pins loads an AddressSanitizer / UndefinedBehaviorSanitizer build)
+    path = os.environ.get("ORACLE_LIB")
+    if not path:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        path = _LIB
+    lib = ctypes.CDLL(path)
     i64, dp, ip = ctypes.c_int64, _c_double_p, _c_int64_p
     lib.oracle_znorm.argtypes = [dp, i64, dp]
     lib.oracle_znorm.restype = None

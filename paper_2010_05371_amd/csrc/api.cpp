@@ -5,7 +5,9 @@
 
 #include <climits>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -52,6 +54,7 @@ struct eapdtw_ctx {
   // may allocate (0: none), and a device fault reported by the next call
   int64_t scratch_limit = 0;
   int64_t inject_fault = 0;
+  int64_t log = 0;  // one stderr line per kernel choice (EAPDTW_LOG=1 at create sets it)
   int64_t lb_ec = 0;         // cascade: apply the candidate-envelope LB_Keogh
   int64_t lb_probe_div = 0;  // cascade: first pass over K / div candidates (0: one pass)
   float lb_ms = 0.f, lb_dp_ms = 0.f;  // cascade timing of the last timed call
@@ -93,6 +96,18 @@ int fail(eapdtw_ctx *c, int code, const std::string &msg) {
 bool is_fault(hipError_t e) {
   return e == hipErrorIllegalAddress || e == hipErrorLaunchFailure ||
          e == hipErrorIllegalState || e == hipErrorAssert;
+}
+
+// Launch log: which kernel (template parameters, class) and launch shape a
+// call took, one line on stderr each, when the context's option "log" is set.
+__attribute__((format(printf, 2, 3))) void logf(const eapdtw_ctx *c, const char *fmt, ...) {
+  if (!c || !c->log) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  fprintf(stderr, "[eapdtw] %s\n", buf);
 }
 
 int fail_hip(eapdtw_ctx *c, hipError_t e, const char *what) {
@@ -195,6 +210,12 @@ int64_t wide_grid(int64_t ntasks) {
 int pick_rows(const eapdtw_ctx *ctx, int r) {
   if (ctx->rows_per_group) return (int)ctx->rows_per_group;
   return r == 0 ? 8 : 4;
+}
+
+// Tile height the tiled kernel takes for a problem (the launch's choice).
+int wide_h(const eapdtw_ctx *ctx, int64_t r, int64_t lrow, int64_t lcol) {
+  const int h = wide_rows_for((int)r, (int)lrow, (int)lcol);
+  return h == kWideFullRows && ctx->wide_rows == 32 ? 32 : h;
 }
 
 // Reads `nbytes` at scratch offset `off` back into the pinned buffer and waits.
@@ -302,6 +323,7 @@ int eapdtw_create(int device, void *hip_stream, eapdtw_ctx **out) {
   eapdtw_ctx *c = new eapdtw_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (const char *lv = std::getenv("EAPDTW_LOG")) c->log = lv[0] && strcmp(lv, "0") != 0;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess ||
       hipEventCreate(&c->ev_lb[0]) != hipSuccess || hipEventCreate(&c->ev_lb[1]) != hipSuccess ||
@@ -395,6 +417,7 @@ static int64_t *option_slot(eapdtw_ctx *ctx, const char *key) {
   if (!strcmp(key, "wf_lanes")) return &ctx->wf_lanes;
   if (!strcmp(key, "scratch_limit")) return &ctx->scratch_limit;
   if (!strcmp(key, "inject_fault")) return &ctx->inject_fault;
+  if (!strcmp(key, "log")) return &ctx->log;
   return nullptr;
 }
 
@@ -406,7 +429,7 @@ int eapdtw_set_option(eapdtw_ctx *ctx, const char *key, int64_t value) {
   if (!strcmp(key, "check_interval")) ok = value >= 0 && value <= (1 << 20);
   else if (!strcmp(key, "seed") || !strcmp(key, "graph") || !strcmp(key, "force_wide") ||
            !strcmp(key, "border") || !strcmp(key, "ed") || !strcmp(key, "autotune") ||
-           !strcmp(key, "lanes") || !strcmp(key, "lb_ec"))
+           !strcmp(key, "lanes") || !strcmp(key, "lb_ec") || !strcmp(key, "log"))
     ok = value == 0 || value == 1;
   else if (!strcmp(key, "lb_probe_div")) ok = value == 0 || (value >= 2 && value <= 4096);
   else if (!strcmp(key, "wf_lanes")) ok = value == 0 || value == 16 || value == 32 || value == 64;
@@ -491,6 +514,9 @@ static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
     a.out = out;
     a.counters = cnt;
     HIPCHK(pair_band_launcher((int)r)(a, ntasks, pick_rows(ctx, (int)r), st));
+    logf(ctx, "pairs %lld x (%lld, %lld) r=%lld: pair_band_kernel<%lld,%d> grid=%lld", (long long)npairs,
+         (long long)lrow, (long long)lcol, (long long)r, (long long)r, pick_rows(ctx, (int)r),
+         (long long)ntasks);
   } else {
     WideArgs w{};
     w.lrow = (int)lrow;
@@ -510,6 +536,9 @@ static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
     w.counters = cnt;
     w.check_interval = 1;
     HIPCHK(launch_wide(kWidePairs, (int)ctx->wide_rows, w, (int)grid, st));
+    logf(ctx, "pairs %lld x (%lld, %lld) r=%lld: wide_kernel<%d,pairs> %lld blocks of 64 on %lld waves",
+         (long long)npairs, (long long)lrow, (long long)lcol, (long long)r, wide_h(ctx, r, lrow, lcol),
+         (long long)ntasks, (long long)grid);
   }
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
@@ -643,6 +672,9 @@ int eapdtw_pairwise(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int
   w.check_interval = 1;
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
   HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
+  logf(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
+       w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
+       wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -800,6 +832,10 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       HIPCHK(hipEventRecord(ctx->ev_join, ss));
       joined = false;
     }
+    logf(ctx, "search seeding: %s grid=%lld (every %lld-th block of 64), then %s window %lld, 1 workgroup%s",
+         ctx->ed ? "ed_search_kernel" : "nn_band_kernel<0,8>", (long long)((nblk + sstr - 1) / sstr),
+         (long long)sstr, wgt ? "nn_wband_kernel" : (rs == 0 && ctx->ed && !kb) ? "ed_search_kernel" : "nn_band_kernel",
+         (long long)rs, ss != st ? " on the seed stream" : "");
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev2, st));
   if (lb && lb_applies(ctx, r)) {
@@ -864,6 +900,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       b.lq = lb->lq;
       HIPCHK(nn_list_launcher((int)r)(b, (hi - lo + kWave - 1) / kWave, dists != nullptr,
                                       ctx->border != 0, st));
+      logf(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "
+           "nn_list_kernel<%lld,4,border=%d> grid=%lld", (long long)m, (long long)r, (long long)lo,
+           (long long)hi, (long long)r, ctx->border != 0, (long long)((hi - lo + kWave - 1) / kWave));
       if (time_main && pi + 1 < nranges) HIPCHK(hipEventRecord(ctx->ev_lb[e++], st));
     }
   } else if (use_band(ctx, r)) {
@@ -871,20 +910,30 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     a.counters = cnt;
     a.fixed_ub = fixed_ub;
     a.dists = dists;
+    const bool bord = ctx->border != 0 && r >= kBorderMinR;
     if (wgt) {
       HIPCHK(nn_wband_launcher((int)r)(a, nblk, dists != nullptr, ctx->border != 0, st));
+      logf(ctx, "search m=%lld r=%lld: nn_wband_kernel<%lld,4,border=%d> grid=%lld", (long long)m,
+           (long long)r, (long long)r, bord, (long long)nblk);
     } else if (kb) {
       a.knn = kb->k;
       a.knn_buf = kb->buf;
       a.knn_n = kb->n;
       HIPCHK(nn_band_launcher((int)r)(a, nblk, 4, false, ctx->border != 0, st));
-    } else if (r == 0 && ctx->ed)
+      logf(ctx, "search m=%lld r=%lld k=%d: nn_band_kernel<%lld,4,border=%d> grid=%lld", (long long)m,
+           (long long)r, kb->k, (long long)r, bord, (long long)nblk);
+    } else if (r == 0 && ctx->ed) {
       HIPCHK(launch_ed_search(a, nblk, dists != nullptr, st));
-    else if (!dists && ctx->lanes && lane_search_supported((int)r, (int)m))
+      logf(ctx, "search m=%lld r=0: ed_search_kernel grid=%lld", (long long)m, (long long)nblk);
+    } else if (!dists && ctx->lanes && lane_search_supported((int)r, (int)m)) {
       HIPCHK(launch_lane_search((int)r, a, st));
-    else
-      HIPCHK(nn_band_launcher((int)r)(a, nblk, dists ? 4 : pick_rows(ctx, (int)r), dists != nullptr,
-                                      ctx->border != 0, st));
+      logf(ctx, "search m=%lld r=%lld: lane-refill kernel", (long long)m, (long long)r);
+    } else {
+      const int u = dists ? 4 : pick_rows(ctx, (int)r);
+      HIPCHK(nn_band_launcher((int)r)(a, nblk, u, dists != nullptr, ctx->border != 0, st));
+      logf(ctx, "search m=%lld r=%lld: nn_band_kernel<%lld,%d,border=%d> grid=%lld", (long long)m,
+           (long long)r, (long long)r, u, bord, (long long)nblk);
+    }
   } else {
     WideArgs w{};
     w.lrow = (int)m;
@@ -910,6 +959,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       w.knn_n = kb->n;
     }
     HIPCHK(launch_wide(kWideSearch, (int)ctx->wide_rows, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
+    logf(ctx, "search m=%lld r=%lld: wide_kernel<%d,search> %lld blocks of 64 on %lld persistent waves",
+         (long long)m, (long long)r, wide_h(ctx, r, m, m), (long long)nblk,
+         (long long)(bnd_waves < nblk ? bnd_waves : nblk));
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev3, st));
   if (!joined) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
@@ -1299,6 +1351,9 @@ int eapdtw_nn1(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t 
   HIPCHK(launch_nn1_seed(w, (int)grid, st));
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
   HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
+  logf(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
+       w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
+       wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -1370,6 +1425,9 @@ int eapdtw_nn1_ref(eapdtw_ctx *ctx, const float *Q, int64_t nq, const float *R, 
   HIPCHK(launch_nn1_seed(w, (int)grid, st));
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
   HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
+  logf(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
+       w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
+       wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -1662,6 +1720,10 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   }
   const bool use_graph = ctx->graph != 0;
   const bool rebuild = !use_graph || !ctx->batch_exec || ctx->batch_key != key;
+  logf(ctx, "batch %lld queries: %lld band launches on up to %lld streams, %lld units of 64 offsets in "
+       "the persistent batch_main_kernel (%d waves), %lld seeding blocks; %s",
+       (long long)nq, (long long)(nq - nband_first), (long long)ctx->batch_branches, (long long)units,
+       grid, (long long)seeds, use_graph ? (rebuild ? "graph captured" : "graph replayed") : "no graph");
   if (rebuild) {
     // descriptors are constant for a given key: upload them outside the graph
     int rc = ensure_pinned(ctx, sizeof(BatchQuery) * nq);
@@ -2063,6 +2125,7 @@ static int wf_launch_batch(eapdtw_ctx *ctx, const float *S, const float *T, cons
     a.ub = ub;
     a.counters = cnt;
     HIPCHK(launch_wf_fwd(c, mode, a, ctx->stream));
+    logf(ctx, "pair batch: wf_fwd_kernel<%d,%d,%d> %lld pairs", kWfG[c], kWfNC[c], mode, (long long)n);
   }
   return EAPDTW_OK;
 }
@@ -2087,6 +2150,7 @@ static int wf_walk_batch(eapdtw_ctx *ctx, const WfBatchPlan &pl, const WfPair *d
     w.max_chunks = pl.max_chunks[gi];
     w.max_ranges = pl.max_ranges[gi];
     HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
+    logf(ctx, "pair batch: wf_walk_kernel<%d> %lld pairs", kWfG[c] * kWfNC[c], (long long)n);
   }
   return EAPDTW_OK;
 }
@@ -2253,6 +2317,7 @@ static int wf_batch_backward(eapdtw_ctx *ctx, const float *S, const float *T,
   g.gS = grad_S;
   g.gT = grad_T;
   HIPCHK(launch_wf_grad(g, ctx->stream));
+  logf(ctx, "wf_grad_kernel %lld pairs", (long long)g.npairs);
   return EAPDTW_OK;
 }
 
@@ -2360,6 +2425,8 @@ static int wf_uniform_rec_fwd(eapdtw_ctx *ctx, const float *S, const float *T, i
   a.lds_stride = (int)(u.mode == 2 ? wf_fused_words((int)len, (int)len, u.cls)
                                    : 2 * len + 2 * kWfPad);
   HIPCHK(launch_wf_fwd(u.cls, u.mode, a, ctx->stream));
+  logf(ctx, "pairs %lld x %lld r=%d: wf_fwd_kernel<%d,%d,%d>", (long long)a.nitems, (long long)len, a.r,
+       kWfG[u.cls], kWfNC[u.cls], u.mode);
   return EAPDTW_OK;
 }
 
@@ -2410,6 +2477,8 @@ int eapdtw_dtw_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npai
   a.out = out_dist;
   a.lds_stride = (int)(2 * len + 2 * kWfPad);
   HIPCHK(launch_wf_fwd(c, 0, a, ctx->stream));
+  logf(ctx, "pairs %lld x %lld r=%lld: wf_fwd_kernel<%d,%d,0>", (long long)npairs, (long long)len,
+       (long long)r, kWfG[c], kWfNC[c]);
   return EAPDTW_OK;
 }
 
@@ -2450,6 +2519,7 @@ static int wf_uniform_backward(eapdtw_ctx *ctx, const float *S, const float *T, 
     w.max_chunks = wf_chunks((int)len, (int)len);
     w.max_ranges = (int)(2 * len);
     HIPCHK(launch_wf_walk(kWfG[u.cls] * kWfNC[u.cls], w, ctx->stream));
+    logf(ctx, "wf_walk_kernel<%d> %lld pairs", kWfG[u.cls] * kWfNC[u.cls], (long long)w.nitems);
   }
   if (!grad_S) return EAPDTW_OK;
   WfGradArgs g{};
@@ -2464,6 +2534,7 @@ static int wf_uniform_backward(eapdtw_ctx *ctx, const float *S, const float *T, 
   g.gS = grad_S;
   g.gT = grad_T;
   HIPCHK(launch_wf_grad(g, ctx->stream));
+  logf(ctx, "wf_grad_kernel %lld pairs", (long long)g.npairs);
   return EAPDTW_OK;
 }
 

@@ -316,7 +316,6 @@ __device__ __forceinline__ void stage_copy(float *dst, const float *__restrict__
     if (t < N) dst[t] = tmp[j];
   }
 }
-constexpr int kBorderMinR = 24;  // narrower bands gain too little to pay for the borders
 
 struct Border {
   int lo, hi;  // diagonal chunks [kBorderChunk * lo, kBorderChunk * (hi + 1))

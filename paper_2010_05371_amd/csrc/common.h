@@ -15,6 +15,9 @@ constexpr int kBandRMax = 64;
 // columns hold +inf so that their cells evaluate to +inf.  Twice the largest
 // band window, because a row-longer-than-column pair reaches 2r past the end.
 constexpr int kColPad = 2 * kBandRMax + 16;
+// Smallest band window swept between pruning borders (narrower bands gain
+// too little to pay for the borders).
+constexpr int kBorderMinR = 24;
 // Tile heights of the wide-window kernels (banded / whole-matrix windows).
 // Banded windows take the tall tiles when 2r + 2 >= kWideBandRowsTall (every
 // search window above 64): per column, the boundary load and store, the

@@ -104,7 +104,7 @@ __device__ __forceinline__ bool has_path(const PairView &v) {
 // left guard is 0) and carry the value 0 up to step -2: it is M(0,0) = 0, the
 // diagonal predecessor of cell (0,0), and then leaves (+inf above row 0).
 //
-// Steps run in chunks of CH = 16 steps (32 when P >= 32).  A lane-slot's
+// Steps run in chunks of CH = 16 steps (32 when P >= 32 and NC <= 2).  A lane-slot's
 // rows start at least P >= CH steps apart, so a chunk involves at most its
 // current row a and the next row b = a + P: per chunk it prepares b's state,
 // the steps that use b, and the mask of its active steps; a step then only
