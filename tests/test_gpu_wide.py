@@ -138,3 +138,42 @@ def test_wide_nn_search_planted(force_wide):
     xp = gen.plant(x32, q32, 2222, a=3.0, b=1.0)
     k, d = eap.nn_search(torch.from_numpy(q32), torch.from_numpy(xp), 40)
     assert k == 2222 and d <= 1e-6
+
+
+@pytest.mark.parametrize("rows", [32, 64])
+def test_whole_window_tile_heights(rows):
+    """Whole-matrix windows under every tile height of the tiled kernel (option
+    wide_rows): pairs with ragged last tiles, all pairs, NN1 and the search,
+    against the oracle and bit for bit against the default height."""
+    L, w = 150, 149                       # 150 = 2 x 64 + 22 = 4 x 32 + 22: ragged last tiles
+    P = 70
+    X, Y = gen.random_pairs(P, L, seed=4242)
+    want = oracle.dtw_pairs(gen.as_oracle(X), gen.as_oracle(Y), w, np.arange(P), np.arange(P))
+    N = 67
+    Z = gen.as_f32(np.stack([gen.standardise(gen.random_walk(L, gen.rng(801, i))) for i in range(N)]))
+    ia, ib = np.triu_indices(N, 1)
+    want_pw = oracle.dtw_pairs(gen.as_oracle(Z), gen.as_oracle(Z), w, ia, ib)
+    g = gen.rng(902, rows)
+    x32 = gen.as_f32(gen.random_walk(1200, g))
+    q32 = gen.as_f32(gen.random_walk(97, g))
+    ko, do = oracle.nn_search(gen.as_oracle(q32), gen.as_oracle(x32), 96)
+    base = None
+    for opt in (0, rows):
+        eap.set_option("wide_rows", opt)
+        try:
+            got = _cpu(eap.dtw_pairs(torch.from_numpy(X), torch.from_numpy(Y), w))
+            pw = _cpu(eap.pairwise(torch.from_numpy(Z), w))
+            idx, dist = eap.nn1(torch.from_numpy(Z), w)
+            k, d = eap.nn_search(torch.from_numpy(q32), torch.from_numpy(x32), 96)
+        finally:
+            eap.set_option("wide_rows", 0)
+        assert_close_array(got, want, what=f"pairs rows={opt}")
+        assert_close_array(pw, want_pw, what=f"pairwise rows={opt}")
+        check_nn(k, d, ko, do, oracle.nn_dists(gen.as_oracle(q32), gen.as_oracle(x32), 96, [k])[0])
+        cur = (got, pw, np.asarray(idx), np.asarray(dist), k, d)
+        if base is None:
+            base = cur
+        else:
+            for a, b in zip(base[:4], cur[:4]):
+                assert np.array_equal(a, b)
+            assert base[4:] == cur[4:]
