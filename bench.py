@@ -344,6 +344,16 @@ def c5_section(eap, steps, cpu_budget):
     torch.cuda.synchronize()
     ag_ms = (time.perf_counter() - t0) * 1e3 / steps
     same = bool(torch.equal(Sg.grad, gS) and torch.equal(Tg.grad, gT))
+    # the same pairs one call each (the first 256, distance-only forward)
+    n1 = min(P, 256)
+    o1 = torch.empty(1, device=dev)
+
+    def per_pair():
+        for i in range(n1):
+            ctx.check(lib.eapdtw_dtw_fwd(h, p(S[i]), p(T[i]), 1, L, w, p(o1), None))
+
+    per_pair()
+    pp_ms = wall_ms((per_pair,)) if steps >= 1 else float("nan")
     cells = P * _band_cells(L, L, w)
     k_rec = f"wf_fwd_kernel<{cls_rec['lanes']}, {cls_rec['slots']}, {2 if cls_rec['codes_in_lds'] else 1}>"
     k_fwd = f"wf_fwd_kernel<{cls_fwd['lanes']}, {cls_fwd['slots']}, 0>"
@@ -352,6 +362,7 @@ def c5_section(eap, steps, cpu_budget):
         "pairs": P, "len": L, "window": w, "steps": steps,
         "fwd_bwd_pairs_per_s": P / (fb_ms / 1e3), "fwd_bwd_ms": round(fb_ms, 4),
         "fwd_pairs_per_s": P / (f_ms / 1e3), "fwd_ms": round(f_ms, 4),
+        "per_pair_calls_fwd_pairs_per_s": n1 / (pp_ms / 1e3),
         "graph_fwd_bwd_pairs_per_s": P / (graph_ms / 1e3), "graph_fwd_bwd_ms": round(graph_ms, 4),
         "graph_grads_equal_eager": graph_same,
         "autograd_fwd_bwd_pairs_per_s": P / (ag_ms / 1e3), "autograd_fwd_bwd_ms": round(ag_ms, 4),
@@ -404,6 +415,39 @@ def _c5_cpu(S32, T32, w, budget_s):
                       f"gradient, one thread ({dt:.1f} s)"}
 
 
+def c1_section(eap, steps):
+    """Small search: a 128-point random-walk query against an independent
+    20,000-point random walk, window 13 (per call: candidates/s, effective and
+    nominal GCUPS, the pruned-or-abandoned fraction, the main kernel's VALU
+    fraction)."""
+    import numpy as np
+    import torch
+
+    import gen
+    q32, x32, w = gen.c1()
+    q, x = torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda()
+    K = x.numel() - q.numel() + 1
+    for _ in range(3):
+        eap.nn_search(q, x, w)
+    torch.cuda.synchronize()
+    walls, sts = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        (k, d), st = eap.nn_search(q, x, w, stats=True)
+        walls.append((time.perf_counter() - t0) * 1e3)
+        sts.append(st)
+    wall = float(np.median(walls))
+    main_ms = float(np.median([s_["main_kernel_ms"] for s_ in sts]))
+    st = sts[-1]
+    r = _valu_roofline(f"nn_band_kernel<{w}, 4, false, false>", st["cells_evaluated"], main_ms)
+    return {"workload": "nn_search random walk n=20,000, m=128, window 13", "candidates": K,
+            "steps": steps, "candidates_per_s": K / (wall / 1e3), "call_ms": round(wall, 4),
+            "main_kernel_ms": round(main_ms, 4), "best": [int(k), float(d)],
+            "effective_gcups": st["cells_evaluated"] / (wall / 1e3) / 1e9,
+            "nominal_gcups": st["cells_nominal"] / (wall / 1e3) / 1e9,
+            "pruned_fraction": 1.0 - st["cells_evaluated"] / st["cells_nominal"], "roofline": r}
+
+
 C3_KERNEL = "wide_kernel<64, 1, false>"  # the tiled kernel: 64-row tiles, pairwise, whole window
 
 
@@ -438,7 +482,7 @@ def c3_section(eap, steps):
             "roofline": r}
 
 
-def c4_section(eap, steps):
+def c4_section(eap, steps, variants=True):
     """Batched uneven search: 64 random-walk queries (lengths 64-1024, windows
     5-20 %) against a 10,000,000-point random walk, as one batched call and as
     64 single-query calls."""
@@ -467,7 +511,41 @@ def c4_section(eap, steps):
             ev += s1["cells_evaluated"]
     s_ms = (time.perf_counter() - t0) * 1e3 / steps
     same = all(a == b for a, b in zip(res, single))
-    return {"workload": "batched uneven search: 64 queries (m 64-1024, r 5-20%) vs 10,000,000 points",
+    if not variants:
+        return _c4_line(qs, cands, steps, b_ms, s_ms, same, st, ev, None)
+    # the batched call without the graph (every launch issued by the host)
+    eap.set_option("graph", 0)
+    try:
+        eap.nn_search_batch(qs, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res_ng = eap.nn_search_batch(qs, x)
+        ng_ms = (time.perf_counter() - t0) * 1e3 / steps
+    finally:
+        eap.set_option("graph", 1)
+    # with the autotuner's choices per (length, window) bucket (the tuning
+    # runs once, outside the timed calls)
+    t0 = time.perf_counter()
+    eap.set_option("autotune", 1)
+    try:
+        eap.nn_search_batch(qs, x)
+        tune_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res_at = eap.nn_search_batch(qs, x)
+        at_ms = (time.perf_counter() - t0) * 1e3 / steps
+    finally:
+        eap.set_option("autotune", 0)
+    return _c4_line(qs, cands, steps, b_ms, s_ms, same, st, ev,
+                    {"batched_no_graph_ms": round(ng_ms, 3), "no_graph_same_answers": res_ng == res,
+                     "batched_autotuned_ms": round(at_ms, 3), "autotune_seconds": round(tune_s, 2),
+                     "autotuned_same_answers": res_at == res})
+
+
+def _c4_line(qs, cands, steps, b_ms, s_ms, same, st, ev, extra):
+    line = {"workload": "batched uneven search: 64 queries (m 64-1024, r 5-20%) vs 10,000,000 points",
             "queries": len(qs), "candidates": cands, "steps": steps,
             "batched_candidates_per_s": cands / (b_ms / 1e3), "batched_ms": round(b_ms, 3),
             "single_calls_candidates_per_s": cands / (s_ms / 1e3), "single_calls_ms": round(s_ms, 3),
@@ -476,6 +554,9 @@ def c4_section(eap, steps):
             "batched_cells_nominal": st["cells_nominal"],
             "single_cells_evaluated": ev // steps,
             "batched_effective_gcups": st["cells_evaluated"] / (b_ms / 1e3) / 1e9}
+    if extra:
+        line.update(extra)
+    return line
 
 
 def main():
@@ -498,6 +579,11 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=50,
                     help="steps of the differentiation workload (4,096 pairs fwd and fwd+bwd; "
                          "0 = skip)")
+    ap.add_argument("--c1-steps", type=int, default=10,
+                    help="calls of the small search workload (0 = skip)")
+    ap.add_argument("--c4-variants", type=int, default=1,
+                    help="1 = also time the batched call without its graph and with the "
+                         "autotuner's choices (0 = skip)")
     ap.add_argument("--c3-steps", type=int, default=3,
                     help="repetitions of the all-pairs workload (0 = skip)")
     ap.add_argument("--c4-steps", type=int, default=2,
@@ -508,8 +594,8 @@ def main():
                          "that calibrates HBM byte counters in a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -605,12 +691,14 @@ def main():
         if args.batch_streams > 0:
             eap.set_option("batch_branches", args.batch_streams)
         line["batched"] = batched(eap, q, x, windows, K, args.batch_steps, rec)
+    if args.c1_steps > 0:
+        line["c1_search"] = c1_section(eap, args.c1_steps)
     if args.c5_steps > 0:
         line["c5_fwd_bwd"] = c5_section(eap, args.c5_steps, min(args.cpu_budget, 5.0))
     if args.c3_steps > 0:
         line["c3_pairwise"] = c3_section(eap, args.c3_steps)
     if args.c4_steps > 0:
-        line["c4_batched"] = c4_section(eap, args.c4_steps)
+        line["c4_batched"] = c4_section(eap, args.c4_steps, args.c4_variants != 0)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(q32, x32, windows, args.cpu_budget)
         line["cpu_eap_scan"] = cpu_eap_scan(q32, x32, windows, min(args.cpu_budget, 8.0),
