@@ -297,9 +297,10 @@ int eapdtw_tune_load(eapdtw_ctx *ctx, const char *path);
  * anti-diagonals of its band, one matrix row per lane and cell slot (1-8
  * slots); no bound, plain DTW.
  *   S, T [npairs][len] : DEVICE float32, row-major.
- *   window             : r >= 0 (clipped to len - 1).  Supported: len <= 8191
- *                        and min(window + 1, len) <= 511 (rows active at
- *                        once); otherwise EINVAL.
+ *   window             : r >= 0 (clipped to len - 1).  Supported: len <= 8159
+ *                        (a pair's two series sit in one wave's 64 KB of
+ *                        LDS) and min(window + 1, len) <= 511 (rows active
+ *                        at once); otherwise EINVAL.
  *
  * eapdtw_dtw_ckpt_bytes: size of the record the forward leaves for the
  *   backward: a status word per pair and the optimal path as one column range
@@ -356,8 +357,9 @@ int eapdtw_dtw_path(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npa
  * window r_p (clipped to max(s_len, t_len) - 1; |s_len - t_len| > r_p has no
  * warping path: +inf).  Pairs are grouped by kernel class (16, 32 or 64 lanes
  * per pair, 1-8 rows per lane) and run longest first, one launch per group.
- * Supported: lengths up to 8191 and min(r_p + 1, s_len, t_len) <= 511;
- * otherwise EINVAL.  Both series empty: 0; one empty: +inf (Eq. 2-4).
+ * Supported: lengths up to 8191 with s_len + t_len <= 16318 (a pair's two
+ * series sit in one wave's 64 KB of LDS) and min(r_p + 1, s_len, t_len) <=
+ * 511 (rows active at once); otherwise EINVAL.  Both series empty: 0; one empty: +inf (Eq. 2-4).
  *   pairs [npairs] : HOST array (copied before the call returns). */
 typedef struct {
   int64_t s_off, s_len;

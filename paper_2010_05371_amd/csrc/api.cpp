@@ -100,7 +100,7 @@ bool is_fault(hipError_t e) {
 
 // Launch log: which kernel (template parameters, class) and launch shape a
 // call took, one line on stderr each, when the context's option "log" is set.
-__attribute__((format(printf, 2, 3))) void logf(const eapdtw_ctx *c, const char *fmt, ...) {
+__attribute__((format(printf, 2, 3))) void log_launch(const eapdtw_ctx *c, const char *fmt, ...) {
   if (!c || !c->log) return;
   char buf[512];
   va_list ap;
@@ -514,9 +514,9 @@ static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
     a.out = out;
     a.counters = cnt;
     HIPCHK(pair_band_launcher((int)r)(a, ntasks, pick_rows(ctx, (int)r), st));
-    logf(ctx, "pairs %lld x (%lld, %lld) r=%lld: pair_band_kernel<%lld,%d> grid=%lld", (long long)npairs,
-         (long long)lrow, (long long)lcol, (long long)r, (long long)r, pick_rows(ctx, (int)r),
-         (long long)ntasks);
+    log_launch(ctx, "pairs %lld x (%lld, %lld) r=%lld: pair_band_kernel<%lld,%d> grid=%lld", (long long)npairs,
+               (long long)lrow, (long long)lcol, (long long)r, (long long)r, pick_rows(ctx, (int)r),
+               (long long)ntasks);
   } else {
     WideArgs w{};
     w.lrow = (int)lrow;
@@ -536,9 +536,9 @@ static int pairs_engine(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t
     w.counters = cnt;
     w.check_interval = 1;
     HIPCHK(launch_wide(kWidePairs, (int)ctx->wide_rows, w, (int)grid, st));
-    logf(ctx, "pairs %lld x (%lld, %lld) r=%lld: wide_kernel<%d,pairs> %lld blocks of 64 on %lld waves",
-         (long long)npairs, (long long)lrow, (long long)lcol, (long long)r, wide_h(ctx, r, lrow, lcol),
-         (long long)ntasks, (long long)grid);
+    log_launch(ctx, "pairs %lld x (%lld, %lld) r=%lld: wide_kernel<%d,pairs> %lld blocks of 64 on %lld waves",
+               (long long)npairs, (long long)lrow, (long long)lcol, (long long)r, wide_h(ctx, r, lrow, lcol),
+               (long long)ntasks, (long long)grid);
   }
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
@@ -672,9 +672,9 @@ int eapdtw_pairwise(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int
   w.check_interval = 1;
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
   HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
-  logf(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
-       w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
-       wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
+  log_launch(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
+             w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
+             wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -832,10 +832,10 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       HIPCHK(hipEventRecord(ctx->ev_join, ss));
       joined = false;
     }
-    logf(ctx, "search seeding: %s grid=%lld (every %lld-th block of 64), then %s window %lld, 1 workgroup%s",
-         ctx->ed ? "ed_search_kernel" : "nn_band_kernel<0,8>", (long long)((nblk + sstr - 1) / sstr),
-         (long long)sstr, wgt ? "nn_wband_kernel" : (rs == 0 && ctx->ed && !kb) ? "ed_search_kernel" : "nn_band_kernel",
-         (long long)rs, ss != st ? " on the seed stream" : "");
+    log_launch(ctx, "search seeding: %s grid=%lld (every %lld-th block of 64), then %s window %lld, 1 workgroup%s",
+               ctx->ed ? "ed_search_kernel" : "nn_band_kernel<0,8>", (long long)((nblk + sstr - 1) / sstr),
+               (long long)sstr, wgt ? "nn_wband_kernel" : (rs == 0 && ctx->ed && !kb) ? "ed_search_kernel" : "nn_band_kernel",
+               (long long)rs, ss != st ? " on the seed stream" : "");
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev2, st));
   if (lb && lb_applies(ctx, r)) {
@@ -900,9 +900,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       b.lq = lb->lq;
       HIPCHK(nn_list_launcher((int)r)(b, (hi - lo + kWave - 1) / kWave, dists != nullptr,
                                       ctx->border != 0, st));
-      logf(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "
-           "nn_list_kernel<%lld,4,border=%d> grid=%lld", (long long)m, (long long)r, (long long)lo,
-           (long long)hi, (long long)r, ctx->border != 0, (long long)((hi - lo + kWave - 1) / kWave));
+      log_launch(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "
+                 "nn_list_kernel<%lld,4,border=%d> grid=%lld", (long long)m, (long long)r, (long long)lo,
+                 (long long)hi, (long long)r, ctx->border != 0, (long long)((hi - lo + kWave - 1) / kWave));
       if (time_main && pi + 1 < nranges) HIPCHK(hipEventRecord(ctx->ev_lb[e++], st));
     }
   } else if (use_band(ctx, r)) {
@@ -913,26 +913,26 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
     const bool bord = ctx->border != 0 && r >= kBorderMinR;
     if (wgt) {
       HIPCHK(nn_wband_launcher((int)r)(a, nblk, dists != nullptr, ctx->border != 0, st));
-      logf(ctx, "search m=%lld r=%lld: nn_wband_kernel<%lld,4,border=%d> grid=%lld", (long long)m,
-           (long long)r, (long long)r, bord, (long long)nblk);
+      log_launch(ctx, "search m=%lld r=%lld: nn_wband_kernel<%lld,4,border=%d> grid=%lld", (long long)m,
+                 (long long)r, (long long)r, bord, (long long)nblk);
     } else if (kb) {
       a.knn = kb->k;
       a.knn_buf = kb->buf;
       a.knn_n = kb->n;
       HIPCHK(nn_band_launcher((int)r)(a, nblk, 4, false, ctx->border != 0, st));
-      logf(ctx, "search m=%lld r=%lld k=%d: nn_band_kernel<%lld,4,border=%d> grid=%lld", (long long)m,
-           (long long)r, kb->k, (long long)r, bord, (long long)nblk);
+      log_launch(ctx, "search m=%lld r=%lld k=%d: nn_band_kernel<%lld,4,border=%d> grid=%lld", (long long)m,
+                 (long long)r, kb->k, (long long)r, bord, (long long)nblk);
     } else if (r == 0 && ctx->ed) {
       HIPCHK(launch_ed_search(a, nblk, dists != nullptr, st));
-      logf(ctx, "search m=%lld r=0: ed_search_kernel grid=%lld", (long long)m, (long long)nblk);
+      log_launch(ctx, "search m=%lld r=0: ed_search_kernel grid=%lld", (long long)m, (long long)nblk);
     } else if (!dists && ctx->lanes && lane_search_supported((int)r, (int)m)) {
       HIPCHK(launch_lane_search((int)r, a, st));
-      logf(ctx, "search m=%lld r=%lld: lane-refill kernel", (long long)m, (long long)r);
+      log_launch(ctx, "search m=%lld r=%lld: lane-refill kernel", (long long)m, (long long)r);
     } else {
       const int u = dists ? 4 : pick_rows(ctx, (int)r);
       HIPCHK(nn_band_launcher((int)r)(a, nblk, u, dists != nullptr, ctx->border != 0, st));
-      logf(ctx, "search m=%lld r=%lld: nn_band_kernel<%lld,%d,border=%d> grid=%lld", (long long)m,
-           (long long)r, (long long)r, u, bord, (long long)nblk);
+      log_launch(ctx, "search m=%lld r=%lld: nn_band_kernel<%lld,%d,border=%d> grid=%lld", (long long)m,
+                 (long long)r, (long long)r, u, bord, (long long)nblk);
     }
   } else {
     WideArgs w{};
@@ -959,9 +959,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       w.knn_n = kb->n;
     }
     HIPCHK(launch_wide(kWideSearch, (int)ctx->wide_rows, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
-    logf(ctx, "search m=%lld r=%lld: wide_kernel<%d,search> %lld blocks of 64 on %lld persistent waves",
-         (long long)m, (long long)r, wide_h(ctx, r, m, m), (long long)nblk,
-         (long long)(bnd_waves < nblk ? bnd_waves : nblk));
+    log_launch(ctx, "search m=%lld r=%lld: wide_kernel<%d,search> %lld blocks of 64 on %lld persistent waves",
+               (long long)m, (long long)r, wide_h(ctx, r, m, m), (long long)nblk,
+               (long long)(bnd_waves < nblk ? bnd_waves : nblk));
   }
   if (time_main) HIPCHK(hipEventRecord(ctx->ev3, st));
   if (!joined) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
@@ -1351,9 +1351,9 @@ int eapdtw_nn1(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t 
   HIPCHK(launch_nn1_seed(w, (int)grid, st));
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
   HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
-  logf(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
-       w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
-       wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
+  log_launch(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
+             w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
+             wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -1425,9 +1425,9 @@ int eapdtw_nn1_ref(eapdtw_ctx *ctx, const float *Q, int64_t nq, const float *R, 
   HIPCHK(launch_nn1_seed(w, (int)grid, st));
   if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
   HIPCHK(launch_wide(kWidePairwise, (int)ctx->wide_rows, w, (int)grid, st));
-  logf(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
-       w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
-       wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
+  log_launch(ctx, "%s rows %lld x %lld columns of length %d, r=%d: wide_kernel<%d,pairwise> %lld tasks on %lld waves",
+             w.nn1 ? "nn1" : "pairwise", (long long)(w.nq ? w.nq : w.N), (long long)w.N, w.lrow, w.r,
+             wide_h(ctx, w.r, w.lrow, w.lcol), (long long)w.ntasks, (long long)grid);
   if (stats) {
     HIPCHK(hipEventRecord(ctx->ev3, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -1720,10 +1720,10 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   }
   const bool use_graph = ctx->graph != 0;
   const bool rebuild = !use_graph || !ctx->batch_exec || ctx->batch_key != key;
-  logf(ctx, "batch %lld queries: %lld band launches on up to %lld streams, %lld units of 64 offsets in "
-       "the persistent batch_main_kernel (%d waves), %lld seeding blocks; %s",
-       (long long)nq, (long long)(nq - nband_first), (long long)ctx->batch_branches, (long long)units,
-       grid, (long long)seeds, use_graph ? (rebuild ? "graph captured" : "graph replayed") : "no graph");
+  log_launch(ctx, "batch %lld queries: %lld band launches on up to %lld streams, %lld units of 64 offsets in "
+             "the persistent batch_main_kernel (%d waves), %lld seeding blocks; %s",
+             (long long)nq, (long long)(nq - nband_first), (long long)ctx->batch_branches, (long long)units,
+             grid, (long long)seeds, use_graph ? (rebuild ? "graph captured" : "graph replayed") : "no graph");
   if (rebuild) {
     // descriptors are constant for a given key: upload them outside the graph
     int rc = ensure_pinned(ctx, sizeof(BatchQuery) * nq);
@@ -1948,7 +1948,8 @@ static int wf_validate(eapdtw_ctx *ctx, const float *S, int64_t s_total, const f
     const int64_t r = clip_window(q.window, q.s_len, q.t_len);
     if (q.s_len > 0 && q.t_len > 0 && wf_class_for((int)q.s_len, (int)q.t_len, (int)r) < 0)
       return fail(ctx, EAPDTW_EINVAL,
-                  "pair " + std::to_string(p) + ": more than 511 rows active at once");
+                  "pair " + std::to_string(p) +
+                      ": more than 511 rows active at once, or s_len + t_len above 16318");
     hp[(size_t)p] = WfHostPair{q.s_off, q.t_off, q.s_len, q.t_len, r};
   }
   if (disjoint) {
@@ -2125,7 +2126,7 @@ static int wf_launch_batch(eapdtw_ctx *ctx, const float *S, const float *T, cons
     a.ub = ub;
     a.counters = cnt;
     HIPCHK(launch_wf_fwd(c, mode, a, ctx->stream));
-    logf(ctx, "pair batch: wf_fwd_kernel<%d,%d,%d> %lld pairs", kWfG[c], kWfNC[c], mode, (long long)n);
+    log_launch(ctx, "pair batch: wf_fwd_kernel<%d,%d,%d> %lld pairs", kWfG[c], kWfNC[c], mode, (long long)n);
   }
   return EAPDTW_OK;
 }
@@ -2150,7 +2151,7 @@ static int wf_walk_batch(eapdtw_ctx *ctx, const WfBatchPlan &pl, const WfPair *d
     w.max_chunks = pl.max_chunks[gi];
     w.max_ranges = pl.max_ranges[gi];
     HIPCHK(launch_wf_walk(kWfG[c] * kWfNC[c], w, ctx->stream));
-    logf(ctx, "pair batch: wf_walk_kernel<%d> %lld pairs", kWfG[c] * kWfNC[c], (long long)n);
+    log_launch(ctx, "pair batch: wf_walk_kernel<%d> %lld pairs", kWfG[c] * kWfNC[c], (long long)n);
   }
   return EAPDTW_OK;
 }
@@ -2317,7 +2318,7 @@ static int wf_batch_backward(eapdtw_ctx *ctx, const float *S, const float *T,
   g.gS = grad_S;
   g.gT = grad_T;
   HIPCHK(launch_wf_grad(g, ctx->stream));
-  logf(ctx, "wf_grad_kernel %lld pairs", (long long)g.npairs);
+  log_launch(ctx, "wf_grad_kernel %lld pairs", (long long)g.npairs);
   return EAPDTW_OK;
 }
 
@@ -2399,8 +2400,8 @@ static int diff_validate(eapdtw_ctx *ctx, const float *S, const float *T, int64_
   WfUniformRec u;
   if (!wf_uniform_rec(npairs, len, window, 0, u))
     return fail(ctx, EAPDTW_EINVAL,
-                "the differentiable batch supports lengths up to 8191 with at most 511 rows "
-                "active at once (min(window + 1, len) <= 511)");
+                "the differentiable batch supports lengths up to 8159 (both series in a "
+                "wave's LDS) with at most 511 rows active at once (min(window + 1, len) <= 511)");
   return EAPDTW_OK;
 }
 
@@ -2425,8 +2426,8 @@ static int wf_uniform_rec_fwd(eapdtw_ctx *ctx, const float *S, const float *T, i
   a.lds_stride = (int)(u.mode == 2 ? wf_fused_words((int)len, (int)len, u.cls)
                                    : 2 * len + 2 * kWfPad);
   HIPCHK(launch_wf_fwd(u.cls, u.mode, a, ctx->stream));
-  logf(ctx, "pairs %lld x %lld r=%d: wf_fwd_kernel<%d,%d,%d>", (long long)a.nitems, (long long)len, a.r,
-       kWfG[u.cls], kWfNC[u.cls], u.mode);
+  log_launch(ctx, "pairs %lld x %lld r=%d: wf_fwd_kernel<%d,%d,%d>", (long long)a.nitems, (long long)len, a.r,
+             kWfG[u.cls], kWfNC[u.cls], u.mode);
   return EAPDTW_OK;
 }
 
@@ -2477,8 +2478,8 @@ int eapdtw_dtw_fwd(eapdtw_ctx *ctx, const float *S, const float *T, int64_t npai
   a.out = out_dist;
   a.lds_stride = (int)(2 * len + 2 * kWfPad);
   HIPCHK(launch_wf_fwd(c, 0, a, ctx->stream));
-  logf(ctx, "pairs %lld x %lld r=%lld: wf_fwd_kernel<%d,%d,0>", (long long)npairs, (long long)len,
-       (long long)r, kWfG[c], kWfNC[c]);
+  log_launch(ctx, "pairs %lld x %lld r=%lld: wf_fwd_kernel<%d,%d,0>", (long long)npairs, (long long)len,
+             (long long)r, kWfG[c], kWfNC[c]);
   return EAPDTW_OK;
 }
 
@@ -2519,7 +2520,7 @@ static int wf_uniform_backward(eapdtw_ctx *ctx, const float *S, const float *T, 
     w.max_chunks = wf_chunks((int)len, (int)len);
     w.max_ranges = (int)(2 * len);
     HIPCHK(launch_wf_walk(kWfG[u.cls] * kWfNC[u.cls], w, ctx->stream));
-    logf(ctx, "wf_walk_kernel<%d> %lld pairs", kWfG[u.cls] * kWfNC[u.cls], (long long)w.nitems);
+    log_launch(ctx, "wf_walk_kernel<%d> %lld pairs", kWfG[u.cls] * kWfNC[u.cls], (long long)w.nitems);
   }
   if (!grad_S) return EAPDTW_OK;
   WfGradArgs g{};
@@ -2534,7 +2535,7 @@ static int wf_uniform_backward(eapdtw_ctx *ctx, const float *S, const float *T, 
   g.gS = grad_S;
   g.gT = grad_T;
   HIPCHK(launch_wf_grad(g, ctx->stream));
-  logf(ctx, "wf_grad_kernel %lld pairs", (long long)g.npairs);
+  log_launch(ctx, "wf_grad_kernel %lld pairs", (long long)g.npairs);
   return EAPDTW_OK;
 }
 
@@ -2576,7 +2577,8 @@ int eapdtw_dba_step(eapdtw_ctx *ctx, const float *B, int64_t lb, const float *X,
   if (std::llabs(lb - len) > r)
     return fail(ctx, EAPDTW_EINVAL, "no warping path: |lb - len| exceeds the window");
   if (lb > kWfMaxLen || len > kWfMaxLen || wf_class_for((int)lb, (int)len, (int)r) < 0)
-    return fail(ctx, EAPDTW_EINVAL, "more than 511 rows active at once, or series too long");
+    return fail(ctx, EAPDTW_EINVAL,
+                "more than 511 rows active at once, or series too long for a wave's LDS");
   HIPCHK(hipSetDevice(ctx->device));
   // the pairs (B, X[p]) as a batch over a broadcast copy of B
   std::vector<WfHostPair> hp((size_t)n);

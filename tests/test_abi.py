@@ -76,6 +76,24 @@ def test_ckpt_bytes_is_host_arithmetic():
     assert lib.eapdtw_dtw_ckpt_bytes(-1, 10, 2) < 0
 
 
+def test_record_sizes_follow_the_size_limits():
+    """The wavefront batches' limits, decided on the host: at most 511 rows
+    active at once (512 lane-slots), and a pair's two series in one wave's
+    64 KB of LDS (s_len + t_len + 66 <= 16384 floats)."""
+    lib = _lib.load()
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 8159, 3) > 0
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 8160, 3) == -1
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 600, 510) > 0
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 600, 511) == -1
+
+    def rec(ls, lt, r):
+        p = (_lib.Pair * 1)()
+        p[0].s_off, p[0].s_len, p[0].t_off, p[0].t_len, p[0].window = 0, ls, 0, lt, r
+        return lib.eapdtw_dtw_batch_record_bytes(p, 1)
+    assert rec(8191, 8127, 510) > 0 and rec(8191, 500, 8190) > 0
+    assert rec(8191, 8128, 100) < 0 and rec(8191, 8127, 511) < 0 and rec(8192, 10, 9000) < 0
+
+
 def test_xcd_block_mapping_is_a_bijection():
     """The dispatch-index to logical-block map of the search kernels (runs of
     64 consecutive logical blocks dealt to the eight XCDs in turn) permutes

@@ -170,6 +170,9 @@ def test_ckpt_bytes():
     assert b == 256 + 2 * 8448 + 7 * 38 * 512 * 4, b
     assert lib.eapdtw_dtw_ckpt_bytes(10, 600, 599) == -1   # 600 rows active at once
     assert lib.eapdtw_dtw_ckpt_bytes(10, 9000, 3) == -1    # longer than 8191
+    # both series of a pair in one wave's 64 KB of LDS: 2 len + 66 <= 16384
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 8159, 3) > 0
+    assert lib.eapdtw_dtw_ckpt_bytes(10, 8160, 3) == -1
 
 
 def test_kernel_class_follows_the_lanes_option():

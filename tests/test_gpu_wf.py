@@ -232,3 +232,53 @@ def test_dba_step_on_the_gpu_paths(n, lb, L, w):
         same = np.array_equal(oc, c)
         if same:
             assert np.allclose(out, ob, rtol=2e-6, atol=1e-6)
+
+
+def test_uneven_batch_at_the_size_limits():
+    """The largest pairs a wavefront class holds: series of up to 8,191 points
+    whose two lengths sum to at most 16,318 (both sit in one wave's 64 KB of
+    LDS), and 512 lane-slots (at most 511 rows active at a step).  Distances and the
+    differentiable batch's paths and gradients, against the oracle.  A float32
+    DP over a path of up to lS + lT cells rounds at up to ~1e-5 relative per
+    2,000 cells, so the distances use that tolerance scaled by the path
+    length, and so does the float64 cost of the GPU's own path against the
+    optimum."""
+    g = np.random.default_rng(77)
+
+    def walk(n):
+        return gen.as_f32(_std(np.cumsum(g.standard_normal(n))))
+
+    S = [walk(8191), walk(8191), walk(511), walk(8159), walk(300)]
+    T = [walk(8127), walk(500), walk(8191), walk(8159), walk(299)]
+    W = [510, 8190, 8190, 20, 299]
+    for ls, lt, r in ((8191, 8128, 100), (8159, 8160, 20), (8191, 8127, 511)):
+        with pytest.raises(eap.EapdtwError):    # past the LDS or the lane-slots
+            eap.dtw_pairs_batch([walk(ls)], [walk(lt)], [r])
+    want = _oracle(S, T, W)
+    d = eap.dtw_pairs_batch(S, T, W).cpu().numpy()
+    for k in range(len(S)):
+        rel = 1e-5 * max(1.0, (S[k].size + T[k].size) / 2000.0)
+        assert close(float(d[k]), want[k], rel=rel), (k, d[k], want[k])
+    S_pool, T_pool, pairs = eap.pack_pairs(S, T, W)
+    Sp = S_pool.clone().requires_grad_(True)
+    Tp = T_pool.clone().requires_grad_(True)
+    dd = eap.DTWBatchFunction.apply(Sp, Tp, pairs, len(S))
+    dd.backward(torch.ones_like(dd))
+    assert np.array_equal(dd.detach().cpu().numpy(), d), "recorded and distance-only sweeps differ"
+    gS, gT = Sp.grad.cpu().numpy(), Tp.grad.cpu().numpy()
+    rr, cr = eap.dtw_batch_path(S_pool, T_pool, pairs, len(S))
+    lo, hi = unpack(rr.cpu().numpy())
+    for k in range(len(S)):
+        p = pairs[k]
+        ls, lt = p.s_len, p.t_len
+        sl = slice(p.s_off, p.s_off + ls)
+        tl = slice(p.t_off, p.t_off + lt)
+        r = min(W[k], max(ls, lt) - 1)
+        assert ranges_are_path(lo[sl], hi[sl], ls, lt, r), k
+        clo, chi = column_ranges(lo[sl], hi[sl], lt)
+        cost, dS, dT = range_path_cost_grad(S[k], T[k], lo[sl], hi[sl], clo, chi, 1.0)
+        rel = 1e-5 * max(1.0, (ls + lt) / 2000.0)
+        assert close(cost, want[k], rel=rel), (k, cost, want[k])
+        tol = 1e-5 * max(1.0, float(np.max(np.abs(dS)) + np.max(np.abs(dT))))
+        assert np.all(np.abs(gS[sl] - dS) <= tol + 1e-5 * np.abs(dS)), k
+        assert np.all(np.abs(gT[tl] - dT) <= tol + 1e-5 * np.abs(dT)), k

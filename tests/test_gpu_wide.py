@@ -177,3 +177,18 @@ def test_whole_window_tile_heights(rows):
             for a, b in zip(base[:4], cur[:4]):
                 assert np.array_equal(a, b)
             assert base[4:] == cur[4:]
+
+
+@pytest.mark.parametrize("m,w,n", [(2048, 300, 3000), (1500, 1499, 1500), (1024, 65, 1090)])
+def test_wide_search_long_queries(m, w, n):
+    """Long queries through the tiled kernel: many tiles per candidate, a
+    single candidate (n = m), and a ragged last block of candidates."""
+    g = gen.rng(903, m + w)
+    x32 = gen.as_f32(gen.random_walk(n, g))
+    q32 = gen.as_f32(gen.random_walk(m, g))
+    k, d = eap.nn_search(torch.from_numpy(q32), torch.from_numpy(x32), w)
+    q, x = gen.as_oracle(q32), gen.as_oracle(x32)
+    ko, do = oracle.nn_search(q, x, w)
+    # a DP over ~2m cells in float32: the tolerance scales with the path length
+    rel = 1e-5 * max(1.0, 2 * m / 2000.0)
+    check_nn(k, d, ko, do, oracle.nn_dists(q, x, w, [k])[0], rel=rel)
