@@ -246,6 +246,24 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
                            eapdtw_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * The batched search with a top-k bound per query: the k nearest neighbours
+ * (Section 2.2's NN search with the k-th best distance as the bound, as in
+ * eapdtw_knn_search) of every query of the batch, in the same launches as
+ * eapdtw_nn_search_batch (band launches, persistent tiled launch, hipGraph
+ * replay) with a bound word, k slot words and a buffer of kept candidates per
+ * query, then per query the filter and the k-best selection.
+ *   k           : 1..64, the same for every query.
+ *   out_offsets : HOST [nq][k], query q's k offsets ascending by (distance,
+ *                 offset), in the order of qs; -1 past the n-m+1 offsets.
+ *   out_dists   : HOST [nq][k], their distances; +inf past the offsets.
+ * The kept-candidate buffers take 16 bytes per candidate offset of every
+ * query (device memory of the context's batch buffer).  Errors as
+ * eapdtw_nn_search_batch; k outside 1..64: EINVAL.  Synchronous. */
+int eapdtw_knn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
+                            const float *series, int64_t n, int64_t k, int64_t *out_offsets,
+                            double *out_dists, eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
  * Autotuning of the search kernels (a tuning aid; the paper has no
  * counterpart).  Choices are kept per bucket of (query length, window):
  * length bucket = bit length of m; window bucket = 0 for r = 0, bit length of

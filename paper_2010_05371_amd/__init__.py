@@ -38,6 +38,7 @@ from ._lib import EapdtwError, LbStats, Pair, Query, Result, Stats, Tune
 
 __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_dists",
            "window_stats", "znorm", "window_from_ratio", "DTWFunction", "Context",
+           "knn_search_batch",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
            "nn_lower_bounds", "LbStats", "knn_search", "nn1", "nn_search_w", "nn_dists_w",
@@ -221,6 +222,28 @@ def nn_search_batch(queries, series, stats: bool = False):
     ctx.check(ctx._lib.eapdtw_nn_search_batch(ctx.handle, arr, len(qs), _ptr(x), x.numel(), res,
                                               ctypes.byref(st) if stats else None))
     out = [(r.offset, r.dist) for r in res]
+    return (out, st.as_dict()) if stats else out
+
+
+def knn_search_batch(queries, series, k: int, stats: bool = False):
+    """queries: list of (query, window).  Returns, per query, its k nearest
+    offsets as a list of (offset, distance) in (distance, offset) order."""
+    x = _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    qs = [(_dev(q, x.device.index), int(w)) for q, w in queries]
+    arr = (Query * max(len(qs), 1))()
+    for i, (q, w) in enumerate(qs):
+        arr[i].query = q.data_ptr()
+        arr[i].m = q.numel()
+        arr[i].window = w
+    kk = int(k)
+    offs = (ctypes.c_int64 * max(len(qs) * kk, 1))()
+    dists = (ctypes.c_double * max(len(qs) * kk, 1))()
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_knn_search_batch(ctx.handle, arr, len(qs), _ptr(x), x.numel(), kk,
+                                               offs, dists, ctypes.byref(st) if stats else None))
+    out = [[(offs[q * kk + j], dists[q * kk + j]) for j in range(kk)] for q in range(len(qs))]
     return (out, st.as_dict()) if stats else out
 
 

@@ -98,6 +98,8 @@ def load():
                                       ctypes.POINTER(f64)], i32),
         "eapdtw_nn_search_batch": ([vp, ctypes.POINTER(Query), i64, vp, i64,
                                     ctypes.POINTER(Result), sp], i32),
+        "eapdtw_knn_search_batch": ([vp, ctypes.POINTER(Query), i64, vp, i64, i64,
+                                     ctypes.POINTER(i64), ctypes.POINTER(f64), sp], i32),
         "eapdtw_dtw_ckpt_bytes": ([i64, i64, i64], i64),
         "eapdtw_dtw_fwd": ([vp, vp, vp, i64, i64, i64, vp, vp], i32),
         "eapdtw_dtw_bwd": ([vp, vp, vp, i64, i64, i64, vp, vp, vp, vp], i32),

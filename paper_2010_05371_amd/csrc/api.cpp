@@ -1571,24 +1571,43 @@ static int batch_queue(eapdtw_ctx *ctx, const BatchArgs &ba, int grid,
     const eapdtw_tune &t = knob[i];
     a.check_interval = (int)t.check_interval;
     const int rows = t.rows_per_group ? (int)t.rows_per_group : pick_rows(ctx, d.r);
-    if (d.r == 0 && ctx->ed)
+    if (ba.knn > 0) {
+      a.knn = ba.knn;
+      a.knn_buf = d.knn_buf;
+      a.knn_n = d.knn_n;
+      a.knn_slots = d.knn_slots;
+      // (the window-0 kernel publishes only the best)
+      HIPCHK(nn_band_launcher(d.r)(a, nblk, 4, false, t.border != 0, bs));
+    } else if (d.r == 0 && ctx->ed) {
       HIPCHK(launch_ed_search(a, nblk, false, bs));
-    else
+    } else {
       HIPCHK(nn_band_launcher(d.r)(a, nblk, rows, false, t.border != 0, bs));
+    }
   }
   if (ba.total_units > 0) HIPCHK(launch_batch_main(ba, grid, st));
   for (int b = 0; b < nside; ++b) {
     HIPCHK(hipEventRecord(ctx->ev_bjoin[b], ctx->branch[b]));
     HIPCHK(hipStreamWaitEvent(st, ctx->ev_bjoin[b], 0));
   }
+  // k nearest neighbours: per query, the kept candidates at or below its
+  // final bound, then the k best of them (knn_res, k words per query)
+  for (size_t i = 0; ba.knn > 0 && i < desc.size(); ++i) {
+    const BatchQuery &d = desc[i];
+    HIPCHK(launch_knn_select(d.knn_buf, d.knn_n, d.bsf, d.knn_buf + d.K, d.knn_nsel, ba.knn,
+                             d.knn_res, st));
+  }
   return EAPDTW_OK;
 }
 
-int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
-                           const float *series, int64_t n, eapdtw_result *out,
-                           eapdtw_stats *stats) {
+// The batched search: nearest neighbour of every query (k == 0, results in
+// out) or its k nearest neighbours (k >= 1, offsets and distances [nq][k]).
+static int batch_impl(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq, const float *series,
+                      int64_t n, int64_t k, eapdtw_result *out, int64_t *out_offsets,
+                      double *out_dists, eapdtw_stats *stats) {
   CHECK_CTX();
-  if (nq < 0 || (nq > 0 && (!qs || !out))) return fail(ctx, EAPDTW_EINVAL, "bad query array");
+  if (nq < 0 || (nq > 0 && (!qs || (k == 0 ? !out : (!out_offsets || !out_dists)))))
+    return fail(ctx, EAPDTW_EINVAL, "bad query array");
+  if (k < 0 || k > kKnnMax) return fail(ctx, EAPDTW_EINVAL, "k must be in 1..64");
   if (nq > 65536) return fail(ctx, EAPDTW_EINVAL, "too many queries");
   if (stats) std::memset(stats, 0, sizeof *stats);
   if (nq == 0) return EAPDTW_OK;
@@ -1633,8 +1652,18 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   const size_t o_work = pl.add(sizeof(unsigned long long));
   const size_t o_desc = pl.add(sizeof(BatchQuery) * nq);
   const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2 * nq);
-  std::vector<size_t> o_q(nq);
+  // k nearest neighbours: the k result words of every query (read back with
+  // the counters and best-so-far words)
+  const size_t o_kres = k > 0 ? pl.add(sizeof(unsigned long long) * kKnnMax * nq) : 0;
+  std::vector<size_t> o_q(nq), o_knn(nq);
   for (int64_t i = 0; i < nq; ++i) o_q[i] = pl.add(sizeof(float) * (qs[order[i]].m + 2 * kColPad));
+  // k nearest neighbours, per query: the slot words (k, kCntStride apart),
+  // the two counts, and the kept candidates with their filtered copy (K words
+  // each)
+  constexpr size_t kKnnHead = (size_t)kKnnMax * kCntStride + 2;
+  if (k > 0)
+    for (int64_t i = 0; i < nq; ++i)
+      o_knn[i] = pl.add(sizeof(unsigned long long) * (kKnnHead + 2 * (size_t)(n - qs[order[i]].m + 1)));
   const size_t o_bnd = pl.add(sizeof(float) * (size_t)grid * (max_m + 1) * kWave);
   if (pl.off > ctx->batch_cap) {
     HIPCHK(hipStreamSynchronize(st));
@@ -1669,6 +1698,14 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
     const int64_t nblk = (d.K + kWave - 1) / kWave;
     const int64_t sstr = seed_stride_for(ctx->batch_seed_stride, nblk);
     d.seed_stride = (int)sstr;
+    if (k > 0) {
+      unsigned long long *kw = reinterpret_cast<unsigned long long *>(bb + o_knn[i]);
+      d.knn_slots = kw;
+      d.knn_n = kw + (size_t)kKnnMax * kCntStride;
+      d.knn_nsel = d.knn_n + 1;
+      d.knn_buf = d.knn_n + 2;
+      d.knn_res = reinterpret_cast<unsigned long long *>(bb + o_kres) + (size_t)kKnnMax * i;
+    }
     if (use_band(ctx, d.r)) {
       if (nband_first == nq) nband_first = i;
     } else {
@@ -1701,6 +1738,7 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   ba.bnd_stride = (max_m + 1) * kWave;
   ba.counters = reinterpret_cast<unsigned long long *>(bb + o_cnt);
   ba.check_interval = (int)ctx->check_interval;
+  ba.knn = (int)k;
   // graph key: everything the captured launches depend on
   uint64_t key = 1469598103934665603ull;
   key = fnv1a(key, &bb, sizeof bb);
@@ -1766,7 +1804,8 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   }
   if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
   // counters, work counter, descriptors and best-so-far words read back at once
-  const size_t nbytes = o_bsf + sizeof(unsigned long long) * 2 * nq;
+  const size_t nbytes = k > 0 ? o_kres + sizeof(unsigned long long) * kKnnMax * nq
+                              : o_bsf + sizeof(unsigned long long) * 2 * nq;
   int rc = ensure_pinned(ctx, nbytes);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(ctx->pinned, bb, nbytes, hipMemcpyDeviceToHost, st));
@@ -1774,17 +1813,43 @@ int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
   const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned + o_cnt);
   if (counter_sum(hc, kCntNonFinite)) return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in a query or the series");
   const unsigned long long *hb = reinterpret_cast<unsigned long long *>(ctx->pinned + o_bsf);
-  for (int64_t i = 0; i < nq; ++i) {
+  for (int64_t i = 0; k == 0 && i < nq; ++i) {
     const unsigned long long b = hb[2 * i];
     eapdtw_result &r = out[order[i]];
     r.offset = best_offset(b) == 0xffffffffu ? -1 : (int64_t)best_offset(b);
     r.dist = (double)best_dist(b);
+  }
+  if (k > 0) {
+    const unsigned long long *hr = reinterpret_cast<unsigned long long *>(ctx->pinned + o_kres);
+    for (int64_t i = 0; i < nq; ++i) {
+      const int64_t q = order[i];
+      const int64_t Kq = n - qs[q].m + 1;
+      for (int64_t j = 0; j < k; ++j) {
+        const unsigned long long w = hr[(size_t)kKnnMax * i + j];
+        const bool have = j < Kq && w != ~0ull;
+        out_offsets[q * k + j] = have ? (int64_t)best_offset(w) : -1;
+        out_dists[q * k + j] = have ? (double)best_dist(w) : INFINITY;
+      }
+    }
   }
   if (stats) {
     const float ms = elapsed(ctx->ev0, ctx->ev1);
     fill_stats(stats, hc, nominal, problems, ms, ms);
   }
   return EAPDTW_OK;
+}
+
+int eapdtw_nn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
+                           const float *series, int64_t n, eapdtw_result *out,
+                           eapdtw_stats *stats) {
+  return batch_impl(ctx, qs, nq, series, n, 0, out, nullptr, nullptr, stats);
+}
+
+int eapdtw_knn_search_batch(eapdtw_ctx *ctx, const eapdtw_query *qs, int64_t nq,
+                            const float *series, int64_t n, int64_t k, int64_t *out_offsets,
+                            double *out_dists, eapdtw_stats *stats) {
+  if (ctx && (k < 1 || k > kKnnMax)) return fail(ctx, EAPDTW_EINVAL, "k must be in 1..64");
+  return batch_impl(ctx, qs, nq, series, n, k, nullptr, out_offsets, out_dists, stats);
 }
 
 int eapdtw_autotune(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,

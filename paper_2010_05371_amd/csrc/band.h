@@ -617,8 +617,8 @@ __device__ __forceinline__ void publish_knn(const KnnOut &a, bool keep, float d,
     const unsigned long long kth = __shfl(s, a.k - 1, kWave);
     if (lane == 0) atomicMin(a.bound, pack_best(best_dist(kth), 0xffffffffu));
   }
-  if (a.counters) {
-    unsigned long long *slots = a.counters + kCntKnnSlot;
+  unsigned long long *slots = a.slots ? a.slots : (a.counters ? a.counters + kCntKnnSlot : nullptr);
+  if (slots) {
     if (keep)
       atomicMax(&slots[(id % (uint32_t)a.k) * kCntStride],
                 (unsigned long long)(0xffffffffu - __builtin_bit_cast(uint32_t, d)));
@@ -901,7 +901,8 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   if (DISTS) {
     if (active) a.dists[k - a.k_begin] = keep ? d : kInf;
   } else if (!LIST && a.knn > 0) {
-    publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters}, keep, d, (uint32_t)k);
+    publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters, a.knn_slots}, keep, d,
+                (uint32_t)k);
   } else {
     publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }

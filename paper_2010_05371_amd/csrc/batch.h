@@ -15,6 +15,11 @@ struct BatchQuery {
   int64_t unit_begin;          // first work unit (64 offsets each) of the main pass
   int64_t seed_begin;          // first workgroup of the window-0 seeding pass
   int seed_stride;             // that pass visits every seed_stride-th block of the query
+  // k nearest neighbours (BatchArgs::knn > 0): bsf[0] bounds the k-th best;
+  // kept candidates go to knn_buf (knn_n counting them), the k slot words
+  // are knn_slots (kCntStride apart), knn_nsel counts the selection's filter
+  unsigned long long *knn_buf, *knn_n, *knn_slots, *knn_nsel;
+  unsigned long long *knn_res;  // the k best, packed (distance, offset), ascending
 };
 
 struct BatchArgs {
@@ -31,6 +36,7 @@ struct BatchArgs {
   int64_t bnd_stride;
   unsigned long long *counters;
   int check_interval;
+  int knn;                     // 0: nearest neighbour; 1..kKnnMax: k nearest neighbours
 };
 
 hipError_t launch_batch_prep(const BatchArgs &a, hipStream_t st);

@@ -45,6 +45,14 @@ __global__ void batch_prep_kernel(BatchArgs a) {
   __shared__ double sh[16];
   const BatchQuery &q = a.qs[blockIdx.x];
   const int bad = znorm_block(q.query, q.m, q.qpad, kColPad, sh);
+  if (a.knn > 0) {
+    // the kept-candidate and filter counts and the k slot words start at 0
+    for (int s = threadIdx.x; s < a.knn; s += blockDim.x) q.knn_slots[s * kCntStride] = 0ull;
+    if (threadIdx.x == 0) {
+      *q.knn_n = 0ull;
+      *q.knn_nsel = 0ull;
+    }
+  }
   if (threadIdx.x == 0) {
     q.bsf[0] = pack_best(kInf, 0xffffffffu);
     q.bsf[1] = pack_best(kInf, 0xffffffffu);
@@ -79,6 +87,14 @@ __global__ __launch_bounds__(64) void batch_seed_kernel(BatchArgs a) {
   n.center = bq.bsf + 1;
   n.bsf_init = bq.bsf + 1;
   n.bound_only = 1;
+  if (a.knn > 0) {
+    // k nearest neighbours: the window-0 pass only locates this workgroup (its
+    // minimum bounds the best, not the k-th best); the workgroup publishes the
+    // k-th best of its 64 distances and appends nothing (they are distances
+    // under a narrower window)
+    n.bsf_init = nullptr;
+    n.knn = a.knn;
+  }
   const int rs = bq.r < a.seed_window ? bq.r : a.seed_window;
   switch (rs) {
     case 1: batch_seed_rs<1>(n); break;
@@ -118,6 +134,12 @@ __global__ __launch_bounds__(64) void batch_main_kernel(BatchArgs a) {
       w.k_begin = 0;
       w.k_end = bq.K;
       w.check_interval = a.check_interval;
+      if (a.knn > 0) {
+        w.knn = a.knn;
+        w.knn_buf = bq.knn_buf;
+        w.knn_n = bq.knn_n;
+        w.knn_slots = bq.knn_slots;
+      }
       const int64_t task = unit - bq.unit_begin;
       if (2 * w.r + 2 >= kWideBandRowsTall)
         wide_search_task<kWideBandRowsTall, true>(w, task, Bw, lane, evaluated, computed, abandoned);

@@ -115,6 +115,8 @@ struct NNArgs {
   int knn;
   unsigned long long *knn_buf;
   unsigned long long *knn_n;
+  // the k slot words (kCntStride apart; nullptr: those of the counter array)
+  unsigned long long *knn_slots;
   // weighted DTW kernels: the weight of phase difference |i - j| = 0..kBandRMax
   float wgt[kBandRMax + 1];
 };
@@ -129,6 +131,7 @@ struct KnnOut {
   unsigned long long *buf;        // kept candidates (nullable)
   unsigned long long *n;          // their count
   unsigned long long *counters;   // counter array holding the k slot words (nullable)
+  unsigned long long *slots;      // the k slot words instead (nullable)
 };
 
 // Relative margin by which float32 lower bounds are lowered before they are

@@ -57,6 +57,7 @@ struct WideArgs {
   unsigned long long *nn1;           // pairwise: per-series nearest neighbour words (NN1 mode)
   int knn;                           // search: k nearest neighbours (bsf bounds the k-th best)
   unsigned long long *knn_buf, *knn_n;
+  unsigned long long *knn_slots;     // the k slot words (nullptr: those of the counter array)
   int64_t nq;                        // pairwise: > 0 = rows are the nq series of X, columns the
                                      // N series of XT, every (row, column) pair (NN1 of a test
                                      // set against a reference set); 0 = i < j within one set
@@ -499,7 +500,8 @@ __device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task
   if (a.dists_mode) {
     if (p.active) a.dists[k - a.k_begin] = d;
   } else if (a.knn > 0) {
-    publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters}, keep, d, (uint32_t)k);
+    publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters, a.knn_slots}, keep, d,
+                (uint32_t)k);
   } else {
     publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }

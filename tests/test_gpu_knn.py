@@ -109,3 +109,57 @@ def test_knn_many_ties_multi_tile_selection():
         assert len(set(ds)) == 1
         qo, xo = gen.as_oracle(q32), gen.as_oracle(x32)
         assert close(ds[0], oracle.nn_dists(qo, xo, w, [3])[0])
+
+
+def _batch_queries(seed, n_queries, mlo, mhi, rlo, rhi):
+    g = gen.rng(seed)
+    out = []
+    for _ in range(n_queries):
+        m = int(g.integers(mlo, mhi + 1))
+        w = int(np.ceil(float(g.uniform(rlo, rhi)) * m))
+        out.append((gen.as_f32(gen.random_walk(m, g)), w))
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 7, 64])
+def test_knn_batch_equals_single_queries(k):
+    """The batched search with a top-k bound per query: every query's k best
+    (offset, distance) pairs are the single-query k-NN search's, bit for bit
+    (band windows on concurrent streams, windows past 64 in the persistent
+    tiled launch, window 0, a query with fewer offsets than k), and
+    k = 1 is the batched nearest-neighbour search."""
+    x32 = gen.as_f32(gen.random_walk(60_000, gen.rng(4500)))
+    qs = _batch_queries(4501, 10, 40, 400, 0.0, 0.4)
+    qs.append((gen.as_f32(gen.random_walk(90, gen.rng(4502))), 0))
+    qs.append((gen.as_f32(gen.random_walk(300, gen.rng(4503))), 299))
+    qs.append((x32[-60:].copy(), 5))
+    xs = gen.as_f32(gen.random_walk(1000, gen.rng(4504)))
+    x = torch.from_numpy(x32).cuda()
+    tq = [(torch.from_numpy(q).cuda(), w) for q, w in qs]
+    for graph in (1, 0):
+        eap.set_option("graph", graph)
+        try:
+            got, st = eap.knn_search_batch(tq, x, k, stats=True)
+            again = eap.knn_search_batch(tq, x, k)
+        finally:
+            eap.set_option("graph", 1)
+        assert again == got
+        for (q, w), res in zip(tq, got):
+            assert res == eap.knn_search(q, x, w, k), (q.numel(), w, k)
+        assert st["problems"] == sum(x.numel() - q.numel() + 1 for q, _ in tq)
+    if k == 1:
+        assert [r[0] for r in got] == eap.nn_search_batch(tq, x)
+    # fewer offsets than k, and the oracle's definition on a short series
+    small = [(torch.from_numpy(q).cuda(), min(w, 60)) for q, w in qs[:4]]
+    small.append((torch.from_numpy(gen.as_f32(gen.random_walk(995, gen.rng(4506)))).cuda(), 3))
+    got = eap.knn_search_batch(small, torch.from_numpy(xs).cuda(), k)
+    for (q, w), res in zip(small, got):
+        _check(res, q.cpu().numpy(), xs, w, k)
+
+
+def test_knn_batch_rejects_bad_k():
+    x = torch.from_numpy(gen.as_f32(gen.random_walk(500, gen.rng(4505)))).cuda()
+    q = x[:50].clone()
+    for k in (0, 65):
+        with pytest.raises(eap.EapdtwError):
+            eap.knn_search_batch([(q, 5)], x, k)
