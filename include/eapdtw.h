@@ -477,9 +477,12 @@ int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
  * skipped, which can only change which of two such near-equal candidates is
  * reported.
  *
- * Windows 1..64 with the band kernels take the cascade; window 0 (where
- * LB_Keogh is the squared Euclidean distance the window-0 kernel computes
- * anyway), wider windows and option force_wide run eapdtw_nn_search's path,
+ * Windows 1..64 take the cascade in front of the band kernels, windows
+ * 65..2048 in front of the tiled kernel (survivors swept 64 per wave with
+ * their stored normalisation and re-checked against the bound in force, no
+ * per-row tightening); window 0 (where LB_Keogh is the squared Euclidean
+ * distance the window-0 kernel computes anyway), windows above 2048 and
+ * option force_wide with a window up to 64 run eapdtw_nn_search's path,
  * reported as every candidate reaching the DTW.
  *
  * Counters of one call (lbstats may be NULL):
@@ -528,7 +531,7 @@ int eapdtw_nn_dists_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const flo
 /* The three bounds of every candidate k in [0, n-m], in full (no skipping):
  *   out_kim, out_eq, out_ec [n-m+1] : DEVICE float32 (LB_Kim, LB_Keogh with
  *   the query's envelope, LB_Keogh with the candidate's envelope).
- * window above 64 (after clamping to m-1): EINVAL.  Non-finite values:
+ * window above 2048 (after clamping to m-1): EINVAL.  Non-finite values:
  * ENONFINITE.  Synchronous. */
 int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                            int64_t n, int64_t window, float *out_kim, float *out_eq,

@@ -744,7 +744,11 @@ static hipError_t ensure_seed_stream(eapdtw_ctx *ctx) {
 
 // The cascade serves band windows from 1 on (at window 0 LB_Keogh is the
 // squared Euclidean distance itself, which the window-0 kernel computes).
-static bool lb_applies(const eapdtw_ctx *ctx, int64_t r) { return r >= 1 && use_band(ctx, r); }
+// The cascade runs in front of the band kernels' list mode, and for windows
+// above them (up to kEnvMaxR) in front of the tiled kernel's list kernel.
+static bool lb_applies(const eapdtw_ctx *ctx, int64_t r) {
+  return r >= 1 && (use_band(ctx, r) || (r > kBandRMax && r <= kEnvMaxR));
+}
 
 static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                         int64_t n, int64_t r, float *qpad, unsigned long long *bsf,
@@ -898,11 +902,45 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       b.list_lbmax = la.list_lbmax;
       b.uq = lb->uq;
       b.lq = lb->lq;
-      HIPCHK(nn_list_launcher((int)r)(b, (hi - lo + kWave - 1) / kWave, dists != nullptr,
-                                      ctx->border != 0, st));
-      log_launch(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "
-                 "nn_list_kernel<%lld,4,border=%d> grid=%lld", (long long)m, (long long)r, (long long)lo,
-                 (long long)hi, (long long)r, ctx->border != 0, (long long)((hi - lo + kWave - 1) / kWave));
+      if (use_band(ctx, r)) {
+        HIPCHK(nn_list_launcher((int)r)(b, (hi - lo + kWave - 1) / kWave, dists != nullptr,
+                                        ctx->border != 0, st));
+        log_launch(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "
+                   "nn_list_kernel<%lld,4,border=%d> grid=%lld", (long long)m, (long long)r,
+                   (long long)lo, (long long)hi, (long long)r, ctx->border != 0,
+                   (long long)((hi - lo + kWave - 1) / kWave));
+      } else {
+        // windows above the band kernels': the tiled kernel over the list
+        WideArgs w{};
+        w.lrow = (int)m;
+        w.lcol = (int)m;
+        w.r = (int)r;
+        w.x = series;
+        w.n = n;
+        w.qpad = qpad;
+        w.bsf = bsf;
+        w.k_begin = 0;
+        w.k_end = K;
+        w.fixed_ub = fixed_ub;
+        w.dists = dists;
+        w.dists_mode = dists != nullptr;
+        w.ntasks = (hi - lo + kWave - 1) / kWave;
+        w.bnd = bnd;
+        w.bnd_stride = (m + 1) * kWave;
+        w.counters = cnt;
+        w.check_interval = (int)ctx->check_interval;
+        w.list_n = la.list_n;
+        w.list_k = la.list_k;
+        w.list_mh = la.list_mh;
+        w.list_ml = la.list_ml;
+        w.list_inv = la.list_inv;
+        w.list_lbmax = la.list_lbmax;
+        const int64_t g = bnd_waves < w.ntasks ? bnd_waves : w.ntasks;
+        HIPCHK(launch_wide_list((int)ctx->wide_rows, w, (int)g, st));
+        log_launch(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "
+                   "wide_list_kernel<%d> on %lld persistent waves", (long long)m, (long long)r,
+                   (long long)lo, (long long)hi, wide_h(ctx, r, m, m), (long long)g);
+      }
       if (time_main && pi + 1 < nranges) HIPCHK(hipEventRecord(ctx->ev_lb[e++], st));
     }
   } else if (use_band(ctx, r)) {
@@ -1259,7 +1297,7 @@ int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const
   int rc = search_validate(ctx, query, m, series, n, window);
   if (rc) return rc;
   const int64_t r = window < m - 1 ? window : m - 1;
-  if (r > kBandRMax) return fail(ctx, EAPDTW_EINVAL, "lower bounds: window above 64");
+  if (r > kEnvMaxR) return fail(ctx, EAPDTW_EINVAL, "lower bounds: window above 2048");
   const int64_t K = n - m + 1;
   Plan pl;
   const size_t o_cnt = pl.add(kCntBytes);

@@ -49,6 +49,9 @@ hipError_t launch_knn_select(const unsigned long long *buf, const unsigned long 
 struct WideArgs;
 hipError_t launch_wide(int kind, int rows, const WideArgs &a, int grid, hipStream_t st);
 int wide_rows_for(int r, int lrow, int lcol);
+// The lower-bound cascade's search over a survivor list with the tiled kernel
+// (windows above kBandRMax; WideArgs::list_* set).
+hipError_t launch_wide_list(int rows, const WideArgs &a, int grid, hipStream_t st);
 // NN1 seeding: every pair's squared Euclidean distance min-ed into both series'
 // nearest-neighbour words (pairwise geometry of WideArgs).
 hipError_t launch_nn1_seed(const WideArgs &a, int grid, hipStream_t st);

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float *__re
                                                                const float *__restrict__ qz, int m,
                                                                int r, float *ux, float *lx,
                                                                float *uq, float *lq, int64_t nbx) {
-  __shared__ float tile[kEnvTile + 2 * kBandRMax];
+  extern __shared__ float tile[];  // kEnvTile + 2 r values
   const bool isq = (int64_t)blockIdx.x >= nbx;
   const float *__restrict__ src = isq ? qz : x;
   const int64_t len = isq ? (int64_t)m : n;
@@ -244,11 +244,12 @@ __global__ __launch_bounds__(64) void lb_pass_kernel(LBArgs a) {
 
 hipError_t launch_envelopes(const float *x, int64_t n, const float *qz, int m, int r, float *ux,
                             float *lx, float *uq, float *lq, hipStream_t st) {
-  if (r < 0 || r > kBandRMax) return hipErrorInvalidValue;
+  if (r < 0 || r > kEnvMaxR) return hipErrorInvalidValue;
   const int64_t nbx = (n + kEnvTile - 1) / kEnvTile;
   const int64_t nbq = ((int64_t)m + kEnvTile - 1) / kEnvTile;
-  hipLaunchKernelGGL(envelope_kernel, dim3((unsigned)(nbx + nbq)), dim3(kEnvThreads), 0, st, x, n,
-                     qz, m, r, ux, lx, uq, lq, nbx);
+  const size_t lds = sizeof(float) * (size_t)(kEnvTile + 2 * r);
+  hipLaunchKernelGGL(envelope_kernel, dim3((unsigned)(nbx + nbq)), dim3(kEnvThreads), lds, st, x,
+                     n, qz, m, r, ux, lx, uq, lq, nbx);
   return hipGetLastError();
 }
 

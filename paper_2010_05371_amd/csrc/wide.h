@@ -58,6 +58,12 @@ struct WideArgs {
   int knn;                           // search: k nearest neighbours (bsf bounds the k-th best)
   unsigned long long *knn_buf, *knn_n;
   unsigned long long *knn_slots;     // the k slot words (nullptr: those of the counter array)
+  // search over a survivor list (lower-bound cascade, wide_list_kernel):
+  // entry e holds the offset list_k[e], its normalisation constants and its
+  // largest lower bound; list_n counts the entries
+  const unsigned long long *list_n;
+  const uint32_t *list_k;
+  const float *list_mh, *list_ml, *list_inv, *list_lbmax;
   int64_t nq;                        // pairwise: > 0 = rows are the nq series of X, columns the
                                      // N series of XT, every (row, column) pair (NN1 of a test
                                      // set against a reference set); 0 = i < j within one set
@@ -506,6 +512,53 @@ __device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task
     publish_best(a.bsf, keep, d, a.bound_only ? 0xffffffffu : (uint32_t)k);
   }
   abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
+}
+
+// The search over a survivor list of the lower-bound cascade: lane l of task
+// t takes list entry 64 t + l (tasks cover the longest possible list; entries
+// past list_n are inactive) with the normalisation constants the bound pass
+// stored; an entry whose largest lower bound (lowered by kLbMargin) is now
+// above the bound in force is dropped before its sweep (counted as
+// re-checked).  Otherwise the tiled sweep of wide_search_task.
+template <int H, bool BANDED>
+__global__ __launch_bounds__(64) void wide_list_kernel(WideArgs a) {
+  const int lane = threadIdx.x;
+  float *Bw = a.bnd + (int64_t)blockIdx.x * a.bnd_stride;
+  uint64_t evaluated = 0, computed = 0, abandoned = 0, rechecked = 0;
+  const uint64_t nl = *a.list_n;
+  for (int64_t task = blockIdx.x; task * kWave < (int64_t)nl; task += gridDim.x) {
+    WideProblem p{};
+    const int64_t e = task * kWave + lane;
+    p.active = e < (int64_t)nl;
+    const int64_t ec = p.active ? e : 0;
+    const int64_t k = a.list_k[ec];
+    p.mu_hi = a.list_mh[ec];
+    p.mu_lo = a.list_ml[ec];
+    p.inv = a.list_inv[ec];
+    p.xk = a.x + k;
+    p.ub = a.dists_mode ? a.fixed_ub : load_bsf_dist(a.bsf);
+    if (p.active && a.list_lbmax[ec] * (1.0f - kLbMargin) > p.ub) {
+      p.ub = -1.0f;  // dead from the start: +inf, never kept
+      ++rechecked;
+    }
+    const float d = wide_problem<H, kWideSearch, BANDED>(a, p, Bw, lane, evaluated, computed);
+    const bool keep = p.active && d <= p.ub && d < kInf;
+    if (a.dists_mode) {
+      if (p.active) a.dists[k - a.k_begin] = d;
+    } else {
+      publish_best(a.bsf, keep, d, (uint32_t)k);
+    }
+    abandoned += (uint64_t)__popcll(__ballot(p.active && !(d < kInf)));
+  }
+  // (re-checked entries were counted per lane)
+  for (int o = 32; o >= 1; o >>= 1) rechecked += (uint64_t)__shfl_xor((long long)rechecked, o, kWave);
+  if (a.counters && lane == 0) {
+    unsigned long long *c = counter_stripe(a.counters, blockIdx.x);
+    atomicAdd(&c[kCntEvaluated], (unsigned long long)evaluated);
+    atomicAdd(&c[kCntComputed], (unsigned long long)computed);
+    atomicAdd(&c[kCntAbandoned], (unsigned long long)abandoned);
+    atomicAdd(&c[kCntLbRecheck], (unsigned long long)rechecked);
+  }
 }
 
 template <int H, int KIND, bool BANDED>

@@ -79,4 +79,22 @@ hipError_t launch_wide(int kind, int rows, const WideArgs &a, int grid, hipStrea
   }
 }
 
+// The cascade's search over a survivor list (windows above the band
+// kernels': banded 32-row tiles or whole-matrix tiles).
+hipError_t launch_wide_list(int rows, const WideArgs &a, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  const dim3 g((unsigned)grid), b(kWave);
+  switch (wide_rows_for(a.r, a.lrow, a.lcol)) {
+    case kWideFullRows:
+      if (rows == 32)
+        hipLaunchKernelGGL((wide_list_kernel<32, false>), g, b, 0, st, a);
+      else
+        hipLaunchKernelGGL((wide_list_kernel<64, false>), g, b, 0, st, a);
+      break;
+    case kWideBandRowsTall: hipLaunchKernelGGL((wide_list_kernel<kWideBandRowsTall, true>), g, b, 0, st, a); break;
+    default: return hipErrorInvalidValue;  // narrower windows: the band kernels' list mode
+  }
+  return hipGetLastError();
+}
+
 }  // namespace eapdtw
