@@ -592,8 +592,9 @@ int eapdtw_nn1_ref(eapdtw_ctx *ctx, const float *Q, int64_t nq, const float *R, 
  * (Jeong, Jeong & Omitaomu, 2011), w(k) = 1 / (1 + exp(-g (k - m/2))), maximum
  * weight 1, m the query length; weights are computed in double and rounded to
  * float32.  Otherwise as eapdtw_nn_search / eapdtw_nn_dists (z-normalisation,
- * early abandoning, pruning, ties, errors).  g must be finite; windows above
- * 64 (after clamping to m-1): EINVAL.
+ * early abandoning, pruning, ties, errors).  Windows up to 64 run the band
+ * kernels, wider ones the tiled kernel with the 2r + 1 weights in LDS.  g
+ * must be finite; windows above 4095 (after clamping to m-1): EINVAL.
  * eapdtw_nn_search_w: synchronous.  eapdtw_nn_dists_w: asynchronous unless
  * stats are requested. */
 int eapdtw_nn_search_w(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,

@@ -755,7 +755,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
                         unsigned long long *cnt, float *dists, float fixed_ub, float *bnd,
                         int64_t bnd_waves, bool time_main, const LbBufs *lb = nullptr,
                         const KnnBufs *kb = nullptr, const float *wgt = nullptr,
-                        bool one_stream = false) {
+                        bool one_stream = false, const float *wt_dev = nullptr) {
   hipStream_t st = ctx->stream;
   const int64_t K = n - m + 1;
   const int64_t nblk = (K + kWave - 1) / kWave;
@@ -775,7 +775,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
   // weighted DTW: the weights of phase differences 0..r (the unweighted
   // window-0 seeding pass stays valid: every weight is at most 1, so the
   // squared Euclidean distance bounds the weighted diagonal path's cost)
-  if (wgt) std::memcpy(a.wgt, wgt, sizeof(float) * (size_t)(r + 1));
+  // (above the band kernels' windows only the seeding workgroup's narrower
+  // window reads them; the tiled kernel takes wt_dev)
+  if (wgt) std::memcpy(a.wgt, wgt, sizeof(float) * (size_t)((r < kBandRMax ? r : kBandRMax) + 1));
   bool joined = true;
   if (!dists && ctx->seed) {
     // Bound seeding.  A candidate's DTW under a narrower window is never below
@@ -943,7 +945,7 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       }
       if (time_main && pi + 1 < nranges) HIPCHK(hipEventRecord(ctx->ev_lb[e++], st));
     }
-  } else if (use_band(ctx, r)) {
+  } else if (use_band(ctx, r) || (wgt && r <= kBandRMax)) {
     a.bsf = bsf;
     a.counters = cnt;
     a.fixed_ub = fixed_ub;
@@ -996,7 +998,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       w.knn_buf = kb->buf;
       w.knn_n = kb->n;
     }
-    HIPCHK(launch_wide(kWideSearch, (int)ctx->wide_rows, w, (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
+    w.wt_band = wt_dev;
+    HIPCHK(launch_wide(wgt ? kWideSearchW : kWideSearch, (int)ctx->wide_rows, w,
+                       (int)(bnd_waves < nblk ? bnd_waves : nblk), st));
     log_launch(ctx, "search m=%lld r=%lld: wide_kernel<%d,search> %lld blocks of 64 on %lld persistent waves",
                (long long)m, (long long)r, wide_h(ctx, r, m, m), (long long)nblk,
                (long long)(bnd_waves < nblk ? bnd_waves : nblk));
@@ -1080,6 +1084,18 @@ static void fill_lb_stats(eapdtw_lb_stats *ls, const unsigned long long *cnt, bo
   ls->lb_ms = lb_ms;
 }
 
+static int upload(eapdtw_ctx *ctx, size_t off, const void *src, size_t nbytes);
+
+// Weighted search above the band kernels' windows: the 2r + 1 weights w(|d|),
+// d = -r..r, for the tiled kernel's LDS (wgt holds w(0..r)), with kWtPad
+// entries of 1 on each side.
+static size_t band_weight_words(int64_t r) { return (size_t)(2 * r + 1 + 2 * kWtPad); }
+static int upload_band_weights(eapdtw_ctx *ctx, size_t off, const float *wgt, int64_t r) {
+  std::vector<float> t(band_weight_words(r), 1.0f);
+  for (int64_t d = -r; d <= r; ++d) t[(size_t)(d + r + kWtPad)] = wgt[d < 0 ? -d : d];
+  return upload(ctx, off, t.data(), sizeof(float) * t.size());
+}
+
 static int nn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                           int64_t n, int64_t window, int64_t *out_offset, double *out_dist,
                           eapdtw_stats *stats, bool use_lb, eapdtw_lb_stats *lbstats,
@@ -1101,12 +1117,15 @@ static int nn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const 
   const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);  // [0] search, [1] seeding pass
   const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
   const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
+  const bool wide_w = wgt && r > kBandRMax;
+  const size_t o_wt = wide_w ? pl.add(sizeof(float) * band_weight_words(r)) : 0;
   size_t o_lb[10];
   if (lb_on) lb_plan(pl, o_lb, n, m, K);
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
+  if (wide_w && (rc = upload_band_weights(ctx, o_wt, wgt, r))) return rc;
   unsigned long long *bsf = at<unsigned long long>(ctx, o_bsf);
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
   LbBufs lbb{};
@@ -1114,7 +1133,7 @@ static int nn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const 
   if (timed) HIPCHK(hipEventRecord(ctx->ev0, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
                     grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr,
-                    nullptr, wgt);
+                    nullptr, wgt, false, wide_w ? at<float>(ctx, o_wt) : nullptr);
   if (rc) return rc;
   if (timed) HIPCHK(hipEventRecord(ctx->ev1, st));
   // counters and the two best-so-far words are contiguous
@@ -1216,12 +1235,15 @@ static int nn_dists_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const f
   const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
   const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
   const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
+  const bool wide_w = wgt && r > kBandRMax;
+  const size_t o_wt = wide_w ? pl.add(sizeof(float) * band_weight_words(r)) : 0;
   size_t o_lb[10];
   if (lb_on) lb_plan(pl, o_lb, n, m, K);
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
+  if (wide_w && (rc = upload_band_weights(ctx, o_wt, wgt, r))) return rc;
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
   LbBufs lbb{};
   if (lb_on) lbb = lb_bind(ctx, o_lb);
@@ -1229,7 +1251,7 @@ static int nn_dists_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const f
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q),
                     at<unsigned long long>(ctx, o_bsf), cnt, out, ub,
                     grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr,
-                    nullptr, wgt);
+                    nullptr, wgt, false, wide_w ? at<float>(ctx, o_wt) : nullptr);
   if (rc) return rc;
   if (timed) {
     HIPCHK(hipEventRecord(ctx->ev1, st));
@@ -1258,13 +1280,16 @@ int eapdtw_nn_dists_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const flo
 // Weights of weighted DTW for phase differences 0..r of a query of length m
 // (modified logistic weight, maximum 1, midpoint m / 2).  Fails for windows
 // the band kernels do not serve.
-static int wdtw_prepare(eapdtw_ctx *ctx, int64_t m, int64_t window, float g, float *wt) {
+// The weights w(0..r) (at least kBandRMax + 1 entries) of a weighted search.
+static int wdtw_prepare(eapdtw_ctx *ctx, int64_t m, int64_t window, float g, std::vector<float> &wt) {
   if (!std::isfinite(g)) return fail(ctx, EAPDTW_EINVAL, "weighted DTW: g must be finite");
+  wt.assign(kBandRMax + 1, 0.0f);
   if (m <= 0 || window < 0) return EAPDTW_OK;  // left to the search's own checks
   const int64_t r = window < m - 1 ? window : m - 1;
-  if (!use_band(ctx, r)) return fail(ctx, EAPDTW_EINVAL, "weighted DTW: window above 64");
+  if (r > kWtMaxR) return fail(ctx, EAPDTW_EINVAL, "weighted DTW: window above 4095");
+  if (r + 1 > (int64_t)wt.size()) wt.resize((size_t)(r + 1));
   for (int64_t k = 0; k <= r; ++k)
-    wt[k] = (float)(1.0 / (1.0 + std::exp(-(double)g * ((double)k - (double)m / 2.0))));
+    wt[(size_t)k] = (float)(1.0 / (1.0 + std::exp(-(double)g * ((double)k - (double)m / 2.0))));
   return EAPDTW_OK;
 }
 
@@ -1272,21 +1297,21 @@ int eapdtw_nn_search_w(eapdtw_ctx *ctx, const float *query, int64_t m, const flo
                        int64_t n, int64_t window, float g, int64_t *out_offset, double *out_dist,
                        eapdtw_stats *stats) {
   CHECK_CTX();
-  float wt[kBandRMax + 1] = {};
+  std::vector<float> wt;
   int rc = wdtw_prepare(ctx, m, window, g, wt);
   if (rc) return rc;
   return nn_search_impl(ctx, query, m, series, n, window, out_offset, out_dist, stats, false,
-                        nullptr, wt);
+                        nullptr, wt.data());
 }
 
 int eapdtw_nn_dists_w(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
                       int64_t n, int64_t window, float g, float ub, float *out,
                       eapdtw_stats *stats) {
   CHECK_CTX();
-  float wt[kBandRMax + 1] = {};
+  std::vector<float> wt;
   int rc = wdtw_prepare(ctx, m, window, g, wt);
   if (rc) return rc;
-  return nn_dists_impl(ctx, query, m, series, n, window, ub, out, stats, false, nullptr, wt);
+  return nn_dists_impl(ctx, query, m, series, n, window, ub, out, stats, false, nullptr, wt.data());
 }
 
 int eapdtw_nn_lower_bounds(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,

@@ -15,6 +15,9 @@ constexpr int kBandRMax = 64;
 // columns hold +inf so that their cells evaluate to +inf.  Twice the largest
 // band window, because a row-longer-than-column pair reaches 2r past the end.
 constexpr int kColPad = 2 * kBandRMax + 16;
+// Widest window of the weighted search (its tiled kernel keeps the 2 r + 1
+// weights in LDS).
+constexpr int kWtMaxR = 4095;
 // Widest window of the lower-bound cascade (its envelopes keep a window of
 // 2 r + 1 values per output in LDS).
 constexpr int kEnvMaxR = 2048;

@@ -33,7 +33,17 @@ enum WideKind : int {
   kWideSearch = 0,   // rows: z-normalised candidate (per lane); columns: query (uniform)
   kWidePairwise = 1, // rows: X[i] (uniform); columns: X[j] (per lane), i < j
   kWidePairs = 2,    // rows and columns per lane from transposed copies
+  kWideSearchW = 3,  // as kWideSearch, cell (i, j) costing w(|i - j|) (a - b)^2 (weighted DTW)
 };
+
+// Padding of the weighted search's weight table on each side: the rows a
+// whole-matrix tile computes past the matrix's last row (values +inf) reach up
+// to H - 1 diagonals beyond -r, and read a finite weight there.
+constexpr int kWtPad = 64;
+
+__host__ __device__ constexpr bool wide_is_search(int kind) {
+  return kind == kWideSearch || kind == kWideSearchW;
+}
 
 struct WideArgs {
   int lrow, lcol, r;
@@ -47,6 +57,8 @@ struct WideArgs {
   float *dists;
   int dists_mode;
   int bound_only;
+  const float *wt_band;              // weighted search: w(|d|) at index d + r + kWtPad, d = -r..r,
+                                     // kWtPad entries of 1 on each side
   // pairwise / pairs
   const float *X;                    // pairwise: rows X [N][len]
   const float *XT;                   // pairwise: X transposed [len][ldN]; pairs: columns [lcol][ld]
@@ -92,12 +104,14 @@ struct WideProblem {
   float ed;
   // pairwise NN1: the two series' nearest-neighbour words (row uniform)
   const unsigned long long *nn_i, *nn_j;
+  // weighted search: the weights staged in LDS, w(|d|) at index d + r
+  const float *wsh;
 };
 
 template <int KIND>
 __device__ __forceinline__ float wide_row_value(const WideArgs &a, const WideProblem &p, int i) {
   if (i >= a.lrow) return kInf;  // rows past the end: every cell +inf
-  if (KIND == kWideSearch) return znorm_value(p.xk[i], p.mu_hi, p.mu_lo, p.inv);
+  if (wide_is_search(KIND)) return znorm_value(p.xk[i], p.mu_hi, p.mu_lo, p.inv);
   if (KIND == kWidePairwise) return p.rowp[i];  // uniform address; kept in VGPRs
   return p.rowp[(int64_t)i * a.ld];
 }
@@ -106,16 +120,17 @@ template <int KIND>
 __device__ __forceinline__ float wide_col_value(const WideArgs &a, const WideProblem &p, int j) {
   // the query value is wave-uniform; it is loaded into a VGPR (one cache line
   // per wave) so that the prefetch queue does not compete for SGPRs
-  if (KIND == kWideSearch) return (a.qpad + kColPad)[j];
+  if (wide_is_search(KIND)) return (a.qpad + kColPad)[j];
   return p.colp[(int64_t)j * p.cstride];
 }
 
 // Computes column j of the tile for rows [h_lo, h_hi] (static); rows above
 // h_lo read +inf as their top neighbour (out of band), rows below h_hi are not
 // computed and are forced to +inf when FORCE_BELOW.
-template <int H, int H_LO, int H_HI, bool FORCE_BELOW>
+// wl (weighted search only): the weight of row h of the column is wl[H-1-h].
+template <int H, int H_LO, int H_HI, bool FORCE_BELOW, bool WT = false>
 __device__ __forceinline__ void wide_column(float (&col)[H], const float (&rv)[H], float cv,
-                                            float top0, float diag0) {
+                                            float top0, float diag0, const float *wl = nullptr) {
   float up = (H_LO == 0) ? top0 : kInf;
   float dg = (H_LO == 0) ? diag0 : col[H_LO > 0 ? H_LO - 1 : 0];
   if (H_LO > 0) dg = col[H_LO - 1];
@@ -123,7 +138,8 @@ __device__ __forceinline__ void wide_column(float (&col)[H], const float (&rv)[H
   for (int h = H_LO; h <= H_HI; ++h) {
     const float left = col[h];
     const float diff = cv - rv[h];
-    const float nv = __builtin_fmaf(diff, diff, fmin3(left, up, dg));
+    const float dw = WT ? diff * wl[H - 1 - h] : diff;
+    const float nv = __builtin_fmaf(dw, diff, fmin3(left, up, dg));
     dg = left;
     up = nv;
     col[h] = nv;
@@ -193,7 +209,16 @@ template <int H, int KIND, int H_LO, int H_HI, int PD>
 __device__ __forceinline__ void wide_step_body(const WideArgs &a, float *Bw, int lane,
                                                float (&col)[H], const float (&rv)[H], Sweep<PD> &s,
                                                float ub, int tlast, int hans, float &ans,
-                                               float top0, float cv);
+                                               float top0, float cv, const float *wl);
+
+// Weighted search: where column j's weights start in LDS (row h of the tile
+// takes wl[H-1-h] = w(|j - (i0 + h)|)); nullptr for the other kinds.
+template <int H, int KIND, int PD>
+__device__ __forceinline__ const float *wide_weights(const WideArgs &a, const WideProblem &p,
+                                                     const Sweep<PD> &s, int j) {
+  if constexpr (KIND == kWideSearchW) return p.wsh + (j - s.t * H + a.r - (H - 1));
+  return nullptr;
+}
 
 // One column: its prefetched values leave the front of the queue, whose
 // entries shift down, and column j + PD enters at the back.
@@ -210,7 +235,8 @@ __device__ __forceinline__ void wide_step(const WideArgs &a, const WideProblem &
     s.qcv[k] = s.qcv[k + 1];
   }
   wide_fetch<KIND, PD>(a, p, Bw, lane, s, j + PD, s.qtop[PD - 1], s.qcv[PD - 1]);
-  wide_step_body<H, KIND, H_LO, H_HI, PD>(a, Bw, lane, col, rv, s, ub, tlast, hans, ans, top0, cv);
+  wide_step_body<H, KIND, H_LO, H_HI, PD>(a, Bw, lane, col, rv, s, ub, tlast, hans, ans, top0, cv,
+                                          wide_weights<H, KIND, PD>(a, p, s, j));
 }
 
 // One column taking queue slot K (the column's index from the queue's start,
@@ -227,16 +253,17 @@ __device__ __forceinline__ void wide_step_slot(const WideArgs &a, const WideProb
   const float top0 = qhave[K] ? s.qtop[K] : kInf;
   const float cv = s.qcv[K];
   wide_fetch_raw<KIND, PD>(a, p, Bw, lane, s, j + PD, s.qtop[K], s.qcv[K], qhave[K]);
-  wide_step_body<H, KIND, 0, H - 1, PD>(a, Bw, lane, col, rv, s, ub, tlast, hans, ans, top0, cv);
+  wide_step_body<H, KIND, 0, H - 1, PD>(a, Bw, lane, col, rv, s, ub, tlast, hans, ans, top0, cv,
+                                        wide_weights<H, KIND, PD>(a, p, s, j));
 }
 
 template <int H, int KIND, int H_LO, int H_HI, int PD>
 __device__ __forceinline__ void wide_step_body(const WideArgs &a, float *Bw, int lane,
                                                float (&col)[H], const float (&rv)[H], Sweep<PD> &s,
                                                float ub, int tlast, int hans, float &ans,
-                                               float top0, float cv) {
+                                               float top0, float cv, const float *wl) {
   const int j = s.j;
-  wide_column<H, H_LO, H_HI, false>(col, rv, cv, top0, s.diag0);
+  wide_column<H, H_LO, H_HI, false, KIND == kWideSearchW>(col, rv, cv, top0, s.diag0, wl);
   s.diag0 = top0;
   Bw[(int64_t)(j + 1) * kWave + lane] = col[H - 1];
   const bool lane_alive = (s.alive_mask >> lane) & 1ull;
@@ -285,6 +312,7 @@ __device__ __forceinline__ void wide_step2(const WideArgs &a, const WideProblem 
   wide_fetch<KIND, PD>(a, p, Bw, lane, s, j + PD + 1, s.qtop[PD - 1], s.qcv[PD - 1]);
   // keep column j's last row for the boundary store before it is overwritten
   float lastA;
+  const float *wlA = wide_weights<H, KIND, PD>(a, p, s, j);  // column j + 1: wlA + 1
   {
     float upA = topA, dgA = s.diag0;
     float prevA = 0.0f;
@@ -295,14 +323,16 @@ __device__ __forceinline__ void wide_step2(const WideArgs &a, const WideProblem 
       if (h < H) {
         const float left = col[h];
         const float diff = cvA - rv[h];
-        nA = __builtin_fmaf(diff, diff, fmin3(left, upA, dgA));
+        const float dw = KIND == kWideSearchW ? diff * wlA[H - 1 - h] : diff;
+        nA = __builtin_fmaf(dw, diff, fmin3(left, upA, dgA));
         dgA = left;
         upA = nA;
       }
       if (h >= 1) {
         const int hb = h - 1;
         const float diff = cvB - rv[hb];
-        const float nB = __builtin_fmaf(diff, diff, fmin3(prevA, upB, dgB));
+        const float dw = KIND == kWideSearchW ? diff * wlA[1 + H - 1 - hb] : diff;
+        const float nB = __builtin_fmaf(dw, diff, fmin3(prevA, upB, dgB));
         dgB = prevA;
         upB = nB;
         col[hb] = nB;
@@ -474,7 +504,7 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
     }
     lo = s.first_live;
     hi = s.last_live;
-    if (KIND == kWideSearch && !a.dists_mode && ++since >= a.check_interval) {
+    if (wide_is_search(KIND) && !a.dists_mode && ++since >= a.check_interval) {
       since = 0;
       ub = fminf(ub, load_bsf_dist(a.bsf));
     } else if (KIND == kWidePairwise && a.nn1 && ++since >= a.check_interval) {
@@ -487,11 +517,12 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
 
 // One block of 64 consecutive candidate offsets of a search (task t covers
 // offsets k_begin + 64 t + lane).
-template <int H, bool BANDED>
+template <int H, bool BANDED, int KIND = kWideSearch>
 __device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task, float *Bw,
                                                  int lane, uint64_t &evaluated, uint64_t &computed,
-                                                 uint64_t &abandoned) {
+                                                 uint64_t &abandoned, const float *wsh = nullptr) {
   WideProblem p{};
+  p.wsh = wsh;
   const int64_t kb = a.k_begin + task * kWave;
   const int64_t k = kb + lane;
   p.active = k < a.k_end;
@@ -501,7 +532,7 @@ __device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task
   znorm_params(mean, sd, p.mu_hi, p.mu_lo, p.inv);
   p.xk = a.x + kc;
   p.ub = a.dists_mode ? a.fixed_ub : load_bsf_dist(a.bsf);
-  const float d = wide_problem<H, kWideSearch, BANDED>(a, p, Bw, lane, evaluated, computed);
+  const float d = wide_problem<H, KIND, BANDED>(a, p, Bw, lane, evaluated, computed);
   const bool keep = p.active && d <= p.ub && d < kInf;
   if (a.dists_mode) {
     if (p.active) a.dists[k - a.k_begin] = d;
@@ -566,10 +597,20 @@ __global__ __launch_bounds__(64) void wide_kernel(WideArgs a) {
   const int lane = threadIdx.x;
   float *Bw = a.bnd + (int64_t)blockIdx.x * a.bnd_stride;
   uint64_t evaluated = 0, computed = 0, abandoned = 0;
+  // weighted search: the 2r + 1 weights staged in LDS (launched with that
+  // many floats of dynamic LDS; other kinds use none)
+  extern __shared__ float wsh[];
+  if constexpr (KIND == kWideSearchW) {
+    for (int t = lane; t < 2 * a.r + 1 + 2 * kWtPad; t += kWave) wsh[t] = a.wt_band[t];
+    __syncthreads();
+  }
   for (int64_t task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
     WideProblem p{};
     if (KIND == kWideSearch) {
       wide_search_task<H, BANDED>(a, task, Bw, lane, evaluated, computed, abandoned);
+    } else if (KIND == kWideSearchW) {
+      wide_search_task<H, BANDED, kWideSearchW>(a, task, Bw, lane, evaluated, computed, abandoned,
+                                                wsh + kWtPad);
     } else if (KIND == kWidePairwise) {
       const int64_t i = task / a.nblk_j, jb = task % a.nblk_j;
       const bool cross = a.nq > 0;

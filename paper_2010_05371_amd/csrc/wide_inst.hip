@@ -13,6 +13,16 @@ static hipError_t launch_wide_h(int kind, const WideArgs &a, int grid, hipStream
     case kWidePairwise:
       hipLaunchKernelGGL((wide_kernel<H, kWidePairwise, BANDED>), dim3(grid), dim3(kWave), 0, st, a);
       break;
+    case kWideSearchW:
+      // weighted search: windows above the band kernels' (tall banded tiles
+      // or whole-matrix tiles), the 2r + 1 weights in dynamic LDS
+      if constexpr ((BANDED && H == kWideBandRowsTall) || (!BANDED && (H == 32 || H == 64))) {
+        hipLaunchKernelGGL((wide_kernel<H, kWideSearchW, BANDED>), dim3(grid), dim3(kWave),
+                           sizeof(float) * (size_t)(2 * a.r + 1 + 2 * kWtPad), st, a);
+        break;
+      } else {
+        return hipErrorInvalidValue;
+      }
     default:
       hipLaunchKernelGGL((wide_kernel<H, kWidePairs, BANDED>), dim3(grid), dim3(kWave), 0, st, a);
       break;

@@ -20,9 +20,10 @@ def _cpu(t):
 
 
 # (m, window, g): window 0, narrow, bordered (>= 24) and the whole query,
-# ragged row groups, weights from flat (g = 0) to steep
+# ragged row groups, weights from flat (g = 0) to steep; windows above 64 (the
+# tiled kernel with the weights in LDS: banded tiles, and whole-query tiles)
 CASES = [(64, 0, 0.1), (101, 13, 0.05), (128, 26, 0.25), (250, 52, 0.02), (37, 40, 1.0),
-         (96, 30, 0.0)]
+         (96, 30, 0.0), (300, 100, 0.05), (150, 149, 0.1), (200, 65, 0.0)]
 
 
 @pytest.mark.parametrize("m,w,g", CASES)
@@ -41,7 +42,8 @@ def test_nn_dists_w_threshold_contract(m, w, g):
 
 
 @pytest.mark.parametrize("m,w,g,n", [(128, 13, 0.1, 20_000), (256, 52, 0.05, 30_000),
-                                     (77, 0, 0.3, 9_000), (200, 26, 0.15, 25_000)])
+                                     (77, 0, 0.3, 9_000), (200, 26, 0.15, 25_000),
+                                     (200, 100, 0.05, 12_000), (120, 119, 0.2, 8_000)])
 def test_nn_search_w_vs_oracle(m, w, g, n):
     gg = gen.rng(4601, m + w)
     q32, x32 = gen.as_f32(gen.random_walk(m, gg)), gen.as_f32(gen.random_walk(n, gg))
@@ -71,5 +73,21 @@ def test_wdtw_errors():
     x = torch.from_numpy(gen.as_f32(gen.random_walk(3000, gg))).cuda()
     with pytest.raises(eap.EapdtwError):
         eap.nn_search_w(q, x, 10, math.inf)
-    with pytest.raises(eap.EapdtwError):
-        eap.nn_search_w(q, x, 100, 0.1)
+    q = torch.from_numpy(gen.as_f32(gen.random_walk(5000, gg))).cuda()
+    x = torch.from_numpy(gen.as_f32(gen.random_walk(6000, gg))).cuda()
+    with pytest.raises(eap.EapdtwError):  # window 4999 > 4095 after clamping to m - 1
+        eap.nn_search_w(q, x, 5000, 0.1)
+
+
+def test_wdtw_force_wide_keeps_band_windows():
+    """Windows up to 64 take the band kernels even with option force_wide
+    (the tiled kernel's weighted form serves the windows above them)."""
+    gg = gen.rng(4604)
+    q = torch.from_numpy(gen.as_f32(gen.random_walk(90, gg))).cuda()
+    x = torch.from_numpy(gen.as_f32(gen.random_walk(3000, gg))).cuda()
+    want = eap.nn_search_w(q, x, 20, 0.1)
+    eap.set_option("force_wide", 1)
+    try:
+        assert eap.nn_search_w(q, x, 20, 0.1) == want
+    finally:
+        eap.set_option("force_wide", 0)
