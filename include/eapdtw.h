@@ -479,8 +479,9 @@ int eapdtw_nn_dists(eapdtw_ctx *ctx, const float *query, int64_t m, const float 
  *
  * Windows 1..64 take the cascade in front of the band kernels, windows
  * 65..2048 in front of the tiled kernel (survivors swept 64 per wave with
- * their stored normalisation and re-checked against the bound in force, no
- * per-row tightening); window 0 (where LB_Keogh is the squared Euclidean
+ * their stored normalisation, re-checked against the bound in force, and
+ * tightened per tile of rows by the rest of their LB_Keogh below the tile);
+ * window 0 (where LB_Keogh is the squared Euclidean
  * distance the window-0 kernel computes anyway), windows above 2048 and
  * option force_wide with a window up to 64 run eapdtw_nn_search's path,
  * reported as every candidate reaching the DTW.

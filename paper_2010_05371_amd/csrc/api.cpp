@@ -937,6 +937,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
         w.list_ml = la.list_ml;
         w.list_inv = la.list_inv;
         w.list_lbmax = la.list_lbmax;
+        w.list_lbq = la.list_lbq;
+        w.uq = lb->uq;
+        w.lq = lb->lq;
         const int64_t g = bnd_waves < w.ntasks ? bnd_waves : w.ntasks;
         HIPCHK(launch_wide_list((int)ctx->wide_rows, w, (int)g, st));
         log_launch(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "

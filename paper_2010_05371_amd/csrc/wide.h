@@ -76,6 +76,8 @@ struct WideArgs {
   const unsigned long long *list_n;
   const uint32_t *list_k;
   const float *list_mh, *list_ml, *list_inv, *list_lbmax;
+  const float *list_lbq;             // LB_Keogh with the query's envelope (full sum)
+  const float *uq, *lq;              // envelope of z(query) [lrow]
   int64_t nq;                        // pairwise: > 0 = rows are the nq series of X, columns the
                                      // N series of XT, every (row, column) pair (NN1 of a test
                                      // set against a reference set); 0 = i < j within one set
@@ -106,6 +108,9 @@ struct WideProblem {
   const unsigned long long *nn_i, *nn_j;
   // weighted search: the weights staged in LDS, w(|d|) at index d + r
   const float *wsh;
+  // cascade list mode: the candidate's query-envelope LB_Keogh (lowered) and
+  // the sum of its terms over the rows swept so far
+  float lb_total, lb_prefix;
 };
 
 template <int KIND>
@@ -415,7 +420,7 @@ struct ExitPhase<H, KIND, H - 1, PD> {
 
 // One problem per lane: all tiles.  Returns the lane's result (+inf if the
 // distance exceeds the bound); accumulates the work counters.
-template <int H, int KIND, bool BANDED>
+template <int H, int KIND, bool BANDED, bool LIST = false>
 __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p, float *Bw, int lane,
                                               uint64_t &evaluated, uint64_t &computed) {
   const int r = a.r, lrow = a.lrow, lcol = a.lcol;
@@ -436,6 +441,23 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
     for (int h = 0; h < H; ++h) {
       rv[h] = wide_row_value<KIND>(a, p, i0 + h);
       col[h] = kInf;
+    }
+    // cascade list mode: every path through the tile still pays the
+    // query-envelope LB_Keogh terms of the rows below it, so the tile's
+    // liveness tests use the bound lowered by that rest (the cumulative-bound
+    // tightening); the answer itself is compared with the bound
+    float ubt = ub;
+    if constexpr (LIST) {
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        if (i0 + h < lrow) {
+          const float z = rv[h];
+          const float dd = z - __builtin_amdgcn_fmed3f(z, a.lq[i0 + h], a.uq[i0 + h]);
+          p.lb_prefix = __builtin_fmaf(dd, dd, p.lb_prefix);
+        }
+      }
+      const float rest = p.lb_total - p.lb_prefix;
+      ubt = ub - (rest > 0.0f ? rest : 0.0f);
     }
     const int jb_lo = i0 - r > 0 ? i0 - r : 0;
     const int jb_hi = i0 + H - 1 + r < lcol - 1 ? i0 + H - 1 + r : lcol - 1;
@@ -462,12 +484,12 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
     for (int k = 0; k < PD; ++k) wide_fetch<KIND, PD>(a, p, Bw, lane, s, s.j + k, s.qtop[k], s.qcv[k]);
     // entering triangle [i0-r, i0-r+H-2], full columns up to i0+r, exiting triangle
     if (BANDED) {
-      EnterPhase<H, KIND, 0, PD>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 - r);
+      EnterPhase<H, KIND, 0, PD>::run(a, p, Bw, lane, col, rv, s, ubt, tlast, hans, ans, i0 - r);
       while (s.go && s.j <= i0 + r) {
-        if (H <= 32 && wide_pair_ok(s, i0 + r, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ub);
-        else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+        if (H <= 32 && wide_pair_ok(s, i0 + r, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ubt);
+        else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ubt, tlast, hans, ans);
       }
-      ExitPhase<H, KIND, 0, PD>::run(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans, i0 + r + 1);
+      ExitPhase<H, KIND, 0, PD>::run(a, p, Bw, lane, col, rv, s, ubt, tlast, hans, ans, i0 + r + 1);
     } else {
       // the window covers the whole matrix: every column is a full column
       if constexpr (H > 32) {
@@ -478,17 +500,17 @@ __device__ __forceinline__ float wide_problem(const WideArgs &a, WideProblem &p,
         for (int k = 0; k < PD; ++k)
           wide_fetch_raw<KIND, PD>(a, p, Bw, lane, s, s.j + k, s.qtop[k], s.qcv[k], qhave[k]);
         while (s.go) {
-          wide_step_slot<H, KIND, PD, 0>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
-          if (s.go) wide_step_slot<H, KIND, PD, 1 % PD>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
-          if (s.go) wide_step_slot<H, KIND, PD, 2 % PD>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
-          if (s.go) wide_step_slot<H, KIND, PD, 3 % PD>(a, p, Bw, lane, col, rv, s, qhave, ub, tlast, hans, ans);
+          wide_step_slot<H, KIND, PD, 0>(a, p, Bw, lane, col, rv, s, qhave, ubt, tlast, hans, ans);
+          if (s.go) wide_step_slot<H, KIND, PD, 1 % PD>(a, p, Bw, lane, col, rv, s, qhave, ubt, tlast, hans, ans);
+          if (s.go) wide_step_slot<H, KIND, PD, 2 % PD>(a, p, Bw, lane, col, rv, s, qhave, ubt, tlast, hans, ans);
+          if (s.go) wide_step_slot<H, KIND, PD, 3 % PD>(a, p, Bw, lane, col, rv, s, qhave, ubt, tlast, hans, ans);
         }
       } else {
         while (s.go) {
           // (two-column steps only pay off while the doubled state still fits
           // in registers at a useful occupancy)
-          if (wide_pair_ok(s, s.jend, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ub);
-          else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ub, tlast, hans, ans);
+          if (wide_pair_ok(s, s.jend, tlast, a.lcol)) wide_step2<H, KIND, PD>(a, p, Bw, lane, col, rv, s, ubt);
+          else wide_step<H, KIND, 0, H - 1, PD>(a, p, Bw, lane, col, rv, s, ubt, tlast, hans, ans);
         }
       }
     }
@@ -550,7 +572,9 @@ __device__ __forceinline__ void wide_search_task(const WideArgs &a, int64_t task
 // past list_n are inactive) with the normalisation constants the bound pass
 // stored; an entry whose largest lower bound (lowered by kLbMargin) is now
 // above the bound in force is dropped before its sweep (counted as
-// re-checked).  Otherwise the tiled sweep of wide_search_task.
+// re-checked).  Otherwise the tiled sweep of wide_search_task, each tile's
+// liveness tests taking the bound lowered by the rest of the entry's
+// query-envelope LB_Keogh.
 template <int H, bool BANDED>
 __global__ __launch_bounds__(64) void wide_list_kernel(WideArgs a) {
   const int lane = threadIdx.x;
@@ -568,11 +592,13 @@ __global__ __launch_bounds__(64) void wide_list_kernel(WideArgs a) {
     p.inv = a.list_inv[ec];
     p.xk = a.x + k;
     p.ub = a.dists_mode ? a.fixed_ub : load_bsf_dist(a.bsf);
+    p.lb_total = a.list_lbq[ec] * (1.0f - kLbMargin);
+    p.lb_prefix = 0.0f;
     if (p.active && a.list_lbmax[ec] * (1.0f - kLbMargin) > p.ub) {
       p.ub = -1.0f;  // dead from the start: +inf, never kept
       ++rechecked;
     }
-    const float d = wide_problem<H, kWideSearch, BANDED>(a, p, Bw, lane, evaluated, computed);
+    const float d = wide_problem<H, kWideSearch, BANDED, true>(a, p, Bw, lane, evaluated, computed);
     const bool keep = p.active && d <= p.ub && d < kInf;
     if (a.dists_mode) {
       if (p.active) a.dists[k - a.k_begin] = d;
