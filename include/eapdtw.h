@@ -558,6 +558,21 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
                       int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
                       double *out_dists, eapdtw_stats *stats);
 
+/* eapdtw_knn_search behind the lower-bound cascade of eapdtw_nn_search_lb
+ * (Section 5's UCR Suite bounds with the k-th best distance as the bound
+ * in force): LB_Kim and LB_Keogh skip a candidate whose bound exceeds the
+ * bound word, the survivors run the DTW of the list kernels (per-row
+ * tightening as in eapdtw_nn_search_lb) and append to the buffer as above.
+ * Arguments, outputs and errors as eapdtw_knn_search; lbstats (may be NULL)
+ * as eapdtw_nn_search_lb.  The k results are eapdtw_knn_search's, except that
+ * a candidate whose distance lies within float32 rounding of the k-th best
+ * may be skipped (only the order among such near-equal candidates can
+ * change).  Windows 0 and above 2048 run eapdtw_knn_search's path.
+ * Synchronous. */
+int eapdtw_knn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                         int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
+                         double *out_dists, eapdtw_stats *stats, eapdtw_lb_stats *lbstats);
+
 /* ---------------------------------------------------------------------------
  * Leave-one-out nearest neighbour of every series of a set (the NN1
  * classification use of Section 2.2): for each series i, the series j != i with

@@ -41,7 +41,7 @@ __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_d
            "knn_search_batch",
            "EapdtwError", "Stats", "set_option", "get_option", "pairwise_index", "autotune",
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
-           "nn_lower_bounds", "LbStats", "knn_search", "nn1", "nn_search_w", "nn_dists_w",
+           "nn_lower_bounds", "LbStats", "knn_search", "knn_search_lb", "nn1", "nn_search_w", "nn_dists_w",
            "nn1_ref", "dtw_path", "dtw_pairs_batch", "pack_pairs", "DTWBatchFunction",
            "dtw_batch_path", "dba_step", "unpack_ranges"]
 
@@ -308,6 +308,25 @@ def knn_search(query, series, window: int, k: int, stats: bool = False):
                                          ctypes.byref(st) if stats else None))
     res = [(offs[i], dists[i]) for i in range(kk)]
     return (res, st.as_dict()) if stats else res
+
+
+def knn_search_lb(query, series, window: int, k: int, stats: bool = False):
+    """knn_search with the lower-bound cascade in front of the DTW (the k-th
+    best distance as the bound in force).  With stats=True returns
+    (list, stats) where stats also holds the cascade's counters."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    kk = int(k)
+    offs = (ctypes.c_int64 * max(kk, 1))()
+    dists = (ctypes.c_double * max(kk, 1))()
+    st, ls = Stats(), LbStats()
+    ctx.check(ctx._lib.eapdtw_knn_search_lb(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                            int(window), kk, offs, dists,
+                                            ctypes.byref(st) if stats else None,
+                                            ctypes.byref(ls) if stats else None))
+    res = [(offs[i], dists[i]) for i in range(kk)]
+    return (res, {**st.as_dict(), **ls.as_dict()}) if stats else res
 
 
 def nn_search_w(query, series, window: int, g: float, stats: bool = False):

@@ -821,7 +821,9 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       s.knn = kb->k;
     }
     hipStream_t ss = st;
-    if (use_band(ctx, r) && !one_stream) {
+    // (a k-NN search behind the cascade seeds on the search stream: its bound
+    // pass has no window-0 bound to start from, the seed's k-th best is it)
+    if (use_band(ctx, r) && !one_stream && !(kb && lb && lb_applies(ctx, r))) {
       HIPCHK(ensure_seed_stream(ctx));
       HIPCHK(hipEventRecord(ctx->ev_fork, st));
       HIPCHK(hipStreamWaitEvent(ctx->seed_stream, ctx->ev_fork, 0));
@@ -904,6 +906,11 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
       b.list_lbmax = la.list_lbmax;
       b.uq = lb->uq;
       b.lq = lb->lq;
+      if (kb) {
+        b.knn = kb->k;
+        b.knn_buf = kb->buf;
+        b.knn_n = kb->n;
+      }
       if (use_band(ctx, r)) {
         HIPCHK(nn_list_launcher((int)r)(b, (hi - lo + kWave - 1) / kWave, dists != nullptr,
                                         ctx->border != 0, st));
@@ -940,6 +947,11 @@ static int search_queue(eapdtw_ctx *ctx, const float *query, int64_t m, const fl
         w.list_lbq = la.list_lbq;
         w.uq = lb->uq;
         w.lq = lb->lq;
+        if (kb) {
+          w.knn = kb->k;
+          w.knn_buf = kb->buf;
+          w.knn_n = kb->n;
+        }
         const int64_t g = bnd_waves < w.ntasks ? bnd_waves : w.ntasks;
         HIPCHK(launch_wide_list((int)ctx->wide_rows, w, (int)g, st));
         log_launch(ctx, "search m=%lld r=%lld candidates %lld..%lld: envelope_kernel, lb_pass_kernel, "
@@ -1513,9 +1525,10 @@ int eapdtw_nn1_ref(eapdtw_ctx *ctx, const float *Q, int64_t nq, const float *R, 
   return EAPDTW_OK;
 }
 
-int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
-                      int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
-                      double *out_dists, eapdtw_stats *stats) {
+static int knn_search_impl(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                           int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
+                           double *out_dists, eapdtw_stats *stats, bool use_lb,
+                           eapdtw_lb_stats *lbstats) {
   CHECK_CTX();
   KnobGuard knobs(ctx);
   knobs.apply_cached(m, window);
@@ -1527,6 +1540,8 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
   if (stats) std::memset(stats, 0, sizeof *stats);
   const int64_t K = n - m + 1;
   const int64_t grid = use_band(ctx, r) ? 0 : wide_grid((K + kWave - 1) / kWave);
+  const bool lb_on = use_lb && lb_applies(ctx, r);
+  const bool timed = stats != nullptr || lbstats != nullptr;
   Plan pl;
   const size_t o_cnt = pl.add(kCntBytes);
   const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
@@ -1535,6 +1550,8 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
   const size_t o_buf = pl.add(sizeof(unsigned long long) * K);
   const size_t o_tmp = pl.add(sizeof(unsigned long long) * K);
   const size_t o_bnd = grid ? pl.add(sizeof(float) * grid * (m + 1) * kWave) : 0;
+  size_t o_lb[10];
+  if (lb_on) lb_plan(pl, o_lb, n, m, K);
   rc = ensure_scratch(ctx, pl.off);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
@@ -1542,16 +1559,18 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
   unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
   unsigned long long *bsf = at<unsigned long long>(ctx, o_bsf);
   // the kept-candidate count and the filtered count live in counter words
-  // (stripe 0 and 1, slot kCntListN), cleared by the set-up kernel
-  const KnnBufs kb{(int)k, at<unsigned long long>(ctx, o_buf), cnt + kCntListN};
-  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  // (stripe 0 and 1, slot kCntKnnN), cleared by the set-up kernel
+  const KnnBufs kb{(int)k, at<unsigned long long>(ctx, o_buf), cnt + kCntKnnN};
+  LbBufs lbb{};
+  if (lb_on) lbb = lb_bind(ctx, o_lb);
+  if (timed) HIPCHK(hipEventRecord(ctx->ev0, st));
   rc = search_queue(ctx, query, m, series, n, r, at<float>(ctx, o_q), bsf, cnt, nullptr, 0.f,
-                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, stats != nullptr, nullptr, &kb);
+                    grid ? at<float>(ctx, o_bnd) : nullptr, grid, timed, lb_on ? &lbb : nullptr, &kb);
   if (rc) return rc;
   HIPCHK(launch_knn_select(kb.buf, kb.n, bsf, at<unsigned long long>(ctx, o_tmp),
-                           cnt + kCntStride + kCntListN, (int)k,
+                           cnt + kCntStride + kCntKnnN, (int)k,
                            at<unsigned long long>(ctx, o_res), st));
-  if (stats) HIPCHK(hipEventRecord(ctx->ev1, st));
+  if (timed) HIPCHK(hipEventRecord(ctx->ev1, st));
   // counters, the best-so-far words and the results are contiguous
   rc = readback(ctx, o_cnt, o_res + sizeof(unsigned long long) * kKnnMax - o_cnt);
   if (rc) return rc;
@@ -1565,10 +1584,26 @@ int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const floa
     out_offsets[i] = have ? (int64_t)best_offset(res[i]) : -1;
     out_dists[i] = have ? (double)best_dist(res[i]) : INFINITY;
   }
+  if (lb_on && timed) lb_split_times(ctx);
   if (stats)
     fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
-               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+               elapsed(ctx->ev0, ctx->ev1), lb_on ? ctx->lb_dp_ms : elapsed(ctx->ev2, ctx->ev3));
+  fill_lb_stats(lbstats, hc, lb_on, (uint64_t)K, ctx->lb_ms);
   return EAPDTW_OK;
+}
+
+int eapdtw_knn_search(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                      int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
+                      double *out_dists, eapdtw_stats *stats) {
+  return knn_search_impl(ctx, query, m, series, n, window, k, out_offsets, out_dists, stats,
+                         false, nullptr);
+}
+
+int eapdtw_knn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                         int64_t n, int64_t window, int64_t k, int64_t *out_offsets,
+                         double *out_dists, eapdtw_stats *stats, eapdtw_lb_stats *lbstats) {
+  return knn_search_impl(ctx, query, m, series, n, window, k, out_offsets, out_dists, stats,
+                         true, lbstats);
 }
 
 static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {

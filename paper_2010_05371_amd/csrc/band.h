@@ -900,7 +900,7 @@ __device__ __forceinline__ void nn_band_body(const NNArgs &a, int64_t blk) {
   const bool keep = alive && !stopped && d <= ub;
   if (DISTS) {
     if (active) a.dists[k - a.k_begin] = keep ? d : kInf;
-  } else if (!LIST && a.knn > 0) {
+  } else if (a.knn > 0) {
     publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters, a.knn_slots}, keep, d,
                 (uint32_t)k);
   } else {

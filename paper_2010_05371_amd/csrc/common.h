@@ -49,6 +49,9 @@ enum Counter : int {
   kCntListN = 7,      // survivor list lengths (one word per pass, in stripes 0, 1, ...)
   kCntLbRecheck = 8,  // list entries dropped when the DP pass re-checks their bound
   kCntSlots = 9,
+  // not a counter: a k-nearest-neighbour search's kept-candidate count
+  // (stripe 0) and its selection's filtered count (stripe 1)
+  kCntKnnN = 10,
   // not a counter: word j of the k-nearest-neighbour slots sits at slot
   // kCntKnnSlot of stripe j (own 128-byte line each; cleared with the counters)
   kCntKnnSlot = 15

@@ -602,6 +602,9 @@ __global__ __launch_bounds__(64) void wide_list_kernel(WideArgs a) {
     const bool keep = p.active && d <= p.ub && d < kInf;
     if (a.dists_mode) {
       if (p.active) a.dists[k - a.k_begin] = d;
+    } else if (a.knn > 0) {
+      publish_knn(KnnOut{a.bsf, a.knn, a.knn_buf, a.knn_n, a.counters, a.knn_slots}, keep, d,
+                  (uint32_t)k);
     } else {
       publish_best(a.bsf, keep, d, (uint32_t)k);
     }

@@ -163,3 +163,41 @@ def test_knn_batch_rejects_bad_k():
     for k in (0, 65):
         with pytest.raises(eap.EapdtwError):
             eap.knn_search_batch([(q, 5)], x, k)
+
+
+# k-NN behind the lower-bound cascade: the same cases (windows 0 and above 2048
+# take the plain path, reported as every candidate reaching the DTW), plus
+# noisy sinusoids where most candidates are skipped
+@pytest.mark.parametrize("m,w,n,k", CASES)
+def test_knn_lb_vs_oracle(m, w, n, k):
+    g = gen.rng(4410, m * 100 + w)
+    q32, x32 = gen.as_f32(gen.random_walk(m, g)), gen.as_f32(gen.random_walk(n, g))
+    res, st = eap.knn_search_lb(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), w, k,
+                                stats=True)
+    _check(res, q32, x32, w, k)
+    K = n - m + 1
+    assert st["pruned_kim"] + st["pruned_keogh_eq"] + st["pruned_keogh_ec"] + \
+        st["pruned_recheck"] + st["dtw_candidates"] == K
+    if w == 0:
+        assert st["dtw_candidates"] == K
+    else:
+        assert min(k, K) <= st["dtw_candidates"] <= K
+
+
+@pytest.mark.parametrize("m,w,k", [(128, 13, 10), (128, 40, 16), (256, 100, 5), (200, 150, 20)])
+def test_knn_lb_sinusoid_prunes(m, w, k):
+    q32, x32, _ = gen.c2(n=20_000, m=m)
+    q, x = torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda()
+    res, st = eap.knn_search_lb(q, x, w, k, stats=True)
+    _check(res, q32, x32, w, k)
+    assert st["dtw_candidates"] < x32.size - m + 1
+    plain = eap.knn_search(q, x, w, k)
+    assert [d for _, d in res] == pytest.approx([d for _, d in plain], rel=1e-5, abs=1e-6)
+
+
+def test_knn_lb_bad_k():
+    q = torch.zeros(16, device="cuda")
+    x = torch.arange(100, dtype=torch.float32, device="cuda")
+    for k in (0, 65):
+        with pytest.raises(eap.EapdtwError):
+            eap.knn_search_lb(q, x, 3, k)
