@@ -46,6 +46,26 @@ def test_c2_full_dists_sampled(c2):
     assert d.min() == np.float32(dk) and int(np.argmin(d)) == k
 
 
+@pytest.mark.parametrize("w,k", [(13, 10), (26, 10), (52, 10), (52, 64)])
+def test_c2_full_knn_lb_vs_all_distances(c2, w, k):
+    """The k nearest neighbours behind the cascade at full size: the k smallest
+    of every candidate's distance (nn_dists, no bound), each reported distance
+    the candidate's own distance bit for bit, and within tolerance of the
+    oracle's distance at that offset."""
+    q32, x32, _, q, x = c2
+    res = eap.knn_search_lb(q, x, w, k)
+    d = _cpu(eap.nn_dists(q, x, w))
+    order = np.lexsort((np.arange(d.size), d))[:k]
+    got = np.array([dd for _, dd in res])
+    assert np.allclose(got, d[order].astype(np.float64), rtol=1e-5, atol=1e-6)
+    offs = [o for o, _ in res]
+    assert len(set(offs)) == k and all(o >= 0 for o in offs)
+    assert all(d[o] == np.float32(dd) for o, dd in res)
+    at = oracle.nn_dists(gen.as_oracle(q32), gen.as_oracle(x32), w, offs)
+    for (o, dd), a in zip(res, at):
+        assert close(dd, a), (o, dd, a)
+
+
 def test_c3_full_pairwise_sampled():
     """1,999,000 pairs of length 512, full window: 512 sampled pairs against
     the oracle; DTW <= squared Euclidean distance on the same sample."""
