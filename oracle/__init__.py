@@ -10,6 +10,9 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
 
 * ``dtw``         -- Section 2, Eq. 1-5 with the Sakoe-Chiba window of
   Section 2.1, full (lS+1)x(lT+1) matrix in double precision;
+* ``erp``, ``erp_pairs`` -- the edit distance with real penalty (Chen & Ng,
+  VLDB 2004), an elastic distance with DTW's three moves and gap costs, of
+  the kind the paper's closing outlook names; same matrix and window;
 * ``eap``         -- Section 2.2's threshold contract: DTW if <= ub else +inf;
 * ``znorm``       -- z-normalisation (population sigma), the UCR-Suite step the
   paper's search inherits (Section 5);
@@ -92,6 +95,8 @@ def _load():
     lib.oracle_window_stats.restype = None
     lib.oracle_dtw.argtypes = [dp, i64, dp, i64, i64]
     lib.oracle_dtw.restype = ctypes.c_double
+    lib.oracle_erp.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double]
+    lib.oracle_erp.restype = ctypes.c_double
     lib.oracle_dtw_matrix.argtypes = [dp, i64, dp, i64, i64, dp]
     lib.oracle_dtw_matrix.restype = ctypes.c_int
     lib.oracle_eap.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double]
@@ -173,6 +178,25 @@ def dtw(S, T, window: int | None = None) -> float:
     S, T = _f64(S), _f64(T)
     r = max(S.size, T.size) if window is None else int(window)
     return float(_load().oracle_dtw(_ptr(S), S.size, _ptr(T), T.size, r))
+
+
+def erp(S, T, window: int | None = None, g: float = 0.0) -> float:
+    """The edit distance with real penalty (Chen & Ng 2004; an elastic distance
+    of the paper's closing outlook) under the Sakoe-Chiba window: the plain
+    full-matrix recurrence, L1 costs, gap value g."""
+    S, T = _f64(S), _f64(T)
+    r = max(S.size, T.size) if window is None else int(window)
+    return float(_load().oracle_erp(_ptr(S), S.size, _ptr(T), T.size, r, float(g)))
+
+
+def erp_pairs(X, Y, window: int, g: float = 0.0, ub=None) -> np.ndarray:
+    """ERP of every row pair (X[p], Y[p]); with ub (one bound per pair) the
+    threshold contract of Section 2.2: the distance if <= ub[p], else +inf."""
+    X, Y = np.atleast_2d(_f64(X)), np.atleast_2d(_f64(Y))
+    out = np.array([erp(X[p], Y[p], window, g) for p in range(X.shape[0])])
+    if ub is not None:
+        out = np.where(out <= np.asarray(ub, dtype=np.float64), out, np.inf)
+    return out
 
 
 def dtw_matrix(S, T, window: int | None = None) -> np.ndarray:

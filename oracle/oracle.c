@@ -166,6 +166,39 @@ double oracle_wdtw(const double *S, int64_t lS, const double *T, int64_t lT, int
   return v;
 }
 
+/* The edit distance with real penalty, ERP (Chen & Ng, VLDB 2004), an elastic
+ * distance of the kind the paper's closing outlook names: DTW's three-move
+ * structure, where a diagonal move costs |S_i - T_j| and a vertical or
+ * horizontal move aligns its point with the gap value g at cost |S_i - g| or
+ * |T_j - g|.  Full (lS+1) x (lT+1) matrix under the Sakoe-Chiba window applied
+ * to every cell, borders included: M(0,0) = 0, M(0,j) = M(0,j-1) + |T_j - g|
+ * and M(i,0) = M(i-1,0) + |S_i - g| while |i - j| <= r, every cell outside the
+ * window +inf; then
+ *   M(i,j) = min(M(i-1,j-1) + |S_i - T_j|, M(i-1,j) + |S_i - g|, M(i,j-1) + |T_j - g|). */
+double oracle_erp(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r, double g) {
+  const int64_t W = lT + 1;
+  double *M = (double *)malloc((size_t)((lS + 1) * W) * sizeof(double));
+  if (!M) return NAN;
+  for (int64_t c = 0; c < (lS + 1) * W; ++c) M[c] = ORACLE_INF;
+  M[0] = 0.0;
+  for (int64_t j = 1; j <= lT && j <= r; ++j) M[j] = M[j - 1] + fabs(T[j - 1] - g);
+  for (int64_t i = 1; i <= lS && i <= r; ++i) M[i * W] = M[(i - 1) * W] + fabs(S[i - 1] - g);
+  for (int64_t i = 1; i <= lS; ++i) {
+    int64_t jlo = i - r, jhi = i + r;
+    if (jlo < 1) jlo = 1;
+    if (jhi > lT) jhi = lT;
+    for (int64_t j = jlo; j <= jhi; ++j) {
+      const double diag = M[(i - 1) * W + j - 1] + fabs(S[i - 1] - T[j - 1]);
+      const double up = M[(i - 1) * W + j] + fabs(S[i - 1] - g);
+      const double left = M[i * W + j - 1] + fabs(T[j - 1] - g);
+      M[i * W + j] = min3d(diag, up, left);
+    }
+  }
+  const double v = M[lS * W + lT];
+  free(M);
+  return v;
+}
+
 double oracle_dtw(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r) {
   if (lS == 0 && lT == 0) return 0.0;          /* Eq. 2 */
   if (lS == 0 || lT == 0) return ORACLE_INF;   /* Eq. 3-4 */
