@@ -202,6 +202,30 @@ int eapdtw_dtw_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t np
                      int64_t window, int ub_mode, const float *ub, float *out, eapdtw_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * ERP, the edit distance with real penalty (Chen & Ng, VLDB 2004), of a batch
+ * of pairs of equal length: an elastic distance with DTW's three moves (the
+ * kind the paper's closing outlook carries the method over to) in which a
+ * diagonal move costs |S_i - T_j| and a vertical or horizontal move aligns
+ * its point with the gap value g at cost |S_i - g| or |T_j - g|.  The
+ * Sakoe-Chiba window applies to every cell, borders included: M(0,0) = 0,
+ * M(0,j) = M(0,j-1) + |T_j - g| and M(i,0) = M(i-1,0) + |S_i - g| while
+ * |i - j| <= r, cells outside the window +inf.  Early abandoning as
+ * Section 2.2: a pair whose row of cells all exceed its bound returns +inf.
+ *   X, Y [npairs][len] : DEVICE float32 row-major; pair p = (X[p], Y[p]),
+ *                        used as given (not normalised).
+ *   window             : r >= 0, clamped to len - 1; at most 64 after the
+ *                        clamp (EINVAL beyond).
+ *   g                  : gap value (finite, taken as float32).
+ *   ub                 : DEVICE float32 [npairs], one bound per pair (the
+ *                        distance if <= ub[p], else +inf), or NULL: no bound.
+ *   out [npairs]       : DEVICE float32 distances.
+ * len 0 gives 0 (X and Y may then be NULL).  Values are float32 sums in the recurrence's order; inputs
+ * are not checked for non-finite values.  Asynchronous on the context's
+ * stream (synchronous when stats is given). */
+int eapdtw_erp_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs, int64_t len,
+                     int64_t window, double g, const float *ub, float *out, eapdtw_stats *stats);
+
+/* ---------------------------------------------------------------------------
  * All pairwise distances of N series (Section 2.3: pruning with the squared
  * Euclidean distance as the only bound, e.g. for 1-NN classification).
  *   X [N][len] : DEVICE float32 row-major.

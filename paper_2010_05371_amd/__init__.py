@@ -43,7 +43,7 @@ __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_d
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
            "nn_lower_bounds", "LbStats", "knn_search", "knn_search_lb", "nn1", "nn_search_w", "nn_dists_w",
            "nn1_ref", "dtw_path", "dtw_pairs_batch", "pack_pairs", "DTWBatchFunction",
-           "dtw_batch_path", "dba_step", "unpack_ranges"]
+           "dtw_batch_path", "dba_step", "unpack_ranges", "erp_pairs"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -308,6 +308,29 @@ def knn_search(query, series, window: int, k: int, stats: bool = False):
                                          ctypes.byref(st) if stats else None))
     res = [(offs[i], dists[i]) for i in range(kk)]
     return (res, st.as_dict()) if stats else res
+
+
+def erp_pairs(X, Y, window: int, g: float = 0.0, ub=None, stats: bool = False):
+    """ERP (edit distance with real penalty, gap value g) of every row pair
+    (X[p], Y[p]) of two [npairs, len] float32 device tensors under the window
+    (at most 64 after clamping to len - 1); with ub (a [npairs] tensor) the
+    distance if <= ub[p], else +inf."""
+    x, y = _dev(X), _dev(Y)
+    if x.dim() != 2 or x.shape != y.shape:
+        raise ValueError("X and Y must be [npairs, len] tensors of one shape")
+    u = None
+    if ub is not None:
+        u = _dev(ub, x.device.index)
+        if u.numel() != x.shape[0]:
+            raise ValueError("ub must hold one bound per pair")
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    out = torch.empty(x.shape[0], device=x.device, dtype=torch.float32)
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_erp_pairs(ctx.handle, _ptr(x), _ptr(y), x.shape[0], x.shape[1],
+                                        int(window), float(g), _ptr(u) if u is not None else None,
+                                        _ptr(out), ctypes.byref(st) if stats else None))
+    return (out, st.as_dict()) if stats else out
 
 
 def knn_search_lb(query, series, window: int, k: int, stats: bool = False):

@@ -3,6 +3,7 @@
 // in the device kernels; the host only validates, plans memory and launches.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -621,6 +622,64 @@ int eapdtw_dtw_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t np
                      int64_t window, int ub_mode, const float *ub, float *out, eapdtw_stats *stats) {
   CHECK_CTX();
   return pairs_common(ctx, X, Y, npairs, len, window, ub_mode, ub, out, stats);
+}
+
+int eapdtw_erp_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs, int64_t len,
+                     int64_t window, double g, const float *ub, float *out, eapdtw_stats *stats) {
+  CHECK_CTX();
+  if (npairs < 0 || len < 0) return fail(ctx, EAPDTW_EINVAL, "negative size");
+  if (window < 0) return fail(ctx, EAPDTW_EINVAL, "window < 0");
+  if (npairs > 0 && (!out || (len > 0 && (!X || !Y)))) return fail(ctx, EAPDTW_EINVAL, "NULL pointer");
+  if (!std::isfinite(g) || std::fabs(g) > FLT_MAX) return fail(ctx, EAPDTW_EINVAL, "g must be a finite float32");
+  if (len > INT_MAX / 2) return fail(ctx, EAPDTW_EINVAL, "series too long");
+  if (npairs > (int64_t)INT_MAX - kWave) return fail(ctx, EAPDTW_EINVAL, "too many pairs");
+  const int64_t r = len > 0 && window > len - 1 ? len - 1 : window;
+  if (len > 0 && r > kErpMaxR)
+    return fail(ctx, EAPDTW_EINVAL, "ERP takes windows up to 64 (after clamping to len - 1)");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (npairs == 0) return EAPDTW_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  if (len == 0) {
+    HIPCHK(launch_fill_f32(out, 0.0f, npairs, st));
+    return EAPDTW_OK;
+  }
+  const int64_t ld = (npairs + kWave - 1) / kWave * kWave;
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_xt = pl.add(sizeof(float) * len * ld);
+  const size_t o_yt = pl.add(sizeof(float) * len * ld);
+  int rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  HIPCHK(launch_fill_u64(cnt, 0ull, kCntWords, st));
+  HIPCHK(launch_transpose_pad(X, npairs, (int)len, ld, 0, 0.0f, at<float>(ctx, o_xt), st));
+  HIPCHK(launch_transpose_pad(Y, npairs, (int)len, ld, 0, 0.0f, at<float>(ctx, o_yt), st));
+  if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
+  ErpArgs e{};
+  e.Xt = at<float>(ctx, o_xt);
+  e.Yt = at<float>(ctx, o_yt);
+  e.ld = ld;
+  e.npairs = npairs;
+  e.len = (int)len;
+  e.g = (float)g;
+  e.ub = ub;
+  e.out = out;
+  e.counters = cnt;
+  HIPCHK(launch_erp_pairs((int)r, e, st));
+  log_launch(ctx, "erp pairs: %lld pairs of length %lld, r=%lld: erp_pairs_kernel<%lld> grid=%lld",
+             (long long)npairs, (long long)len, (long long)r, (long long)r, (long long)(ld / kWave));
+  if (stats) {
+    HIPCHK(hipEventRecord(ctx->ev3, st));
+    HIPCHK(hipEventRecord(ctx->ev1, st));
+    rc = readback(ctx, o_cnt, kCntBytes);
+    if (rc) return rc;
+    fill_stats(stats, reinterpret_cast<unsigned long long *>(ctx->pinned),
+               (uint64_t)(band_cells_total(len, len, r) * npairs), (uint64_t)npairs,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+  }
+  return EAPDTW_OK;
 }
 
 int eapdtw_pairwise(eapdtw_ctx *ctx, const float *X, int64_t N, int64_t len, int64_t window,

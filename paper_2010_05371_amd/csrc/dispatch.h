@@ -56,6 +56,20 @@ hipError_t launch_wide_list(int rows, const WideArgs &a, int grid, hipStream_t s
 // nearest-neighbour words (pairwise geometry of WideArgs).
 hipError_t launch_nn1_seed(const WideArgs &a, int grid, hipStream_t st);
 
+// ERP of a batch of pairs (erp.hip): windows 0..kErpMaxR (r <= len - 1).
+constexpr int kErpMaxR = 64;
+struct ErpArgs {
+  const float *Xt, *Yt;          // [len][ld] transposed series (pair p at column p)
+  int64_t ld;                    // row stride of Xt, Yt: at least npairs rounded up to 64
+  int64_t npairs;
+  int len;
+  float g;                       // gap value
+  const float *ub;               // [npairs] bound per pair, or nullptr (no bound)
+  float *out;                    // [npairs]
+  unsigned long long *counters;  // kCntWords (nullable)
+};
+hipError_t launch_erp_pairs(int r, const ErpArgs &a, hipStream_t st);
+
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
 hipError_t launch_check_finite(const float *x, int64_t n, unsigned long long *counters,

@@ -1,0 +1,101 @@
+"""GPU parity of ERP over a batch of pairs (the edit distance with real
+penalty, an elastic distance of the kind the paper's closing outlook names)
+against the FP64 oracle's full-matrix recurrence.
+
+Tolerance: a result is a float32 sum of at most 2 len + 1 non-negative terms
+(a path has at most 2 len moves, plus the border sums), each the rounded
+difference of two float32 values; recursive summation of n non-negative
+terms errs by at most (n - 1) u of the sum and each term by u of itself
+(u = 2^-24), so |gpu - exact| <= (2 len + 2) u exact.  The test allows twice
+that plus a tiny absolute slack."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2010_05371_amd as eap
+
+pytestmark = pytest.mark.gpu
+
+
+def _tol(L):
+    return 2 * (2 * L + 2) * 2.0 ** -24
+
+
+def _series(npairs, L, seed):
+    g = gen.rng(7200, seed)
+    X = np.stack([gen.random_walk(L, g) for _ in range(npairs)]) if L else np.zeros((npairs, 0))
+    Y = np.stack([gen.warped_copy(x, g) for x in X]) if L > 1 else g.standard_normal((npairs, L))
+    Y[::3] = g.standard_normal(Y[::3].shape) * 3.0  # unrelated pairs mixed in
+    return gen.as_f32(X), gen.as_f32(Y)
+
+
+def _check(got, want, L):
+    got = np.asarray(got, dtype=np.float64)
+    fin = np.isfinite(want)
+    assert np.array_equal(np.isfinite(got), fin)
+    err = np.abs(got[fin] - want[fin])
+    assert np.all(err <= _tol(L) * want[fin] + 1e-6), float(np.max(err / np.maximum(want[fin], 1e-30)))
+
+
+# (npairs, len, window, g): window 0, narrow and wide windows, window = len - 1,
+# a window clamped to len - 1, ragged pair counts and row-group tails
+CASES = [(200, 64, 0, 0.0), (130, 100, 5, 0.3), (97, 256, 26, 0.0), (70, 37, 13, -0.5),
+         (64, 130, 64, 0.1), (65, 65, 64, 0.0), (10, 5, 10, 0.0), (3, 1, 0, 0.2),
+         (129, 200, 40, 1.5), (33, 90, 57, -0.2)]
+
+
+@pytest.mark.parametrize("npairs,L,w,gap", CASES)
+def test_erp_pairs_vs_oracle(npairs, L, w, gap):
+    X, Y = _series(npairs, L, npairs * 1000 + L + w)
+    out, st = eap.erp_pairs(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), w, gap, stats=True)
+    want = oracle.erp_pairs(gen.as_oracle(X), gen.as_oracle(Y), w, gap)
+    _check(out.cpu().numpy(), want, L)
+    r = min(w, L - 1)
+    band = sum(min(L, i + r) - max(1, i - r) + 1 for i in range(1, L + 1))
+    assert st["problems"] == npairs and st["abandoned"] == 0
+    assert st["cells_evaluated"] == band * npairs
+
+
+@pytest.mark.parametrize("npairs,L,w,gap", [(150, 120, 12, 0.0), (64, 256, 52, 0.4), (70, 33, 64, -1.0)])
+def test_erp_pairs_bound_contract(npairs, L, w, gap):
+    """The distance if <= ub[p], else +inf (Section 2.2's contract)."""
+    X, Y = _series(npairs, L, 31 + L)
+    x, y = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    full = eap.erp_pairs(x, y, w, gap).cpu().numpy()
+    ub = full.copy()
+    ub[::2] = np.nextafter(full[::2], np.float32(0))  # just below: abandoned
+    ub[1::4] = full[1::4]                              # equal: kept
+    ub[3::4] = full[3::4] * 1.5                        # above: kept
+    out, st = eap.erp_pairs(x, y, w, gap, ub=torch.from_numpy(ub).cuda(), stats=True)
+    out = out.cpu().numpy()
+    assert np.isinf(out[::2]).all()
+    assert np.array_equal(out[1::2], full[1::2])        # kept results keep their bits
+    assert st["abandoned"] == (npairs + 1) // 2
+    want = oracle.erp_pairs(gen.as_oracle(X), gen.as_oracle(Y), w, gap)
+    _check(full, want, L)
+
+
+def test_erp_pairs_window_zero_and_identity():
+    """Window 0: the float32 running sum of |X - Y| in row order, bit for bit;
+    a pair of equal series: 0 under every window."""
+    X, Y = _series(77, 150, 5)
+    x, y = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    got = eap.erp_pairs(x, y, 0, 0.7).cpu().numpy()
+    want = np.add.accumulate(np.abs(X - Y).astype(np.float32), axis=1, dtype=np.float32)[:, -1]
+    assert np.array_equal(got, want)
+    for w in (0, 9, 64):
+        assert (eap.erp_pairs(x, x, w, 0.3).cpu().numpy() == 0).all()
+
+
+def test_erp_pairs_errors_and_empty():
+    x = torch.zeros(4, 100, device="cuda")
+    with pytest.raises(eap.EapdtwError):
+        eap.erp_pairs(x, x, 65)
+    with pytest.raises(ValueError):
+        eap.erp_pairs(x, torch.zeros(4, 99, device="cuda"), 3)
+    assert (eap.erp_pairs(x[:, :60], x[:, :60], 1000).cpu().numpy() == 0).all()  # clamped to 59
+    e = torch.zeros(5, 0, device="cuda")
+    assert (eap.erp_pairs(e, e, 3).cpu().numpy() == 0).all()
+    assert eap.erp_pairs(x[:0], x[:0], 3).numel() == 0
