@@ -451,6 +451,45 @@ def c1_section(eap, steps):
 C3_KERNEL = "wide_kernel<64, 1, false>"  # the tiled kernel: 64-row tiles, pairwise, whole window
 
 
+ERP_OPS_PER_CELL = 7  # |a-b|, |b-g| (subtractions), three additions, a 3-way minimum (2)
+
+
+def erp_section(eap, steps):
+    """ERP (edit distance with real penalty) of a batch of pairs: 262,144 pairs
+    of a z-normalised random walk of length 256 and a warped noisy copy (4,096
+    distinct pairs, repeated), gap value 0, no bound, windows 13 / 26 / 52;
+    one pair per lane, so the batch is sized to give every SIMD two waves."""
+    import numpy as np
+    import torch
+
+    import gen
+    g = gen.rng(7300)
+    L, base, reps = 256, 4096, 64
+    X = np.stack([gen.standardise(gen.random_walk(L, g)) for _ in range(base)])
+    Y = np.stack([gen.warped_copy(x, g) for x in X])
+    x = torch.from_numpy(gen.as_f32(X)).cuda().repeat(reps, 1).contiguous()
+    y = torch.from_numpy(gen.as_f32(Y)).cuda().repeat(reps, 1).contiguous()
+    P = base * reps
+    per = {}
+    for w in (13, 26, 52):
+        eap.erp_pairs(x, y, w, 0.0, stats=True)
+        ms = []
+        for _ in range(steps):
+            _, st = eap.erp_pairs(x, y, w, 0.0, stats=True)
+            ms.append(st["main_kernel_ms"])
+        m = sum(ms) / len(ms)
+        cells = st["cells_evaluated"]
+        achieved = ERP_OPS_PER_CELL * cells / (m / 1e3)
+        per[str(w)] = {"kernel_ms": round(m, 4), "pairs_per_s": P / (m / 1e3), "cells": cells,
+                       "cells_per_s": cells / (m / 1e3),
+                       "roofline": {"bound": "alu", "kernel": f"erp_pairs_kernel<{w}>",
+                                    "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                                    "traffic": None, "ops_per_cell": ERP_OPS_PER_CELL}}
+    return {"workload": "ERP of 262,144 pairs of length 256 (random walk vs warped copy), g = 0",
+            "pairs": P, "len": L, "steps": steps, "per_window": per}
+
+
 def c3_section(eap, steps):
     """All pairs (Section 2.3 pruning, bound = squared Euclidean distance per
     pair): 2,000 z-normalised random walks of length 512, full window; the
@@ -579,6 +618,8 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=50,
                     help="steps of the differentiation workload (4,096 pairs fwd and fwd+bwd; "
                          "0 = skip)")
+    ap.add_argument("--erp-steps", type=int, default=5,
+                    help="repetitions per window of the ERP pairs workload (0 = skip)")
     ap.add_argument("--c1-steps", type=int, default=10,
                     help="calls of the small search workload (0 = skip)")
     ap.add_argument("--c4-variants", type=int, default=1,
@@ -697,6 +738,8 @@ def main():
         line["c5_fwd_bwd"] = c5_section(eap, args.c5_steps, min(args.cpu_budget, 5.0))
     if args.c3_steps > 0:
         line["c3_pairwise"] = c3_section(eap, args.c3_steps)
+    if args.erp_steps > 0:
+        line["erp_pairs"] = erp_section(eap, args.erp_steps)
     if args.c4_steps > 0:
         line["c4_batched"] = c4_section(eap, args.c4_steps, args.c4_variants != 0)
     if args.cpu_budget > 0:

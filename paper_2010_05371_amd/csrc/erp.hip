@@ -98,8 +98,12 @@ __device__ __forceinline__ void erp_group(float (&v)[2 * R + 1], const float (&a
   }
 }
 
+// Windows 40..57 are held to two waves per SIMD (up to 16 bytes of scratch
+// per lane at 56..57); from 58 the spills would cost more than the second wave
+// brings, and the kernel runs one wave per SIMD.
 template <int R>
-__global__ __launch_bounds__(64) void erp_pairs_kernel(ErpArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R >= 40 && R <= 57) ? 2 : 1)))
+void erp_pairs_kernel(ErpArgs a) {
   constexpr int W = 2 * R + 1;
   const int lane = threadIdx.x;
   const int64_t p = (int64_t)blockIdx.x * kWave + lane;
