@@ -463,13 +463,9 @@ def erp_section(eap, steps):
     import torch
 
     import gen
-    g = gen.rng(7300)
-    L, base, reps = 256, 4096, 64
-    X = np.stack([gen.standardise(gen.random_walk(L, g)) for _ in range(base)])
-    Y = np.stack([gen.warped_copy(x, g) for x in X])
-    x = torch.from_numpy(gen.as_f32(X)).cuda().repeat(reps, 1).contiguous()
-    y = torch.from_numpy(gen.as_f32(Y)).cuda().repeat(reps, 1).contiguous()
-    P = base * reps
+    X, Y = gen.erp_pairs()
+    x, y = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    P, L = X.shape
     per = {}
     for w in (13, 26, 52):
         eap.erp_pairs(x, y, w, 0.0, stats=True)

@@ -100,6 +100,16 @@ def c2(n: int = 2_000_000, m: int = 256):
     return as_f32(query), as_f32(series), [window_from_ratio(f, m) for f in (0.0, 0.05, 0.10, 0.20)]
 
 
+def erp_pairs(base: int = 4096, reps: int = 64, L: int = 256):
+    """ERP pair batch: `base` pairs of a z-normalised random walk and a warped
+    noisy copy of it, the whole set repeated `reps` times (row p is pair
+    p mod base); float32 [base*reps, L] each."""
+    g = rng(7300)
+    X = np.stack([standardise(random_walk(L, g)) for _ in range(base)])
+    Y = np.stack([warped_copy(x, g) for x in X])
+    return np.tile(as_f32(X), (reps, 1)), np.tile(as_f32(Y), (reps, 1))
+
+
 def c3(N: int = 2000, L: int = 512):
     g = rng(3)
     X = np.stack([standardise(random_walk(L, g)) for _ in range(N)])

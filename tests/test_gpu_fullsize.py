@@ -66,6 +66,21 @@ def test_c2_full_knn_lb_vs_all_distances(c2, w, k):
         assert close(dd, a), (o, dd, a)
 
 
+@pytest.mark.parametrize("w", [13, 26, 52])
+def test_erp_full_batch_sampled(w):
+    """ERP of the 262,144-pair batch the benchmark times (length 256, g = 0):
+    512 sampled pairs against the oracle within the float32 summation bound
+    (2 len + 2) u, doubled; repeated pairs give the same bits."""
+    X, Y = gen.erp_pairs()
+    d = _cpu(eap.erp_pairs(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), w, 0.0))
+    assert d.size == X.shape[0] and np.isfinite(d).all()
+    idx = np.sort(gen.rng(7301).choice(d.size, 512, replace=False))
+    want = oracle.erp_pairs(gen.as_oracle(X[idx]), gen.as_oracle(Y[idx]), w, 0.0)
+    tol = 2 * (2 * X.shape[1] + 2) * 2.0 ** -24
+    assert np.all(np.abs(d[idx] - want) <= tol * want + 1e-6)
+    assert np.array_equal(d[:4096], d[-4096:])
+
+
 def test_c3_full_pairwise_sampled():
     """1,999,000 pairs of length 512, full window: 512 sampled pairs against
     the oracle; DTW <= squared Euclidean distance on the same sample."""
