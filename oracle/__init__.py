@@ -13,6 +13,8 @@ function is the plain definition from the paper (Herrmann & Webb, arXiv
 * ``erp``, ``erp_pairs`` -- the edit distance with real penalty (Chen & Ng,
   VLDB 2004), an elastic distance with DTW's three moves and gap costs, of
   the kind the paper's closing outlook names; same matrix and window;
+  ``erp_nn_search`` -- the nearest-neighbour search under ERP (every offset,
+  z-normalised windows, first minimum);
 * ``eap``         -- Section 2.2's threshold contract: DTW if <= ub else +inf;
 * ``znorm``       -- z-normalisation (population sigma), the UCR-Suite step the
   paper's search inherits (Section 5);
@@ -97,6 +99,8 @@ def _load():
     lib.oracle_dtw.restype = ctypes.c_double
     lib.oracle_erp.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double]
     lib.oracle_erp.restype = ctypes.c_double
+    lib.oracle_erp_nn_search.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double, ip, dp]
+    lib.oracle_erp_nn_search.restype = ctypes.c_int
     lib.oracle_dtw_matrix.argtypes = [dp, i64, dp, i64, i64, dp]
     lib.oracle_dtw_matrix.restype = ctypes.c_int
     lib.oracle_eap.argtypes = [dp, i64, dp, i64, i64, ctypes.c_double]
@@ -197,6 +201,19 @@ def erp_pairs(X, Y, window: int, g: float = 0.0, ub=None) -> np.ndarray:
     if ub is not None:
         out = np.where(out <= np.asarray(ub, dtype=np.float64), out, np.inf)
     return out
+
+
+def erp_nn_search(query, series, window: int, g: float = 0.0):
+    """(offset, distance) of the first smallest ERP between the z-normalised
+    query and the z-normalised window at each offset (rows = the window)."""
+    q, x = _f64(query), _f64(series)
+    k = ctypes.c_int64()
+    d = ctypes.c_double()
+    rc = _load().oracle_erp_nn_search(_ptr(q), q.size, _ptr(x), x.size, int(window), float(g),
+                                      ctypes.byref(k), ctypes.byref(d))
+    if rc != 0:
+        raise MemoryError("oracle_erp_nn_search")
+    return k.value, d.value
 
 
 def dtw_matrix(S, T, window: int | None = None) -> np.ndarray:

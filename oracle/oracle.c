@@ -199,6 +199,36 @@ double oracle_erp(const double *S, int64_t lS, const double *T, int64_t lT, int6
   return v;
 }
 
+/* Nearest neighbour of the query under ERP (the search of Section 2.2 with
+ * the outlook's other distance): every offset k of x, its window z-normalised
+ * (oracle_znorm) as the rows, the z-normalised query as the columns; the first
+ * offset of the smallest distance.  Returns 0, or -1 when out of memory. */
+int oracle_erp_nn_search(const double *q, int64_t m, const double *x, int64_t n, int64_t r,
+                         double g, int64_t *out_k, double *out_d) {
+  double *zq = malloc((size_t)m * sizeof(double)), *zc = malloc((size_t)m * sizeof(double));
+  if (!zq || !zc) {
+    free(zq);
+    free(zc);
+    return -1;
+  }
+  oracle_znorm(q, m, zq);
+  int64_t best_k = -1;
+  double best = ORACLE_INF;
+  for (int64_t k = 0; k + m <= n; ++k) {
+    oracle_znorm(x + k, m, zc);
+    const double d = oracle_erp(zc, m, zq, m, r, g);
+    if (d < best) {
+      best = d;
+      best_k = k;
+    }
+  }
+  free(zq);
+  free(zc);
+  *out_k = best_k;
+  *out_d = best;
+  return 0;
+}
+
 double oracle_dtw(const double *S, int64_t lS, const double *T, int64_t lT, int64_t r) {
   if (lS == 0 && lT == 0) return 0.0;          /* Eq. 2 */
   if (lS == 0 || lT == 0) return ORACLE_INF;   /* Eq. 3-4 */

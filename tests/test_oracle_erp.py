@@ -102,3 +102,30 @@ def test_erp_pairs_threshold_contract():
     ub[::2] = full[::2] * 0.999
     out = oracle.erp_pairs(X, Y, 3, 0.1, ub)
     assert np.isinf(out[::2]).all() and (out[1::2] == full[1::2]).all()
+
+
+def _znorm_np(w):
+    sd = w.std()
+    return (w - w.mean()) / sd if sd > 0 else np.zeros_like(w)
+
+
+def test_erp_search_planted_copy_and_window_zero():
+    g0 = np.random.default_rng(7150)
+    q = g0.normal(size=24).cumsum()
+    x = g0.normal(size=600).cumsum()
+    x[311:335] = 2.5 * q - 4.0  # an affine copy: the same z-normalised window, ERP 0
+    k, d = oracle.erp_nn_search(q, x, 3, 0.2)
+    assert k == 311 and d == pytest.approx(0.0, abs=1e-9)
+    # window 0: the L1 distance between z-normalised windows, written out with numpy
+    x2 = g0.normal(size=400).cumsum()
+    zq = _znorm_np(q)
+    l1 = [np.abs(_znorm_np(x2[i:i + 24]) - zq).sum() for i in range(400 - 24 + 1)]
+    k0, d0 = oracle.erp_nn_search(q, x2, 0, 0.7)
+    assert k0 == int(np.argmin(l1)) and d0 == pytest.approx(min(l1), rel=1e-12)
+
+
+def test_erp_search_ties_take_the_smallest_offset():
+    pattern = np.random.default_rng(7160).normal(size=30)
+    x = np.tile(pattern, 8)
+    k, d = oracle.erp_nn_search(pattern[5:25], x, 4, 0.0)
+    assert k == 5 and d == 0.0
