@@ -225,6 +225,21 @@ int eapdtw_dtw_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t np
 int eapdtw_erp_pairs(eapdtw_ctx *ctx, const float *X, const float *Y, int64_t npairs, int64_t len,
                      int64_t window, double g, const float *ub, float *out, eapdtw_stats *stats);
 
+/* Nearest-neighbour search under ERP (Section 2.2's search with the outlook's
+ * other distance; the matrix and window of eapdtw_erp_pairs): the offset k of
+ * series with the smallest ERP between z(series[k..k+m)) (rows) and z(query)
+ * (columns), under eapdtw_nn_search's normalisation and tie rule (smallest
+ * offset among equal float32 distances).  Every candidate is early-abandoned
+ * against the shared best-so-far.
+ *   query [m], series [n] : DEVICE float32; window clamped to m - 1, at most
+ *                           64 after the clamp (EINVAL beyond).
+ *   g                     : gap value in normalised units (finite).
+ *   out_offset, out_dist  : HOST.
+ * Errors as eapdtw_nn_search (non-finite input: ENONFINITE).  Synchronous. */
+int eapdtw_nn_search_erp(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                         int64_t n, int64_t window, double g, int64_t *out_offset, double *out_dist,
+                         eapdtw_stats *stats);
+
 /* ---------------------------------------------------------------------------
  * All pairwise distances of N series (Section 2.3: pruning with the squared
  * Euclidean distance as the only bound, e.g. for 1-NN classification).

@@ -43,7 +43,8 @@ __all__ = ["dtw", "dtw_pairs", "pairwise", "nn_search", "nn_search_batch", "nn_d
            "tune_bucket", "tune_get", "tune_save", "tune_load", "nn_search_lb", "nn_dists_lb",
            "nn_lower_bounds", "LbStats", "knn_search", "knn_search_lb", "nn1", "nn_search_w", "nn_dists_w",
            "nn1_ref", "dtw_path", "dtw_pairs_batch", "pack_pairs", "DTWBatchFunction",
-           "dtw_batch_path", "dba_step", "unpack_ranges", "erp_pairs"]
+           "dtw_batch_path", "dba_step", "unpack_ranges", "erp_pairs",
+           "nn_search_erp"]
 
 
 def window_from_ratio(ratio: float, m: int) -> int:
@@ -331,6 +332,22 @@ def erp_pairs(X, Y, window: int, g: float = 0.0, ub=None, stats: bool = False):
                                         int(window), float(g), _ptr(u) if u is not None else None,
                                         _ptr(out), ctypes.byref(st) if stats else None))
     return (out, st.as_dict()) if stats else out
+
+
+def nn_search_erp(query, series, window: int, g: float = 0.0, stats: bool = False):
+    """Nearest-neighbour search under ERP (gap value g in normalised units,
+    window at most 64 after clamping to m - 1): (offset, distance)."""
+    q, x = _dev(query), _dev(series)
+    ctx = context(x.device.index)
+    ctx.bind_stream()
+    off = ctypes.c_int64()
+    dist = ctypes.c_double()
+    st = Stats()
+    ctx.check(ctx._lib.eapdtw_nn_search_erp(ctx.handle, _ptr(q), q.numel(), _ptr(x), x.numel(),
+                                            int(window), float(g), ctypes.byref(off),
+                                            ctypes.byref(dist), ctypes.byref(st) if stats else None))
+    res = (off.value, dist.value)
+    return (res, st.as_dict()) if stats else res
 
 
 def knn_search_lb(query, series, window: int, k: int, stats: bool = False):

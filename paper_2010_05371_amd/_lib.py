@@ -129,6 +129,8 @@ def load():
         "eapdtw_knn_search": ([vp, vp, i64, vp, i64, i64, i64, ctypes.POINTER(i64),
                                ctypes.POINTER(f64), sp], i32),
         "eapdtw_erp_pairs": ([vp, vp, vp, i64, i64, i64, f64, vp, vp, sp], i32),
+        "eapdtw_nn_search_erp": ([vp, vp, i64, vp, i64, i64, f64, ctypes.POINTER(i64),
+                                  ctypes.POINTER(f64), sp], i32),
         "eapdtw_knn_search_lb": ([vp, vp, i64, vp, i64, i64, i64, ctypes.POINTER(i64),
                                   ctypes.POINTER(f64), sp, lp], i32),
         "eapdtw_nn1": ([vp, vp, i64, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(f64), sp], i32),

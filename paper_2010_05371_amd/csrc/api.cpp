@@ -1665,6 +1665,66 @@ int eapdtw_knn_search_lb(eapdtw_ctx *ctx, const float *query, int64_t m, const f
                          true, lbstats);
 }
 
+int eapdtw_nn_search_erp(eapdtw_ctx *ctx, const float *query, int64_t m, const float *series,
+                         int64_t n, int64_t window, double g, int64_t *out_offset, double *out_dist,
+                         eapdtw_stats *stats) {
+  CHECK_CTX();
+  if (!out_offset || !out_dist) return fail(ctx, EAPDTW_EINVAL, "NULL output");
+  if (!std::isfinite(g) || std::fabs(g) > FLT_MAX) return fail(ctx, EAPDTW_EINVAL, "g must be a finite float32");
+  int rc = search_validate(ctx, query, m, series, n, window);
+  if (rc) return rc;
+  const int64_t r = window < m - 1 ? window : m - 1;
+  if (r > kErpMaxR) return fail(ctx, EAPDTW_EINVAL, "ERP takes windows up to 64 (after clamping to m - 1)");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  const int64_t K = n - m + 1;
+  Plan pl;
+  const size_t o_cnt = pl.add(kCntBytes);
+  const size_t o_bsf = pl.add(sizeof(unsigned long long) * 2);
+  const size_t o_q = pl.add(sizeof(float) * (m + 2 * kColPad));
+  rc = ensure_scratch(ctx, pl.off);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  unsigned long long *cnt = at<unsigned long long>(ctx, o_cnt);
+  unsigned long long *bsf = at<unsigned long long>(ctx, o_bsf);
+  float *qpad = at<float>(ctx, o_q);
+  if (stats) HIPCHK(hipEventRecord(ctx->ev0, st));
+  if (++ctx->epoch == 0) ++ctx->epoch;
+  HIPCHK(launch_search_prep(query, (int)m, qpad, series, n, cnt, bsf, 2,
+                            reinterpret_cast<unsigned *>(cnt + kCntWords), ctx->epoch, st));
+  if (stats) HIPCHK(hipEventRecord(ctx->ev2, st));
+  ErpSearchArgs e{};
+  e.x = series;
+  e.n = n;
+  e.K = K;
+  e.qz = qpad + kColPad;
+  e.m = (int)m;
+  e.g = (float)g;
+  e.bsf = bsf;
+  e.check_interval = (int)(ctx->check_interval > 0 ? ctx->check_interval : 4);
+  e.counters = cnt;
+  HIPCHK(launch_erp_search((int)r, e, st));
+  log_launch(ctx, "erp search m=%lld r=%lld: erp_search_kernel<%lld> grid=%lld", (long long)m,
+             (long long)r, (long long)r, (long long)((K + kWave - 1) / kWave));
+  if (stats) {
+    HIPCHK(hipEventRecord(ctx->ev3, st));
+    HIPCHK(hipEventRecord(ctx->ev1, st));
+  }
+  // counters, the flag word and the best-so-far words are contiguous
+  rc = readback(ctx, o_cnt, o_bsf + 2 * sizeof(unsigned long long) - o_cnt);
+  if (rc) return rc;
+  const unsigned long long *hc = reinterpret_cast<unsigned long long *>(ctx->pinned);
+  if (*reinterpret_cast<const unsigned *>(hc + kCntWords) == ctx->epoch)
+    return fail(ctx, EAPDTW_ENONFINITE, "non-finite value in query or series");
+  const unsigned long long best = *reinterpret_cast<unsigned long long *>(ctx->pinned + (o_bsf - o_cnt));
+  *out_offset = best_offset(best) == 0xffffffffu ? -1 : (int64_t)best_offset(best);
+  *out_dist = (double)best_dist(best);
+  if (stats)
+    fill_stats(stats, hc, (uint64_t)(band_cells_total(m, m, r) * K), (uint64_t)K,
+               elapsed(ctx->ev0, ctx->ev1), elapsed(ctx->ev2, ctx->ev3));
+  return EAPDTW_OK;
+}
+
 static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
   const unsigned char *b = static_cast<const unsigned char *>(p);
   for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;

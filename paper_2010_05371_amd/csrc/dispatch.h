@@ -69,6 +69,18 @@ struct ErpArgs {
   unsigned long long *counters;  // kCntWords (nullable)
 };
 hipError_t launch_erp_pairs(int r, const ErpArgs &a, hipStream_t st);
+// Nearest-neighbour search under ERP (one candidate offset per lane).
+struct ErpSearchArgs {
+  const float *x;                // series [n]
+  int64_t n, K;                  // K = n - m + 1 candidate offsets
+  const float *qz;               // z-normalised query [m]
+  int m;
+  float g;                       // gap value
+  unsigned long long *bsf;       // packed (distance, offset) best-so-far, +inf on entry
+  int check_interval;            // row groups between best-so-far reads
+  unsigned long long *counters;  // kCntWords (nullable)
+};
+hipError_t launch_erp_search(int r, const ErpSearchArgs &a, hipStream_t st);
 
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);

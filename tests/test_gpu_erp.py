@@ -99,3 +99,54 @@ def test_erp_pairs_errors_and_empty():
     e = torch.zeros(5, 0, device="cuda")
     assert (eap.erp_pairs(e, e, 3).cpu().numpy() == 0).all()
     assert eap.erp_pairs(x[:0], x[:0], 3).numel() == 0
+
+
+# ---------------------------------------------------------------- search
+def _search_check(k, d, q32, x32, w, gap):
+    qo, xo = gen.as_oracle(q32), gen.as_oracle(x32)
+    m = q32.size
+    ko, do = oracle.erp_nn_search(qo, xo, w, gap)
+    tol = _tol(m)
+    assert abs(d - do) <= tol * do + 1e-6, (k, d, ko, do)
+    if k != ko:  # a near-tie: the reported offset's own distance ties the minimum
+        at = oracle.erp(oracle.znorm(xo[k:k + m]), oracle.znorm(qo), w, gap)
+        assert abs(at - do) <= tol * do + 1e-6, (k, ko, at, do)
+
+
+# (m, window, n, g): window 0, narrow and wide windows, window = m - 1, a
+# window clamped to m - 1, ragged candidate counts and row-group tails
+SEARCH = [(64, 0, 3000, 0.0), (128, 13, 20_000, 0.0), (96, 30, 8000, 0.3), (37, 6, 5000, -0.2),
+          (150, 64, 6000, 0.0), (65, 64, 4000, 0.1), (30, 100, 2000, 0.5), (200, 52, 9000, 1.0)]
+
+
+@pytest.mark.parametrize("m,w,n,gap", SEARCH)
+def test_erp_search_vs_oracle(m, w, n, gap):
+    g = gen.rng(7400, m * 100 + w)
+    q32, x32 = gen.as_f32(gen.random_walk(m, g)), gen.as_f32(gen.random_walk(n, g))
+    (k, d), st = eap.nn_search_erp(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), w,
+                                   gap, stats=True)
+    _search_check(k, d, q32, x32, min(w, m - 1), gap)
+    assert st["problems"] == n - m + 1
+
+
+def test_erp_search_planted_copy_and_sinusoid():
+    g = gen.rng(7401)
+    q = gen.random_walk(80, g)
+    x = gen.plant(gen.random_walk(30_000, g), q, 17_123, a=2.0, b=-3.0)
+    q32, x32 = gen.as_f32(q), gen.as_f32(x)
+    k, d = eap.nn_search_erp(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), 8, 0.0)
+    assert k == 17_123 and d <= 1e-3
+    q32, x32, _ = gen.c2(n=20_000, m=128)
+    k, d = eap.nn_search_erp(torch.from_numpy(q32).cuda(), torch.from_numpy(x32).cuda(), 13, 0.0)
+    _search_check(k, d, q32, x32, 13, 0.0)
+
+
+def test_erp_search_errors():
+    q = torch.zeros(100, device="cuda")
+    x = torch.arange(1000, dtype=torch.float32, device="cuda")
+    with pytest.raises(eap.EapdtwError):
+        eap.nn_search_erp(q, x, 65)
+    xn = x.clone()
+    xn[500] = float("nan")
+    with pytest.raises(eap.EapdtwError):
+        eap.nn_search_erp(q[:50], xn, 5)
